@@ -1,0 +1,458 @@
+"""Plain FP64 CPU oracle of the IMEX-DG compressible Euler step.
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the CPU-baseline leg of
+the benchmark; the GPU library never imports or links it, and it shares no code with it.
+
+The spatial operators (explicit residual, weak gradient B, weak divergence C, pressure penalty P,
+geometry, mesh) are in ``dg_oracle.c`` as dense loops.  This module composes them, following the
+paper (Orlando, Benacchio, Bonaventura, arXiv 2408.08129):
+
+* Section 2, Eq. (1): Euler equations in SI units, g = 9.81, R = 287, gamma = 1.4, rhoE = rho e +
+  rho k with k = |u|^2 / 2;
+* Section 2: continuity explicit, energy coupled implicitly to momentum; a second-order IMEX-RK
+  method (ARK2 of Giraldo, Kelly, Constantinescu 2013: explicit stage 1, two implicit stages with
+  diagonal 1 - 1/sqrt(2));
+* Section 3.2: each implicit stage runs a fixed-point loop for the pressure whose linear system is
+  non-symmetric and solved with GMRES, applying the operators matrix-free;
+* Section 3.1, Eq. (4)-(5): the stratified initial state (with the factor g^2 / N^2 that makes it
+  hydrostatic), or an isothermal atmosphere.
+
+The pressure unknown of the implicit stage is the perturbation p' = p - pbar from the analytic
+hydrostatic background evaluated at every node, so that an atmosphere at rest has exactly zero
+tendencies.  The implicit stage solves, for the increment delta of p' at fixed-point iterate l,
+
+    A(h^l) delta = b^l - A(h^l) p'^l,
+    A(h) = M / (gamma - 1) + dt a P(h) - (dt a)^2 C diag(h) M^{-1} B,
+    b^l  = M (e~ - rho k^l - pbar / (gamma - 1)) - dt a C (h^l m'),
+
+where h = gamma p / ((gamma - 1) rho) is the specific enthalpy, m' the momentum predictor including
+the implicit buoyancy -dt a (rho - rhobar) g k, and the momentum follows as
+m = m' - dt a M^{-1} B p'.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+G = 9.81
+RGAS = 287.0
+GAMMA = 1.4
+
+FLAT, AGNESI, BELL, GAUSS_HILL, GAUSS_RIDGE = range(5)
+ISOTHERMAL, STRATIFIED = range(2)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dg_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+
+def build_oracle(force: bool = False) -> str:
+    """Compile dg_oracle.c with gcc (FP64, no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared",
+                               "-fopenmp", "-ffp-contract=off", "-fno-fast-math", _SRC, "-o", tmp,
+                               "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Case(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("degree", ctypes.c_int32),
+        ("nbase", ctypes.c_int32 * 3), ("periodic", ctypes.c_int32 * 2),
+        ("n_rules", ctypes.c_int32), ("oro_kind", ctypes.c_int32), ("atm_kind", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("length", ctypes.c_double * 3), ("rules", (ctypes.c_double * 5) * 8),
+        ("oro", ctypes.c_double * 4), ("atm", ctypes.c_double * 3),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = ctypes.CDLL(build_oracle())
+        P = ctypes.c_void_p
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.oc_mesh_build.argtypes = [ctypes.POINTER(_Case), ctypes.POINTER(P)]
+        L.oc_mesh_build.restype = ctypes.c_int
+        L.oc_mesh_free.argtypes = [P]
+        for name in ("oc_ncell", "oc_nloc", "oc_nhang", "oc_lmax"):
+            getattr(L, name).argtypes = [P]
+            getattr(L, name).restype = ctypes.c_int
+        L.oc_cell_table.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+        L.oc_node_geometry.argtypes = [P, dp, dp, dp, dp]
+        L.oc_background_nodes.argtypes = [P, dp, dp]
+        L.oc_explicit_residual.argtypes = [P, dp, dp]
+        L.oc_grad.argtypes = [P, dp, dp]
+        L.oc_div.argtypes = [P, dp, dp]
+        L.oc_penalty.argtypes = [P, dp, dp, dp]
+        L.oc_cell_sizes.argtypes = [P, dp]
+        L.oc_bottom_normals.argtypes = [P, dp]
+        L.oc_bottom_normals.restype = ctypes.c_int
+        L.oc_gauss.argtypes = [ctypes.c_int, dp, dp]
+        L.oc_lagrange_eval.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp, dp]
+        L.oc_background.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def gauss(n: int):
+    x = np.zeros(n)
+    w = np.zeros(n)
+    lib().oc_gauss(n, _p(x), _p(w))
+    return x, w
+
+
+def lagrange_eval(nodes: np.ndarray, x: float):
+    n = len(nodes)
+    v = np.zeros(n)
+    d = np.zeros(n)
+    lib().oc_lagrange_eval(n, _p(np.ascontiguousarray(nodes, dtype=np.float64)), float(x), _p(v), _p(d))
+    return v, d
+
+
+def background(kind: int, atm, z: float):
+    a = np.array(list(atm) + [0.0] * (3 - len(atm)), dtype=np.float64)
+    p = ctypes.c_double()
+    r = ctypes.c_double()
+    lib().oc_background(kind, _p(a), float(z), ctypes.byref(p), ctypes.byref(r))
+    return p.value, r.value
+
+
+@dataclass
+class Case:
+    """Problem description: logical box, base grid, refinement rules, orography, atmosphere."""
+    dim: int
+    degree: int
+    nbase: tuple
+    length: tuple
+    periodic: tuple = (1, 1)
+    rules: list = field(default_factory=list)  # (zeta_max, x_c, hw_x, y_c, hw_y)
+    oro_kind: int = FLAT
+    oro: tuple = (0.0, 1.0, 0.0, 0.0)
+    atm_kind: int = ISOTHERMAL
+    atm: tuple = (1.0e5, 250.0, 0.0)
+
+    def to_struct(self) -> _Case:
+        c = _Case()
+        c.dim = self.dim
+        c.degree = self.degree
+        for i in range(3):
+            c.nbase[i] = int(self.nbase[i])
+            c.length[i] = float(self.length[i])
+        c.periodic[0] = int(self.periodic[0])
+        c.periodic[1] = int(self.periodic[1])
+        c.n_rules = len(self.rules)
+        for i, r in enumerate(self.rules):
+            for j in range(5):
+                c.rules[i][j] = float(r[j])
+        c.oro_kind = self.oro_kind
+        for i in range(4):
+            c.oro[i] = float(self.oro[i])
+        c.atm_kind = self.atm_kind
+        atm = list(self.atm) + [0.0] * (3 - len(self.atm))
+        for i in range(3):
+            c.atm[i] = float(atm[i])
+        return c
+
+
+class MeshError(RuntimeError):
+    pass
+
+
+class Oracle:
+    """Mesh + operators + IMEX-RK2 step of the oracle for one case."""
+
+    # ARK2 (Giraldo, Kelly, Constantinescu 2013) in Butcher form.
+    ARK_G = 1.0 - 1.0 / math.sqrt(2.0)
+    ARK_D = 1.0 / (2.0 * math.sqrt(2.0))
+    ARK_A = (3.0 + 2.0 * math.sqrt(2.0)) / 6.0
+
+    def __init__(self, case: Case, beta: float = 1.0):
+        self.case = case
+        self.beta = beta
+        self._cs = case.to_struct()
+        h = ctypes.c_void_p()
+        rc = lib().oc_mesh_build(ctypes.byref(self._cs), ctypes.byref(h))
+        if rc != 0:
+            raise MeshError("oracle mesh build failed (%d)" % rc)
+        self._m = h
+        L = lib()
+        self.d = case.dim
+        self.r = case.degree
+        self.nf = self.d + 2
+        self.ncell = L.oc_ncell(h)
+        self.nloc = L.oc_nloc(h)
+        self.nhang = L.oc_nhang(h)
+        self.lmax = L.oc_lmax(h)
+        self.N = self.ncell * self.nloc
+        cells = np.zeros((self.ncell, 4), dtype=np.int32)
+        L.oc_cell_table(h, cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        self.cells = cells
+        self.x = np.zeros(self.N)
+        self.y = np.zeros(self.N)
+        self.z = np.zeros(self.N)
+        self.wJ = np.zeros(self.N)
+        L.oc_node_geometry(h, _p(self.x), _p(self.y), _p(self.z), _p(self.wJ))
+        self.pbar = np.zeros(self.N)
+        self.rbar = np.zeros(self.N)
+        L.oc_background_nodes(h, _p(self.pbar), _p(self.rbar))
+        sz = np.zeros((self.ncell, 3))
+        L.oc_cell_sizes(h, _p(sz))
+        self.cell_sizes = sz
+        g, a, dd = self.ARK_G, self.ARK_A, self.ARK_D
+        self.A = np.array([[0, 0, 0], [2 * g, 0, 0], [1 - a, a, 0]], dtype=np.float64)
+        self.At = np.array([[0, 0, 0], [g, g, 0], [dd, dd, g]], dtype=np.float64)
+        self.b = np.array([dd, dd, g])
+        self.bt = np.array([dd, dd, g])
+
+    def __del__(self):
+        try:
+            lib().oc_mesh_free(self._m)
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------------------------- operators
+    def explicit_residual(self, U: np.ndarray) -> np.ndarray:
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        R = np.zeros_like(U)
+        lib().oc_explicit_residual(self._m, _p(U), _p(R))
+        return R
+
+    def grad(self, p: np.ndarray) -> np.ndarray:
+        """M^{-1} B p, shape (d, N)."""
+        p = np.ascontiguousarray(p, dtype=np.float64)
+        q = np.zeros((self.d, self.N))
+        lib().oc_grad(self._m, _p(p), _p(q))
+        return q
+
+    def div(self, w: np.ndarray) -> np.ndarray:
+        """C w in weak form, w of shape (d, N)."""
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        out = np.zeros(self.N)
+        lib().oc_div(self._m, _p(w), _p(out))
+        return out
+
+    def penalty(self, lam_cell: np.ndarray, p: np.ndarray) -> np.ndarray:
+        """Jump penalty sum over faces of lam_f |N| (p_own - p_other) psi, weak form."""
+        lam_cell = np.ascontiguousarray(lam_cell, dtype=np.float64)
+        p = np.ascontiguousarray(p, dtype=np.float64)
+        out = np.zeros(self.N)
+        lib().oc_penalty(self._m, _p(lam_cell), _p(p), _p(out))
+        return out
+
+    def bottom_normals(self) -> np.ndarray:
+        out = np.zeros((self.ncell * self.nloc, 6))
+        n = lib().oc_bottom_normals(self._m, _p(out))
+        return out[:n]
+
+    # ------------------------------------------------------------------- pointwise thermodynamics
+    def pressure(self, U: np.ndarray) -> np.ndarray:
+        rho = U[0]
+        m2 = np.sum(U[1:1 + self.d] ** 2, axis=0)
+        return (GAMMA - 1.0) * (U[1 + self.d] - 0.5 * m2 / rho)
+
+    def enthalpy(self, p: np.ndarray, rho: np.ndarray) -> np.ndarray:
+        return GAMMA * p / ((GAMMA - 1.0) * rho)
+
+    def cell_sound_speed(self, h: np.ndarray) -> np.ndarray:
+        """Per-cell maximum of c = sqrt((gamma - 1) h)."""
+        c = np.sqrt((GAMMA - 1.0) * h)
+        return c.reshape(self.ncell, self.nloc).max(axis=1)
+
+    # ------------------------------------------------------------------------- implicit operator
+    def helmholtz(self, dta: float, h: np.ndarray, lam: np.ndarray, p: np.ndarray) -> np.ndarray:
+        """A(h) p = M p / (gamma-1) + dt a beta/(2(gamma-1)) P p - (dt a)^2 C (h M^{-1} B p)."""
+        q = self.grad(p)
+        out = self.wJ * p / (GAMMA - 1.0)
+        if self.beta != 0.0:
+            out = out + dta * self.beta / (2.0 * (GAMMA - 1.0)) * self.penalty(lam, p)
+        out = out - dta * dta * self.div(h[None, :] * q)
+        return out
+
+    def jacobi_diag(self, dta: float, h: np.ndarray) -> np.ndarray:
+        """Diagonal scaling used as preconditioner: w J [1/(gamma-1) + (dt a)^2 h sum_k ((r+1)/D_k)^2]
+        with D_k the logical cell size along axis k."""
+        r1 = self.r + 1
+        s = np.sum((r1 / self.cell_sizes[:, :self.d]) ** 2, axis=1)
+        s = np.repeat(s, self.nloc)
+        return self.wJ * (1.0 / (GAMMA - 1.0) + dta * dta * h * s)
+
+    # ------------------------------------------------------------------------------------ GMRES
+    @staticmethod
+    def gmres(apply, b: np.ndarray, dinv: np.ndarray, rtol: float, atol: float, restart: int,
+              maxit: int):
+        """Right-preconditioned restarted GMRES(m) with modified Gram-Schmidt and Givens rotations,
+        zero initial guess; stops when the residual 2-norm is <= max(rtol |b|, atol).
+        Returns (x, iterations, final residual norm, converged)."""
+        n = b.shape[0]
+        x = np.zeros(n)
+        bnorm = float(np.linalg.norm(b))
+        tol = max(rtol * bnorm, atol)
+        if bnorm <= tol or bnorm == 0.0:
+            return x, 0, bnorm, True
+        its = 0
+        r = b.copy()
+        beta = bnorm
+        while True:
+            V = np.zeros((restart + 1, n))
+            Hs = np.zeros((restart + 1, restart))
+            cs = np.zeros(restart)
+            sn = np.zeros(restart)
+            g = np.zeros(restart + 1)
+            V[0] = r / beta
+            g[0] = beta
+            j_done = 0
+            res = beta
+            for j in range(restart):
+                w = apply(dinv * V[j])
+                for i in range(j + 1):
+                    Hs[i, j] = float(np.dot(V[i], w))
+                    w = w - Hs[i, j] * V[i]
+                Hs[j + 1, j] = float(np.linalg.norm(w))
+                if Hs[j + 1, j] != 0.0:
+                    V[j + 1] = w / Hs[j + 1, j]
+                for i in range(j):
+                    t = cs[i] * Hs[i, j] + sn[i] * Hs[i + 1, j]
+                    Hs[i + 1, j] = -sn[i] * Hs[i, j] + cs[i] * Hs[i + 1, j]
+                    Hs[i, j] = t
+                den = math.hypot(Hs[j, j], Hs[j + 1, j])
+                cs[j] = Hs[j, j] / den
+                sn[j] = Hs[j + 1, j] / den
+                Hs[j, j] = den
+                Hs[j + 1, j] = 0.0
+                g[j + 1] = -sn[j] * g[j]
+                g[j] = cs[j] * g[j]
+                its += 1
+                j_done = j + 1
+                res = abs(g[j + 1])
+                if res <= tol or its >= maxit:
+                    break
+            y = np.zeros(j_done)
+            for i in range(j_done - 1, -1, -1):
+                y[i] = (g[i] - np.dot(Hs[i, i + 1:j_done], y[i + 1:j_done])) / Hs[i, i]
+            x = x + dinv * (V[:j_done].T @ y)
+            if res <= tol:
+                return x, its, res, True
+            if its >= maxit:
+                r = b - apply(x)
+                return x, its, float(np.linalg.norm(r)), False
+            r = b - apply(x)
+            beta = float(np.linalg.norm(r))
+            if beta <= tol:
+                return x, its, beta, True
+
+    # ------------------------------------------------------------------------------ time step
+    def initial_state(self, ubar: float = 0.0, dT: np.ndarray | None = None) -> np.ndarray:
+        """Hydrostatic background with uniform horizontal wind ubar; with a temperature
+        perturbation dT the pressure is kept and the density recomputed from p = rho R T."""
+        rho = self.rbar.copy()
+        if dT is not None:
+            T = self.pbar / (RGAS * self.rbar) + dT
+            rho = self.pbar / (RGAS * T)
+        U = np.zeros((self.nf, self.N))
+        U[0] = rho
+        U[1] = rho * ubar
+        U[1 + self.d] = self.pbar / (GAMMA - 1.0) + 0.5 * rho * ubar * ubar
+        return U
+
+    def implicit_term(self, U: np.ndarray) -> np.ndarray:
+        """F_I(U) = (0, -M^{-1} B p' - (rho - rhobar) g k, -M^{-1} (C(h m) + beta/(2(gamma-1)) P p'))."""
+        d = self.d
+        rho = U[0]
+        p = self.pressure(U)
+        pp = p - self.pbar
+        h = self.enthalpy(p, rho)
+        lam = self.cell_sound_speed(h)
+        F = np.zeros_like(U)
+        q = self.grad(pp)
+        F[1:1 + d] = -q
+        F[d] -= (rho - self.rbar) * G
+        e = self.div(h[None, :] * U[1:1 + d])
+        if self.beta != 0.0:
+            e = e + self.beta / (2.0 * (GAMMA - 1.0)) * self.penalty(lam, pp)
+        F[1 + d] = -e / self.wJ
+        return F
+
+    def step(self, U: np.ndarray, dt: float, fp_iters: int = 2, rtol: float = 1e-12,
+             atol: float = 0.0, restart: int = 30, maxit: int = 2000, stats: dict | None = None):
+        """One IMEX-RK2 step; returns the new state (the input is not modified)."""
+        d = self.d
+        A, At, b, bt = self.A, self.At, self.b, self.bt
+        FE = [self.explicit_residual(U)]
+        FI = [self.implicit_term(U)]
+        its_log = []
+        pp_prev = self.pressure(U) - self.pbar
+        m_prev = U[1:1 + d].copy()
+        for i in (1, 2):
+            aii = At[i, i]
+            dta = dt * aii
+            rho_i = U[0] + dt * sum(A[i, j] * FE[j][0] for j in range(i))
+            mt = U[1:1 + d] + dt * sum(A[i, j] * FE[j][1:1 + d] + At[i, j] * FI[j][1:1 + d]
+                                       for j in range(i))
+            et = U[1 + d] + dt * sum(A[i, j] * FE[j][1 + d] + At[i, j] * FI[j][1 + d]
+                                     for j in range(i))
+            mprime = mt.copy()
+            mprime[d - 1] -= dta * (rho_i - self.rbar) * G
+            pp = pp_prev.copy()
+            m = m_prev.copy()
+            for _ in range(fp_iters):
+                h = self.enthalpy(self.pbar + pp, rho_i)
+                rk = 0.5 * np.sum(m * m, axis=0) / rho_i
+                lam = self.cell_sound_speed(h)
+                rhs = self.wJ * (et - rk - self.pbar / (GAMMA - 1.0)) - dta * self.div(h[None, :] * mprime)
+                op = lambda v, h=h, lam=lam: self.helmholtz(dta, h, lam, v)
+                r0 = rhs - op(pp)
+                dinv = 1.0 / self.jacobi_diag(dta, h)
+                delta, its, res, ok = self.gmres(op, r0, dinv, rtol, atol, restart, maxit)
+                if not ok:
+                    raise RuntimeError("oracle GMRES did not converge (%d its, res %g)" % (its, res))
+                its_log.append(its)
+                pp = pp + delta
+                m = mprime - dta * self.grad(pp)
+            Ei = (self.pbar + pp) / (GAMMA - 1.0) + 0.5 * np.sum(m * m, axis=0) / rho_i
+            Ui = np.concatenate([rho_i[None], m, Ei[None]], axis=0)
+            Fi = np.zeros_like(U)
+            Fi[1:1 + d] = (m - mt) / dta
+            Fi[1 + d] = (Ei - et) / dta
+            FI.append(Fi)
+            FE.append(self.explicit_residual(Ui))
+            pp_prev = pp
+            m_prev = m
+        Un = U + dt * sum(b[j] * FE[j] + bt[j] * FI[j] for j in range(3))
+        if stats is not None:
+            stats["gmres_iters"] = its_log
+        return Un
+
+    # ------------------------------------------------------------------------------ diagnostics
+    def mass(self, U: np.ndarray) -> float:
+        return float(np.sum(self.wJ * U[0]))
+
+    def max_w(self, U: np.ndarray) -> float:
+        return float(np.max(np.abs(U[self.d] / U[0])))
+
+
+def courant(degree: int, speed: float, dt: float, cell_sizes, dim: int) -> float:
+    """Courant number of Section 3: r c dt sqrt(d) / H with H the minimum cell diameter (the
+    printed formula is garbled; this reading gives r c dt / dx on cubes)."""
+    diam = math.sqrt(sum(float(s) ** 2 for s in cell_sizes))
+    return degree * speed * dt * math.sqrt(dim) / diam
+
+
+def dofs_per_scalar(ncells: int, degree: int, dim: int) -> int:
+    """Unknowns per scalar field: cells x (r+1)^d (Section 3.2)."""
+    return int(ncells) * (degree + 1) ** dim
