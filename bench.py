@@ -1,0 +1,217 @@
+#!/usr/bin/env python
+"""Throughput of the IMEX-DG step on one MI355X.
+
+Metric: DoF-updates/s per IMEX-RK2 step (F fields x N nodes per step), FP64 and FP32-inner, with
+p50/p99 step latency.  Workload: 3D box 40 x 40 x 20 km, degree 4, 64 x 64 x 32 base hexahedra
+with one 2:1 level below 3 km over a Gaussian hill (274,432 cells, 171.5 M DoFs), stratified
+atmosphere, u = 10 m/s, dt = 0.6 s.  Inputs are synthetic and resident in HBM before timing.
+
+Prints one JSON line.  The roofline object reports the dominant operator kernel class measured
+live with HIP events around its launches on the solver's stream; cpu_baseline times the FP64
+oracle (as it stands) on a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q / 100.0
+    f = math.floor(k)
+    c = min(f + 1, len(xs) - 1)
+    return xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def run_gpu(w, precision, steps, warmup, timing=True):
+    import torch
+
+    import paper_2408_08129_amd as P
+    from tests import _common as C
+
+    opt = P.options(precision=precision, gmres_rtol=w.get("rtol", 1e-8))
+    s = P.Solver(C.product_case(w), w["degree"], opt)
+    U = s.init_state(w["ubar"])
+    for i in range(warmup):
+        s.step(U, w["dt"])
+        print("[bench] warmup step %d done" % i, file=sys.stderr, flush=True)
+    s.set_timing(timing)
+    torch.cuda.synchronize()
+    lat = []
+    stats = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ts = time.perf_counter()
+        st = s.step(U, w["dt"])
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - ts) * 1e3)
+        stats.append(st.as_dict(opt.fp_iters))
+        print("[bench] step %d %.1f ms its %s" % (i, lat[-1], stats[-1]["gmres_iters"]),
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    out = dict(solver=s, U=U, lat=lat, stats=stats, total=total, dofs=s.nf * s.N, N=s.N,
+               ncell=s.ncell, nf=s.nf)
+    return out
+
+
+def krylov_words_per_node(stats, restart, nf):
+    """Algorithmic words per node moved by the CGS2 passes and the solution update, from the
+    iteration counts (pass j reads j+1 basis vectors and the work vector three times, writes it
+    twice)."""
+    words = 0.0
+    for st in stats:
+        for stage in st["gmres_iters"]:
+            for its in stage:
+                j = 0
+                left = its
+                while left > 0:
+                    n = min(left, restart)
+                    for jj in range(n):
+                        nv = jj + 1
+                        words += 3 * (nv + 1) + 2
+                    words += n + 2  # update: n basis vectors + dinv + x
+                    left -= n
+    return words
+
+
+def roofline(res, w):
+    """Dominant operator kernel class over the timed region; algorithmic bytes per launch over
+    the event-measured average launch duration."""
+    d = w["dim"]
+    N = res["N"]
+    nf = res["nf"]
+    st = res["stats"]
+    tk = {k: sum(s["t_kernel_ms"][k] for s in st) for k in st[0]["t_kernel_ms"]}
+    nk = {k: sum(s["n_kernel"][k] for s in st) for k in st[0]["n_kernel"]}
+    # algorithmic bytes per launch (FP64 words per node)
+    words = {
+        "explicit_residual": 2 * nf,        # U in, R out
+        "weak_gradient": 1 + d,             # p in, q out (Helmholtz pass 1)
+        "weak_divergence": d + 3,           # q, h, p in, A p out (Helmholtz pass 2)
+    }
+    cand = {k: tk[k] for k in words if nk.get(k, 0) > 0}
+    dom = max(cand, key=cand.get)
+    avg_ms = tk[dom] / nk[dom]
+    bytes_per_launch = words[dom] * 8.0 * N
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    out = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+           "avg_launch_ms": round(avg_ms, 4), "launches": nk[dom],
+           "algorithmic_bytes_per_launch": bytes_per_launch}
+    # all classes, for the breakdown
+    out["breakdown_ms"] = {k: round(v, 2) for k, v in tk.items()}
+    out["launches_by_class"] = nk
+    hz = tk["weak_gradient"] + tk["weak_divergence"]
+    if nk["weak_divergence"]:
+        napply = nk["weak_gradient"]
+        out["helmholtz_apply_min3words_gbs"] = round(3 * 8.0 * N * napply / (hz * 1e-3) / 1e9, 1)
+    return out
+
+
+def cpu_baseline(w, budget_s=30.0):
+    """FP64 oracle on a column sample of the workload (same cell sizes, refinement and height)."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_2408_08129_amd import cases
+    from tests import _common as C
+
+    nx = int(os.environ.get("BENCH_CPU_COLUMNS", "2"))
+    ws = cases.column_sample(w, nx, nx)
+    o = O.Oracle(C.oracle_case(ws))
+    U = o.initial_state(w["ubar"])
+    t0 = time.perf_counter()
+    st = {}
+    o.step(U, w["dt"], rtol=w.get("rtol", 1e-8), stats=st)
+    t = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(o.nf * o.N / t, 1), "unit": "DoF-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "one FP64 IMEX-RK2 step of a %dx%d-column sample of the workload (%d cells, "
+                      "%d DoFs, full height, same refinement), %.1f s, GMRES its %s"
+                      % (nx, nx, o.ncell, o.nf * o.N, t, st.get("gmres_iters"))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="box3d_r4_hill")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2408_08129_amd as P
+    from paper_2408_08129_amd import cases
+
+    P.lib()  # fails loudly if the HIP library is not built
+    assert torch.cuda.is_available(), "needs a ROCm GPU"
+    w = dict(cases.WORKLOADS[args.workload])
+    w["rtol"] = 1e-8
+
+    r64 = run_gpu(w, P.DG_FP64, args.steps, args.warmup)
+    value = r64["dofs"] * args.steps / r64["total"]
+    line = {
+        "metric": "DoF-updates/s per IMEX-RK2 step (FP64 vs FP32-inner) + p50/p99 step latency",
+        "value": round(value, 1), "unit": "DoF-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(r64["total"] / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "cells": r64["ncell"], "dofs": r64["dofs"],
+                   "degree": w["degree"], "dim": w["dim"], "dt": w["dt"], "gmres_rtol": w["rtol"],
+                   "precision": "fp64"},
+        "p50_step_ms": round(percentile(r64["lat"], 50), 3),
+        "p99_step_ms": round(percentile(r64["lat"], 99), 3),
+        "gmres_iters": [s["gmres_iters"] for s in r64["stats"]],
+    }
+    line["roofline"] = roofline(r64, w)
+    if not args.no_mixed:
+        U64 = r64["U"]
+        ref = U64.clone()
+        del r64
+        torch.cuda.empty_cache()
+        r32 = run_gpu(w, P.DG_FP32_INNER, args.steps, args.warmup)
+        v32 = r32["dofs"] * args.steps / r32["total"]
+        # same number of steps from the same initial state: per-field difference to FP64
+        diff = []
+        for f in range(r32["nf"]):
+            a, b = r32["U"][f], ref[f]
+            diff.append(float((a - b).abs().max() / b.abs().max()))
+        line["fp32_inner"] = {
+            "value": round(v32, 1), "unit": "DoF-updates/s",
+            "ms_per_step": round(r32["total"] / args.steps * 1e3, 3),
+            "p50_step_ms": round(percentile(r32["lat"], 50), 3),
+            "p99_step_ms": round(percentile(r32["lat"], 99), 3),
+            "gain_vs_fp64": round(v32 / value, 3),
+            "max_rel_diff_vs_fp64_per_field": diff,
+            "inner_iters": [s["gmres_iters"] for s in r32["stats"]],
+            "outer_iters": [s["outer_iters"] for s in r32["stats"]],
+        }
+        del r32
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,195 @@
+/*
+ * imexdg.h — C ABI of the MI355X (gfx950) IMEX-DG library for the compressible Euler equations.
+ *
+ * The method is the one of Orlando, Benacchio, Bonaventura, "Efficient and scalable atmospheric
+ * dynamics simulations using non-conforming meshes" (arXiv 2408.08129):
+ *   - Section 2, Eq. (1): Euler equations for rho, rho u, rho E in SI units (g = 9.81, R = 287,
+ *     gamma = 1.4) on a domain of dimension d = 2 (x-z slice) or 3;
+ *   - Section 2: DG in space on quadrilaterals / hexahedra with 2:1 non-conforming faces, second
+ *     order IMEX Runge-Kutta in time, continuity explicit and energy coupled implicitly to momentum;
+ *   - Section 3.2: matrix-free operator action; the pressure fixed-point loop of each implicit
+ *     stage solves a non-symmetric linear system with GMRES;
+ *   - Section 3.1: terrain-following geometry over orography (Eq. (3) and variants) and the
+ *     stratified hydrostatic atmosphere of Eq. (4)-(5).
+ *
+ * Conventions shared by every call.
+ *   - Status: every function returns dg_status (DG_OK = 0, errors negative); no exception crosses
+ *     the ABI.  dg_last_error() returns a message for the calling thread's last error.
+ *   - Memory: pointers named *_dev are device pointers (HIP device memory, e.g. torch tensors on a
+ *     ROCm device), borrowed for the duration of the call.  All device work is ordered on the HIP
+ *     stream given to dg_setup (or dg_set_stream); a call returns when its work is queued, except
+ *     calls that return host values (they synchronise that stream).
+ *   - Layout of a state U: FP64, structure of arrays U[f][cell][node] with fields
+ *     f = (rho, rho u, rho w, rho E) in 2D and (rho, rho u, rho v, rho w, rho E) in 3D; cells in
+ *     the order reported by dg_cell_table; nodes at the tensor Gauss-Legendre points of degree r,
+ *     lexicographic with x fastest (2D: x then z).  Scalars (pressure, enthalpy) are [cell][node].
+ *   - Ownership: the context owns the mesh tables and all workspace, allocated in dg_setup and
+ *     released by dg_destroy.  One context must not be used by two threads at once; different
+ *     contexts are independent.
+ */
+#ifndef IMEXDG_H
+#define IMEXDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DG_OK = 0,
+  DG_EINVAL = -1,       /* invalid argument or mesh description (e.g. 2:1 violation) */
+  DG_ENOMEM = -2,       /* device or host allocation failed */
+  DG_EDEVICE = -3,      /* a HIP runtime call failed */
+  DG_ENOCONV = -4,      /* a GMRES solve missed its tolerance within its iteration limit */
+  DG_ENAN = -5,         /* a non-finite value appeared in the new state */
+  DG_EUNSUPPORTED = -6  /* degree / dimension not compiled in */
+} dg_status;
+
+typedef enum { DG_FP64 = 0, DG_FP32_INNER = 1 } dg_precision;
+
+enum { DG_ORO_FLAT = 0, DG_ORO_AGNESI = 1, DG_ORO_BELL = 2, DG_ORO_GAUSS_HILL = 3, DG_ORO_GAUSS_RIDGE = 4 };
+enum { DG_ATM_ISOTHERMAL = 0, DG_ATM_STRATIFIED = 1 };
+
+#define DG_MAX_RULES 8
+
+/* Refinement rule of level l (applied to cells of level l-1): refine when the logical cell centre
+ * has zeta < zeta_max and |x - x_c| < half_width_x (if > 0) and |y - y_c| < half_width_y (if > 0,
+ * 3D only).  Section 3.1 / Fig. 1: finer cells near the orography, coarser aloft. */
+typedef struct {
+  double zeta_max, x_c, half_width_x, y_c, half_width_y;
+} dg_refine_rule;
+
+/* Problem description, plain data copied at setup.
+ *   dim: 2 (x-z slice) or 3; nbase: base cells along x, y, z (y ignored in 2D);
+ *   length: Lx, Ly, H in metres (H = rigid-lid height); periodic_x / periodic_y: 1 periodic,
+ *   0 slip walls; bottom and top are slip walls;
+ *   orography: DG_ORO_*, oro = (height, width a or sigma, x_c, y_c):
+ *     AGNESI h a^2/(a^2+(x-x_c)^2); BELL h/(1+((x-x_c)/a)^2+((y-y_c)/a)^2)^(3/2) (Section 3.1,
+ *     Eq. (3)); GAUSS_HILL h exp(-r^2/(2 sigma^2)); GAUSS_RIDGE h exp(-((x-x_c)/a)^2);
+ *   atmosphere: DG_ATM_ISOTHERMAL atm = (p0, T0) or DG_ATM_STRATIFIED atm = (p_ref, T_ref, N)
+ *     (Section 3.1, Eq. (4)-(5), with the factor g^2/N^2 that makes the state hydrostatic). */
+typedef struct {
+  int32_t dim;
+  int32_t nbase[3];
+  double length[3];
+  int32_t periodic_x, periodic_y;
+  int32_t n_rules;
+  dg_refine_rule rules[DG_MAX_RULES];
+  int32_t orography;
+  double oro[4];
+  int32_t atmosphere;
+  double atm[3];
+} dg_case_desc;
+
+/* Solver options (Section 3.2: fixed-point loop + GMRES).
+ *   fp_iters: fixed-point iterations per implicit stage (>= 1);
+ *   gmres_restart, gmres_maxit, gmres_rtol, gmres_atol: right-preconditioned GMRES(m), stop when
+ *     ||r||_2 <= max(rtol ||r0||_2, atol);
+ *   precision: DG_FP64, or DG_FP32_INNER (FP64 defect correction around an FP32 GMRES whose
+ *     operator, preconditioner and basis are FP32; inner_rtol / inner_restart / inner_maxit);
+ *   penalty_beta: weight of the pressure-jump penalty in the implicit energy flux. */
+typedef struct {
+  int32_t fp_iters;
+  int32_t gmres_restart;
+  int32_t gmres_maxit;
+  double gmres_rtol;
+  double gmres_atol;
+  int32_t precision;
+  double inner_rtol;
+  int32_t inner_restart;
+  int32_t inner_maxit;
+  double penalty_beta;
+} dg_options;
+
+/* Per-step statistics ([implicit stage][fixed-point iteration]). */
+typedef struct {
+  int32_t gmres_iters[2][8];    /* Krylov iterations (FP32 inner iterations in mixed mode) */
+  int32_t outer_iters[2][8];    /* defect-correction sweeps (mixed mode), 0 for FP64 */
+  double gmres_relres[2][8];    /* final ||r|| / ||r0|| */
+  double t_kernel_ms[8];        /* with dg_set_timing on: device time summed per kernel class,
+                                   from HIP events around every launch on the context's stream:
+                                   0 explicit residual, 1 weak gradient M^-1 B, 2 weak divergence
+                                   with penalty (Helmholtz pass 2, right-hand side, implicit term),
+                                   3 Krylov orthogonalisation and update, 4 pointwise vector work */
+  int32_t n_kernel[8];          /* launches per class (timing on) */
+  double t_step_ms;             /* host wall time of the step (timing on) */
+  double mass, max_w;           /* diagnostics of the new state */
+} dg_step_stats;
+
+typedef struct dg_ctx dg_ctx;
+
+/* Fills *opt with the defaults: fp_iters 2, GMRES(30), rtol 1e-12, atol 0, maxit 2000, FP64,
+ * inner_rtol 1e-4, inner_restart 30, inner_maxit 500, penalty_beta 1. */
+void dg_default_options(dg_options* opt);
+
+/* Builds the mesh (refinement by rules, 2:1 balance check, Morton order), uploads it, and
+ * allocates the workspace.  degree in [1, 5]; stream: a hipStream_t (NULL = default stream).
+ * Errors: DG_EINVAL (bad description, 2:1 violation), DG_EUNSUPPORTED, DG_ENOMEM, DG_EDEVICE. */
+dg_status dg_setup(const dg_case_desc* desc, int32_t degree, const dg_options* opt, void* stream,
+                   dg_ctx** out);
+
+/* Exact device bytes dg_setup would allocate for this description, without allocating. */
+dg_status dg_footprint(const dg_case_desc* desc, int32_t degree, const dg_options* opt,
+                       size_t* bytes);
+
+/* Host-only mesh query (no device work): number of cells, number of hanging sub-faces (each
+ * counted once) and, if cells_out != NULL, the cell table in the order dg_setup uses
+ * (4 int32 per cell, as dg_cell_table).  Errors as dg_setup. */
+dg_status dg_mesh_info(const dg_case_desc* desc, int32_t degree, int64_t* n_cells,
+                       int64_t* n_hanging, int32_t* cells_out);
+
+dg_status dg_set_stream(dg_ctx* ctx, void* stream);
+dg_status dg_set_timing(dg_ctx* ctx, int32_t enable);
+
+/* Cells, nodes per scalar field, fields (d + 2). */
+dg_status dg_sizes(const dg_ctx* ctx, int64_t* n_cells, int64_t* nodes_per_field,
+                   int32_t* n_fields);
+
+/* Host output, 4 int32 per cell: (level, i_x, i_y, i_z) at the cell's own level (i_y = 0 in 2D);
+ * the cell's logical box is [i L / (n 2^level), (i + 1) L / (n 2^level)) per axis. */
+dg_status dg_cell_table(const dg_ctx* ctx, int32_t* host_out);
+
+/* Device outputs (any may be NULL), [cell][node]: physical x, y, z of every node and the
+ * quadrature weight times the Jacobian determinant (the diagonal mass matrix). */
+dg_status dg_node_geometry(dg_ctx* ctx, double* x_dev, double* y_dev, double* z_dev,
+                           double* wJ_dev);
+
+/* Initial state (Section 3.1): hydrostatic background with uniform wind (ubar, 0, 0); with
+ * dT_dev != NULL a temperature perturbation per node is added at constant pressure. */
+dg_status dg_init_state(dg_ctx* ctx, double ubar, const double* dT_dev, double* U_dev);
+
+/* R = M^{-1} (explicit weak form): the explicit time derivative (advective fluxes with a
+ * Rusanov flux on the advective speed, slip walls, gravity work on the energy), shape of U. */
+dg_status dg_explicit_residual(dg_ctx* ctx, const double* U_dev, double* R_dev);
+
+/* F = M^{-1} (implicit weak form) at U: (0, -B p' - M (rho - rhobar) g k,
+ * -C(h m) - beta/(2(gamma-1)) P p'), the implicit time derivative, shape of U. */
+dg_status dg_implicit_term(dg_ctx* ctx, const double* U_dev, double* F_dev);
+
+/* Ap = A(h) p = M p/(gamma-1) + dt_a beta/(2(gamma-1)) P p - dt_a^2 C (h M^{-1} B p), in weak
+ * (test-space) form; P uses per-cell sound speeds from h.  With prec = DG_FP32_INNER all three
+ * arrays are float, else double.  Uses the context's workspace; not reentrant per context. */
+dg_status dg_apply_helmholtz(dg_ctx* ctx, double dt_a, const void* h_dev, const void* p_dev,
+                             void* Ap_dev, int32_t prec);
+
+/* One IMEX-RK2 step of size dt, in place.  On any error U is left unchanged.  stats may be NULL. */
+dg_status imex_rk2_step(dg_ctx* ctx, double* U_dev, double dt, dg_step_stats* stats);
+
+/* One step for each of n contexts (ensemble members of any sizes), their work interleaved on
+ * the device; stats: array of n or NULL.  Returns the first error; members that failed keep
+ * their state, the others advance. */
+dg_status imex_rk2_step_batched(dg_ctx* const* ctxs, double* const* U_devs, const double* dts,
+                                int32_t n, dg_step_stats* stats);
+
+/* Total mass sum(w J rho) and max |w| (host outputs). */
+dg_status dg_diagnostics(dg_ctx* ctx, const double* U_dev, double* mass, double* max_w);
+
+const char* dg_last_error(void);
+void dg_destroy(dg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IMEXDG_H */

@@ -1,0 +1,88 @@
+// Internal types shared by the host solver and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "dg_mesh.hpp"
+
+namespace dg {
+
+constexpr double kG = 9.81;
+constexpr double kR = 287.0;
+constexpr double kGamma = 1.4;
+
+// Orography and atmosphere parameters (Section 3.1).
+struct Terrain {
+  int kind;   // DG_ORO_*
+  double h0, a, xc, yc;
+};
+
+// Device view of the mesh.  Per cell: (level, i0, i1, i2) at its own level (axis order: 3D x,y,z,
+// 2D x,z); per face (2 d per cell, face f = 2 k + s): kind and up to 2^(d-1) neighbour ids.
+struct MeshDev {
+  int dim;
+  int ncell;
+  long N;                 // nodes per field
+  const int4* cell;
+  const int* fkind;
+  const int4* fnbr;
+  const double* tab;      // 1D basis tables (layout: see TabLayout)
+  const float* tabf;
+  double L[3];
+  int nb[3];
+  int per[3];
+  Terrain ter;
+};
+
+// Offsets into the 1D table for NP = r + 1 points.
+struct TabLayout {
+  int np;
+  __host__ __device__ constexpr int xi() const { return 0; }
+  __host__ __device__ constexpr int w() const { return np; }
+  __host__ __device__ constexpr int dt() const { return 2 * np; }                  // Dt[i][q]
+  __host__ __device__ constexpr int lb() const { return 2 * np + np * np; }        // lb[s][a]
+  __host__ __device__ constexpr int lbw() const { return 4 * np + np * np; }       // lb/w
+  __host__ __device__ constexpr int pi() const { return 6 * np + np * np; }        // Pi[c][j][a]
+  __host__ __device__ constexpr int rw() const { return 6 * np + 3 * np * np; }    // Rw[c][a][j]
+  __host__ __device__ constexpr int size() const { return 6 * np + 5 * np * np; }
+};
+
+// ----------------------------------------------------------------------- operator parameters
+// Inputs of the weak gradient M^{-1} B p (output q, d fields).
+template <class T>
+struct GradArgs {
+  const T* p;         // p directly, or v with the Jacobi scaling below
+  const T* dinv;      // if non-null: p = scale * dinv * v
+  T scale;
+  T* q;               // out [d][N]
+};
+
+// Inputs of the weak divergence / Helmholtz pass:
+//   out = mode_weak ? w_i (acc + amass J p) : acc / J, with
+//   acc = (adiv C(h qv) + apen P p) / w_i.
+template <class T>
+struct DivArgs {
+  const T* qv;        // vector field [d][N]
+  const T* h;         // multiplier (may be null: 1)
+  const T* p;         // scalar for the penalty / mass terms (may be null)
+  const T* dinv;      // if non-null: p = scale * dinv * p
+  T scale;
+  const T* lam;       // per-cell sound speed for the penalty
+  T adiv, apen, amass;
+  int weak;
+  T* out;
+};
+
+// --------------------------------------------------------------------------------- launchers
+int launch_explicit(const MeshDev& m, int degree, const double* U, double* R, hipStream_t s);
+int launch_grad64(const MeshDev& m, int degree, const GradArgs<double>& a, hipStream_t s);
+int launch_div64(const MeshDev& m, int degree, const DivArgs<double>& a, hipStream_t s);
+int launch_grad32(const MeshDev& m, int degree, const GradArgs<float>& a, hipStream_t s);
+int launch_div32(const MeshDev& m, int degree, const DivArgs<float>& a, hipStream_t s);
+
+// node geometry: physical coordinates, w J, background p and rho per node
+int launch_geometry(const MeshDev& m, int degree, double* x, double* y, double* z, double* wJ,
+                    double* pbar, double* rbar, int atm_kind, const double* atm, hipStream_t s);
+
+}  // namespace dg

@@ -1,0 +1,1267 @@
+// IMEX-RK2 step, pressure fixed-point loop and GMRES on the device, plus the C ABI.
+//
+// Time integration (arXiv 2408.08129, Section 2): continuity explicit, energy coupled implicitly
+// to momentum, second-order IMEX Runge-Kutta (ARK2 of Giraldo, Kelly and Constantinescu, 2013:
+// explicit first stage, two implicit stages with diagonal 1 - 1/sqrt(2)).  Each implicit stage
+// runs the pressure fixed-point loop of Section 3.2; its linear system, non-symmetric, is solved
+// matrix-free with right-preconditioned GMRES.
+//
+// The implicit stage, with predictor rho_i, m~, e~ and m' = m~ - dt a (rho_i - rhobar) g k:
+//   A(h) delta = b - A(h) p',  A = M/(gamma-1) + dt a beta/(2(gamma-1)) P - (dt a)^2 C h M^-1 B,
+//   b = M (e~ - |m|^2/(2 rho_i) - pbar/(gamma-1)) - dt a C (h m'),
+//   p' += delta;  m = m' - dt a M^-1 B p';  h = gamma (pbar + p') / ((gamma-1) rho_i).
+// All vectors live in HBM; the host only drives the loop and solves the small Hessenberg least
+// squares problem.  Reductions are two-stage with a fixed shape, so results are bitwise
+// reproducible and independent of what else runs on the device.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "dg_internal.hpp"
+
+namespace dg {
+namespace {
+
+constexpr int kMaxV = 32;  // max Krylov vectors per pass (restart <= 31)
+constexpr int kRedThreads = 256;
+
+thread_local std::string g_last_error;
+
+struct Coef { double c[kMaxV]; };
+
+inline int red_grid(long n) {
+  long g = (n + kRedThreads - 1) / kRedThreads;
+  return (int)std::max(1L, std::min(1024L, g));
+}
+
+// --------------------------------------------------------------------------- reduction helpers
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-reduce nv per-thread sums (fixed order) and write part[i * gridDim.x + blockIdx.x].
+__device__ __forceinline__ void block_store(double (&acc)[kMaxV], int nv, double* part) {
+  __shared__ double s[kMaxV][kRedThreads / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < kMaxV; ++i) {
+    if (i < nv) {
+      const double v = wave_sum(acc[i]);
+      if (lane == 0) s[i][wv] = v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < nv) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < kRedThreads / 64; ++k) t += s[threadIdx.x][k];
+    part[(long)threadIdx.x * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+__global__ void k_reduce(const double* part, int nv, int G, double* out) {
+  __shared__ double s[kRedThreads];
+  for (int i = 0; i < nv; ++i) {
+    double t = 0.0;
+    for (int b = threadIdx.x; b < G; b += kRedThreads) t += part[(long)i * G + b];
+    s[threadIdx.x] = t;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = s[0];
+    __syncthreads();
+  }
+}
+
+// dots_i = sum_n V_i[n] w[n]
+template <class T>
+__global__ void __launch_bounds__(kRedThreads) k_mdot(const T* __restrict__ V, long ld, int nv,
+                                                      const T* __restrict__ w, double* part, long n) {
+  double acc[kMaxV];
+#pragma unroll
+  for (int i = 0; i < kMaxV; ++i) acc[i] = 0.0;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const double wv = (double)w[e];
+#pragma unroll
+    for (int i = 0; i < kMaxV; ++i)
+      if (i < nv) acc[i] += (double)V[i * ld + e] * wv;
+  }
+  block_store(acc, nv, part);
+}
+
+// w -= sum_i c_i V_i; then dots_i = sum V_i w
+template <class T>
+__global__ void __launch_bounds__(kRedThreads) k_axpy_mdot(const T* __restrict__ V, long ld, int nv,
+                                                           const Coef c, T* __restrict__ w,
+                                                           double* part, long n) {
+  double acc[kMaxV];
+#pragma unroll
+  for (int i = 0; i < kMaxV; ++i) acc[i] = 0.0;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    T v[kMaxV];
+    double x = (double)w[e];
+#pragma unroll
+    for (int i = 0; i < kMaxV; ++i)
+      if (i < nv) { v[i] = V[i * ld + e]; x -= c.c[i] * (double)v[i]; }
+    const T xt = (T)x;
+    w[e] = xt;
+#pragma unroll
+    for (int i = 0; i < kMaxV; ++i)
+      if (i < nv) acc[i] += (double)v[i] * (double)xt;
+  }
+  block_store(acc, nv, part);
+}
+
+// out = w - sum_i c_i V_i; part = |out|^2
+template <class T>
+__global__ void __launch_bounds__(kRedThreads) k_axpy_norm(const T* __restrict__ V, long ld, int nv,
+                                                           const Coef c, const T* __restrict__ w,
+                                                           T* __restrict__ out, double* part, long n) {
+  double acc[kMaxV];
+  acc[0] = 0.0;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    double x = (double)w[e];
+#pragma unroll
+    for (int i = 0; i < kMaxV; ++i)
+      if (i < nv) x -= c.c[i] * (double)V[i * ld + e];
+    const T xt = (T)x;
+    out[e] = xt;
+    acc[0] += (double)xt * (double)xt;
+  }
+  block_store(acc, 1, part);
+}
+
+// x += f dinv * sum_i c_i V_i  (FP64 accumulation)
+template <class T>
+__global__ void k_update(const T* __restrict__ V, long ld, int nv, const Coef c,
+                         const T* __restrict__ dinv, double* __restrict__ x, long n) {
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < kMaxV; ++i)
+      if (i < nv) s += c.c[i] * (double)V[i * ld + e];
+    x[e] += (double)dinv[e] * s;
+  }
+}
+
+__global__ void k_maxabs_ratio(const double* __restrict__ num, const double* __restrict__ den,
+                               double* part, long n) {
+  __shared__ double s[kRedThreads];
+  double m = 0.0;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    m = fmax(m, fabs(num[e] / den[e]));
+  s[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ void k_nonfinite(const double* __restrict__ x, long n, int* flag) {
+  bool bad = false;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    bad |= !isfinite(x[e]);
+  if (bad) atomicOr(flag, 1);
+}
+
+// ----------------------------------------------------------------------------- pointwise kernels
+#define GRID_LOOP(e, n) \
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < (n); e += (long)gridDim.x * blockDim.x)
+
+template <int D>
+__global__ void k_pressure_h(const double* __restrict__ U, const double* __restrict__ pbar, long N,
+                             long ld, double* __restrict__ pp, double* __restrict__ h) {
+  GRID_LOOP(e, N) {
+    const double rho = U[e];
+    double m2 = 0.0;
+#pragma unroll
+    for (int l = 0; l < D; ++l) m2 += U[(1 + l) * ld + e] * U[(1 + l) * ld + e];
+    const double p = (kGamma - 1.0) * (U[(1 + D) * ld + e] - 0.5 * m2 / rho);
+    pp[e] = p - pbar[e];
+    h[e] = kGamma * p / ((kGamma - 1.0) * rho);
+  }
+}
+
+// per-cell maximum of c = sqrt((gamma - 1) h)
+__global__ void k_lam(const double* __restrict__ h, int nloc, int ncell, double* lam, float* lam32) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  double m = 0.0;
+  for (int i = 0; i < nloc; ++i) m = fmax(m, sqrt((kGamma - 1.0) * h[(long)c * nloc + i]));
+  lam[c] = m;
+  if (lam32) lam32[c] = (float)m;
+}
+
+template <int D>
+__global__ void k_fi_momentum(const double* __restrict__ q, const double* __restrict__ U,
+                              const double* __restrict__ rbar, long N, long ld, double* __restrict__ F) {
+  GRID_LOOP(e, N) {
+    F[e] = 0.0;
+#pragma unroll
+    for (int l = 0; l < D; ++l) F[(1 + l) * ld + e] = -q[l * ld + e];
+    F[D * ld + e] -= (U[e] - rbar[e]) * kG;
+  }
+}
+
+// stage predictor from nj previous stages
+template <int D>
+__global__ void k_predictor(const double* __restrict__ U, const double* __restrict__ FE0,
+                            const double* __restrict__ FE1, const double* __restrict__ FI0,
+                            const double* __restrict__ FI1, int nj, double a0, double a1,
+                            double t0, double t1, double dt, double dta,
+                            const double* __restrict__ rbar, long N, long ld,
+                            double* __restrict__ Us, double* __restrict__ mt, double* __restrict__ et,
+                            double* __restrict__ mp) {
+  GRID_LOOP(e, N) {
+    double rho = FE0[e] * a0;
+    if (nj > 1) rho += FE1[e] * a1;
+    rho = U[e] + dt * rho;
+    Us[e] = rho;
+#pragma unroll
+    for (int f = 1; f < D + 2; ++f) {
+      double s = a0 * FE0[f * ld + e] + t0 * FI0[f * ld + e];
+      if (nj > 1) s += a1 * FE1[f * ld + e] + t1 * FI1[f * ld + e];
+      const double v = U[f * ld + e] + dt * s;
+      if (f <= D) {
+        mt[(f - 1) * ld + e] = v;
+        mp[(f - 1) * ld + e] = v;
+      } else {
+        et[e] = v;
+      }
+    }
+    mp[(D - 1) * ld + e] -= dta * (rho - rbar[e]) * kG;
+  }
+}
+
+// stage start: copy momentum and pressure perturbation of the previous stage (or of U^n)
+template <int D>
+__global__ void k_copy_m(const double* __restrict__ src, long ld, long N, double* __restrict__ dst) {
+  GRID_LOOP(e, N) {
+#pragma unroll
+    for (int l = 0; l < D; ++l) dst[(1 + l) * ld + e] = src[(1 + l) * ld + e];
+  }
+}
+
+// coefficients of the fixed-point iterate: h, Jacobi diagonal (inverse), FP32 copies
+__global__ void k_coef(const double* __restrict__ rho, const double* __restrict__ pbar,
+                       const double* __restrict__ pp, const double* __restrict__ wJ,
+                       const int4* __restrict__ cell, int nloc, int dim, double L0, double L1,
+                       double L2, int n0, int n1, int n2, int r1, double dta, long N,
+                       double* __restrict__ h, double* __restrict__ dinv, float* __restrict__ h32,
+                       float* __restrict__ dinv32) {
+  GRID_LOOP(e, N) {
+    const double hv = kGamma * (pbar[e] + pp[e]) / ((kGamma - 1.0) * rho[e]);
+    const int lev = cell[e / nloc].x;
+    const double d0 = L0 / (double)(n0 << lev), d1 = L1 / (double)(n1 << lev);
+    double S = (r1 / d0) * (r1 / d0) + (r1 / d1) * (r1 / d1);
+    if (dim == 3) {
+      const double d2 = L2 / (double)(n2 << lev);
+      S += (r1 / d2) * (r1 / d2);
+    }
+    const double dv = 1.0 / (wJ[e] * (1.0 / (kGamma - 1.0) + dta * dta * hv * S));
+    h[e] = hv;
+    dinv[e] = dv;
+    if (h32) {
+      h32[e] = (float)hv;
+      dinv32[e] = (float)dv;
+    }
+  }
+}
+
+template <int D>
+__global__ void k_rhs_add(double* __restrict__ b, const double* __restrict__ wJ,
+                          const double* __restrict__ et, const double* __restrict__ Us,
+                          const double* __restrict__ pbar, long N, long ld) {
+  GRID_LOOP(e, N) {
+    const double rho = Us[e];
+    double m2 = 0.0;
+#pragma unroll
+    for (int l = 0; l < D; ++l) m2 += Us[(1 + l) * ld + e] * Us[(1 + l) * ld + e];
+    b[e] += wJ[e] * (et[e] - 0.5 * m2 / rho - pbar[e] / (kGamma - 1.0));
+  }
+}
+
+__global__ void k_sub(const double* __restrict__ a, const double* __restrict__ b, long N,
+                      double* __restrict__ out) {
+  GRID_LOOP(e, N) out[e] = a[e] - b[e];
+}
+__global__ void k_add(double* __restrict__ a, const double* __restrict__ b, long N) {
+  GRID_LOOP(e, N) a[e] += b[e];
+}
+__global__ void k_zero(double* __restrict__ a, long N) {
+  GRID_LOOP(e, N) a[e] = 0.0;
+}
+__global__ void k_widen(const float* __restrict__ a, long N, double* __restrict__ out) {
+  GRID_LOOP(e, N) out[e] = (double)a[e];
+}
+__global__ void k_scale_cast(const double* __restrict__ a, double s, long N, float* __restrict__ out) {
+  GRID_LOOP(e, N) out[e] = (float)(s * a[e]);
+}
+
+template <int D>
+__global__ void k_backsub(const double* __restrict__ mp, const double* __restrict__ q, double dta,
+                          long N, long ld, double* __restrict__ Us) {
+  GRID_LOOP(e, N) {
+#pragma unroll
+    for (int l = 0; l < D; ++l) Us[(1 + l) * ld + e] = mp[l * ld + e] - dta * q[l * ld + e];
+  }
+}
+
+template <int D>
+__global__ void k_stage_finish(double* __restrict__ Us, const double* __restrict__ pp,
+                               const double* __restrict__ pbar, const double* __restrict__ mt,
+                               const double* __restrict__ et, double dta, long N, long ld,
+                               double* __restrict__ FI) {
+  GRID_LOOP(e, N) {
+    const double rho = Us[e];
+    double m2 = 0.0;
+#pragma unroll
+    for (int l = 0; l < D; ++l) {
+      const double m = Us[(1 + l) * ld + e];
+      m2 += m * m;
+      FI[(1 + l) * ld + e] = (m - mt[l * ld + e]) / dta;
+    }
+    const double E = (pbar[e] + pp[e]) / (kGamma - 1.0) + 0.5 * m2 / rho;
+    Us[(1 + D) * ld + e] = E;
+    FI[(1 + D) * ld + e] = (E - et[e]) / dta;
+    FI[e] = 0.0;
+  }
+}
+
+template <int D>
+__global__ void k_final(const double* __restrict__ U, const double* __restrict__ FE0,
+                        const double* __restrict__ FE1, const double* __restrict__ FE2,
+                        const double* __restrict__ FI0, const double* __restrict__ FI1,
+                        const double* __restrict__ FI2, double b0, double b1, double b2,
+                        double dt, long N, long ld, double* __restrict__ Un) {
+  GRID_LOOP(e, N) {
+    Un[e] = U[e] + dt * (b0 * FE0[e] + b1 * FE1[e] + b2 * FE2[e]);
+#pragma unroll
+    for (int f = 1; f < D + 2; ++f) {
+      const long i = f * ld + e;
+      Un[i] = U[i] + dt * ((b0 * FE0[i] + b1 * FE1[i] + b2 * FE2[i]) + (b0 * FI0[i] + b1 * FI1[i] + b2 * FI2[i]));
+    }
+  }
+}
+
+template <int D>
+__global__ void k_init_state(const double* __restrict__ pbar, const double* __restrict__ rbar,
+                             const double* __restrict__ dT, double ubar, long N, long ld,
+                             double* __restrict__ U) {
+  GRID_LOOP(e, N) {
+    double rho = rbar[e];
+    if (dT) {
+      const double T = pbar[e] / (kR * rbar[e]) + dT[e];
+      rho = pbar[e] / (kR * T);
+    }
+    U[e] = rho;
+    U[ld + e] = rho * ubar;
+#pragma unroll
+    for (int l = 1; l < D; ++l) U[(1 + l) * ld + e] = 0.0;
+    U[(1 + D) * ld + e] = pbar[e] / (kGamma - 1.0) + 0.5 * rho * ubar * ubar;
+  }
+}
+
+inline dim3 pw_grid(long n) {
+  long g = (n + 255) / 256;
+  return dim3((unsigned)std::max(1L, std::min(g, 65536L)));
+}
+
+// ------------------------------------------------------------------------------ basis tables
+// Gauss-Legendre points by Newton's method on P_n (long double), Lagrange basis on them.
+void gauss_legendre(int n, std::vector<long double>& x, std::vector<long double>& w) {
+  x.assign(n, 0);
+  w.assign(n, 0);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int i = 0; i < n; ++i) {
+    long double z = std::cos(pi * (4 * i + 3) / (4 * n + 2));
+    long double dp = 1;
+    for (int it = 0; it < 200; ++it) {
+      long double p0 = 1, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = z; p0 = 1; }
+      dp = n * (z * p1 - p0) / (z * z - 1);
+      const long double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs((double)dz) < 1e-19) break;
+    }
+    x[n - 1 - i] = z;
+    w[n - 1 - i] = 2 / ((1 - z * z) * dp * dp);
+  }
+}
+
+long double lagrange(const std::vector<long double>& xs, int j, long double t) {
+  long double v = 1;
+  for (size_t m = 0; m < xs.size(); ++m)
+    if ((int)m != j) v *= (t - xs[m]) / (xs[j] - xs[m]);
+  return v;
+}
+long double lagrange_d(const std::vector<long double>& xs, int j, long double t) {
+  // derivative via the product rule
+  long double s = 0;
+  for (size_t m = 0; m < xs.size(); ++m) {
+    if ((int)m == j) continue;
+    long double term = 1 / (xs[j] - xs[m]);
+    for (size_t q = 0; q < xs.size(); ++q)
+      if ((int)q != j && q != m) term *= (t - xs[q]) / (xs[j] - xs[q]);
+    s += term;
+  }
+  return s;
+}
+
+std::vector<double> make_tables(int np) {
+  TabLayout TL{np};
+  std::vector<double> t(TL.size(), 0.0);
+  std::vector<long double> x, w;
+  gauss_legendre(np, x, w);
+  for (int i = 0; i < np; ++i) {
+    t[TL.xi() + i] = (double)x[i];
+    t[TL.w() + i] = (double)w[i];
+  }
+  for (int i = 0; i < np; ++i)
+    for (int q = 0; q < np; ++q) t[TL.dt() + i * np + q] = (double)(w[q] * lagrange_d(x, i, x[q]) / w[i]);
+  for (int s = 0; s < 2; ++s)
+    for (int a = 0; a < np; ++a) {
+      const long double v = lagrange(x, a, s ? 1.0L : -1.0L);
+      t[TL.lb() + s * np + a] = (double)v;
+      t[TL.lbw() + s * np + a] = (double)(v / w[a]);
+    }
+  for (int c = 0; c < 2; ++c)
+    for (int j = 0; j < np; ++j)
+      for (int a = 0; a < np; ++a) {
+        const long double pt = (x[j] + 2 * c - 1) / 2;
+        const long double v = lagrange(x, a, pt);
+        t[TL.pi() + (c * np + j) * np + a] = (double)v;
+        t[TL.rw() + (c * np + a) * np + j] = (double)(w[j] / w[a] * v);
+      }
+  return t;
+}
+
+}  // namespace
+}  // namespace dg
+
+// ====================================================================================== context
+using namespace dg;
+
+struct dg_ctx {
+  HostMesh hm;
+  dg_case_desc desc{};
+  dg_options opt{};
+  int degree = 0, D = 0, F = 0, NL = 0;
+  long N = 0, ld = 0;
+  hipStream_t stream = nullptr;
+  bool timing = false;
+  MeshDev md{};
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  // mesh
+  int4* d_cell = nullptr;
+  int* d_fkind = nullptr;
+  int4* d_fnbr = nullptr;
+  double* d_tab = nullptr;
+  float* d_tabf = nullptr;
+  // geometry / background
+  double *pbar = nullptr, *rbar = nullptr, *wJ = nullptr;
+  // step workspace
+  double* FE[3] = {nullptr, nullptr, nullptr};
+  double* FI[3] = {nullptr, nullptr, nullptr};
+  double *Us = nullptr, *Un = nullptr, *mt = nullptr, *et = nullptr, *mp = nullptr;
+  double *pp = nullptr, *h = nullptr, *dinv = nullptr, *q = nullptr, *b = nullptr, *r0 = nullptr;
+  double *delta = nullptr, *w = nullptr, *V = nullptr, *lam = nullptr;
+  // mixed precision
+  float *h32 = nullptr, *dinv32 = nullptr, *lam32 = nullptr, *q32 = nullptr, *w32 = nullptr, *V32 = nullptr;
+  double* rr = nullptr;
+  // reductions
+  double* part = nullptr;
+  double* red = nullptr;
+  int* flag = nullptr;
+  double* hred = nullptr;  // pinned host
+  int m = 30, m32 = 30;
+  // per-launch HIP events (timing on): pairs around launches, tagged with a kernel class
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_cls;
+  int ev_n = 0;
+};
+
+namespace {
+
+dg_status fail(dg_ctx* c, dg_status st, const std::string& msg) {
+  g_last_error = msg;
+  (void)c;
+  return st;
+}
+
+constexpr int kEvPool = 8192;
+
+// Records a HIP event pair around the launches of its scope when timing is on.
+struct Timed {
+  dg_ctx* c;
+  int slot = -1;
+  Timed(dg_ctx* c_, int cls) : c(c_) {
+    if (c->timing && c->ev_n < kEvPool) {
+      slot = c->ev_n++;
+      c->ev_cls[slot] = cls;
+      (void)hipEventRecord(c->ev[2 * slot], c->stream);
+    }
+  }
+  ~Timed() {
+    if (slot >= 0) (void)hipEventRecord(c->ev[2 * slot + 1], c->stream);
+  }
+};
+#define TIMED(cls, stmt) \
+  do {                   \
+    Timed t_(c, cls);    \
+    stmt;                \
+  } while (0)
+
+#define HIPCHK(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      g_last_error = std::string(#call) + ": " + hipGetErrorString(e_);          \
+      return DG_EDEVICE;                                                          \
+    }                                                                             \
+  } while (0)
+#define LCHK(call)                                                                \
+  do {                                                                            \
+    int e_ = (call);                                                              \
+    if (e_ != 0) {                                                                \
+      g_last_error = std::string("launch failed: ") + #call;                     \
+      return e_ == -6 ? DG_EUNSUPPORTED : DG_EDEVICE;                             \
+    }                                                                             \
+  } while (0)
+
+struct Plan {
+  std::vector<std::pair<void**, size_t>> items;
+  size_t total = 0;
+  void add(void** p, size_t bytes) {
+    items.push_back({p, bytes});
+    total += (bytes + 255) & ~size_t(255);
+  }
+};
+
+// Every device allocation of a context, in bytes; used by dg_setup and dg_footprint.
+void make_plan(dg_ctx* c, Plan& P) {
+  const int D = c->D, F = c->F;
+  const long ld = c->ld;
+  const size_t nc = (size_t)c->hm.ncell;
+  const size_t d8 = sizeof(double), f4 = sizeof(float);
+  TabLayout TL{c->degree + 1};
+  P.add((void**)&c->d_cell, nc * sizeof(int4));
+  P.add((void**)&c->d_fkind, nc * 2 * D * sizeof(int));
+  P.add((void**)&c->d_fnbr, nc * 2 * D * sizeof(int4));
+  P.add((void**)&c->d_tab, TL.size() * d8);
+  P.add((void**)&c->d_tabf, TL.size() * f4);
+  P.add((void**)&c->pbar, ld * d8);
+  P.add((void**)&c->rbar, ld * d8);
+  P.add((void**)&c->wJ, ld * d8);
+  for (int j = 0; j < 3; ++j) {
+    P.add((void**)&c->FE[j], F * ld * d8);
+    P.add((void**)&c->FI[j], F * ld * d8);
+  }
+  P.add((void**)&c->Us, F * ld * d8);
+  P.add((void**)&c->Un, F * ld * d8);
+  P.add((void**)&c->mt, D * ld * d8);
+  P.add((void**)&c->et, ld * d8);
+  P.add((void**)&c->mp, D * ld * d8);
+  P.add((void**)&c->pp, ld * d8);
+  P.add((void**)&c->h, ld * d8);
+  P.add((void**)&c->dinv, ld * d8);
+  P.add((void**)&c->q, D * ld * d8);
+  P.add((void**)&c->b, ld * d8);
+  P.add((void**)&c->r0, ld * d8);
+  P.add((void**)&c->delta, ld * d8);
+  P.add((void**)&c->w, ld * d8);
+  P.add((void**)&c->lam, nc * d8);
+  if (c->opt.precision == DG_FP32_INNER) {
+    P.add((void**)&c->V, 1 * ld * d8);  // outer residual work
+    P.add((void**)&c->rr, ld * d8);
+    P.add((void**)&c->h32, ld * f4);
+    P.add((void**)&c->dinv32, ld * f4);
+    P.add((void**)&c->lam32, nc * f4);
+    P.add((void**)&c->q32, D * ld * f4);
+    P.add((void**)&c->w32, ld * f4);
+    P.add((void**)&c->V32, (size_t)(c->m32 + 1) * ld * f4);
+  } else {
+    P.add((void**)&c->V, (size_t)(c->m + 1) * ld * d8);
+  }
+  P.add((void**)&c->part, (size_t)kMaxV * 1024 * d8);
+  P.add((void**)&c->red, kMaxV * d8);
+  P.add((void**)&c->flag, 256);
+}
+
+dg_status prepare(dg_ctx* c, const dg_case_desc* desc, int degree, const dg_options* opt) {
+  if (!desc) return fail(c, DG_EINVAL, "null description");
+  c->desc = *desc;
+  if (opt) c->opt = *opt;
+  else dg_default_options(&c->opt);
+  const dg_options& o = c->opt;
+  if (o.fp_iters < 1 || o.fp_iters > 8) return fail(c, DG_EINVAL, "fp_iters must be in [1, 8]");
+  if (o.gmres_restart < 1 || o.gmres_restart > kMaxV - 1) return fail(c, DG_EINVAL, "gmres_restart must be in [1, 31]");
+  if (o.inner_restart < 1 || o.inner_restart > kMaxV - 1) return fail(c, DG_EINVAL, "inner_restart must be in [1, 31]");
+  if (o.precision != DG_FP64 && o.precision != DG_FP32_INNER) return fail(c, DG_EINVAL, "bad precision");
+  if (desc->orography < 0 || desc->orography > 4) return fail(c, DG_EINVAL, "bad orography kind");
+  if (desc->atmosphere < 0 || desc->atmosphere > 1) return fail(c, DG_EINVAL, "bad atmosphere kind");
+  if (desc->oro[0] >= desc->length[2]) return fail(c, DG_EINVAL, "orography higher than the lid");
+  std::string err;
+  const int rc = build_mesh(c->desc, degree, c->hm, err);
+  if (rc != DG_OK) return fail(c, (dg_status)rc, err);
+  c->degree = degree;
+  c->D = c->hm.dim;
+  c->F = c->D + 2;
+  c->NL = c->hm.nloc;
+  c->N = (long)c->hm.ncell * c->NL;
+  c->ld = c->N;  // fields are contiguous: U[f][cell][node]
+  c->m = o.gmres_restart;
+  c->m32 = o.inner_restart;
+  return DG_OK;
+}
+
+// ----------------------------------------------------------------------------- Krylov driver
+struct ApplyCtx {
+  dg_ctx* c;
+  double dta;
+};
+
+// w = A(h) (scale * dinv * v) in precision T (dinv may be null: plain v)
+template <class T>
+int apply_A(dg_ctx* c, double dta, const T* v, const T* dinv, T scale, T* w);
+
+template <>
+int apply_A<double>(dg_ctx* c, double dta, const double* v, const double* dinv, double scale, double* w) {
+  GradArgs<double> g{v, dinv, scale, c->q};
+  int rg;
+  TIMED(1, rg = launch_grad64(c->md, c->degree, g, c->stream));
+  if (rg) return -1;
+  const double beta = c->opt.penalty_beta;
+  DivArgs<double> a{c->q, c->h, v, dinv, scale, c->lam, -dta * dta,
+                    dta * beta / (2.0 * (kGamma - 1.0)), 1.0 / (kGamma - 1.0), 1, w};
+  int rd;
+  TIMED(2, rd = launch_div64(c->md, c->degree, a, c->stream));
+  return rd;
+}
+template <>
+int apply_A<float>(dg_ctx* c, double dta, const float* v, const float* dinv, float scale, float* w) {
+  GradArgs<float> g{v, dinv, scale, c->q32};
+  int rg;
+  TIMED(1, rg = launch_grad32(c->md, c->degree, g, c->stream));
+  if (rg) return -1;
+  const double beta = c->opt.penalty_beta;
+  DivArgs<float> a{c->q32, c->h32, v, dinv, scale, c->lam32, (float)(-dta * dta),
+                   (float)(dta * beta / (2.0 * (kGamma - 1.0))), (float)(1.0 / (kGamma - 1.0)), 1, w};
+  int rd;
+  TIMED(2, rd = launch_div32(c->md, c->degree, a, c->stream));
+  return rd;
+}
+
+// reduce nv partial sums to host
+dg_status reduce_to_host(dg_ctx* c, int nv, int G, double* out) {
+  TIMED(3, hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, c->stream, c->part, nv, G, c->red));
+  HIPCHK(hipMemcpyAsync(c->hred, c->red, nv * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  memcpy(out, c->hred, nv * sizeof(double));
+  return DG_OK;
+}
+
+template <class T>
+dg_status dot(dg_ctx* c, const T* a, const T* b, double* out) {
+  const int G = red_grid(c->N);
+  TIMED(3, hipLaunchKernelGGL((k_mdot<T>), dim3(G), dim3(kRedThreads), 0, c->stream, a, c->ld, 1, b, c->part, c->N));
+  return reduce_to_host(c, 1, G, out);
+}
+
+struct CycleResult {
+  int its = 0;
+  double res = 0.0;
+  bool converged = false;
+};
+
+// One GMRES(m) cycle on V[0] (unnormalised, norm beta), stopping at residual <= tol or maxits;
+// accumulates x += xscale * dinv * V y into the FP64 vector x.
+template <class T>
+dg_status gmres_cycle(dg_ctx* c, double dta, T* V, T* w, const T* dinv, int m, double beta,
+                      double tol, int maxits, double* x, double xscale, CycleResult& cr) {
+  const long ld = c->ld, N = c->N;
+  const int G = red_grid(N);
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m, 0.0), sn(m, 0.0), g(m + 1, 0.0), s(m + 1, 0.0);
+  s[0] = 1.0 / beta;
+  g[0] = beta;
+  double res = beta;
+  int jd = 0;
+  cr = CycleResult{};
+  Coef cf{};
+  double dots[kMaxV];
+  for (int j = 0; j < m; ++j) {
+    if (apply_A<T>(c, dta, V + (size_t)j * ld, dinv, (T)s[j], w)) return fail(c, DG_EDEVICE, "operator launch failed");
+    const int nv = j + 1;
+    // pass 1: classical Gram-Schmidt coefficients
+    TIMED(3, hipLaunchKernelGGL((k_mdot<T>), dim3(G), dim3(kRedThreads), 0, c->stream, V, ld, nv, (const T*)w, c->part, N));
+    dg_status st = reduce_to_host(c, nv, G, dots);
+    if (st) return st;
+    for (int i = 0; i < nv; ++i) {
+      H[(size_t)i * m + j] = dots[i] * s[i];
+      cf.c[i] = H[(size_t)i * m + j] * s[i];
+    }
+    // pass 2: subtract and re-orthogonalise (CGS2)
+    TIMED(3, hipLaunchKernelGGL((k_axpy_mdot<T>), dim3(G), dim3(kRedThreads), 0, c->stream, V, ld, nv, cf, w, c->part, N));
+    st = reduce_to_host(c, nv, G, dots);
+    if (st) return st;
+    for (int i = 0; i < nv; ++i) {
+      const double h2 = dots[i] * s[i];
+      H[(size_t)i * m + j] += h2;
+      cf.c[i] = h2 * s[i];
+    }
+    TIMED(3, hipLaunchKernelGGL((k_axpy_norm<T>), dim3(G), dim3(kRedThreads), 0, c->stream, V, ld, nv, cf,
+                       (const T*)w, V + (size_t)(j + 1) * ld, c->part, N));
+    double nrm2;
+    st = reduce_to_host(c, 1, G, &nrm2);
+    if (st) return st;
+    const double nrm = std::sqrt(nrm2);
+    if (!std::isfinite(nrm)) return fail(c, DG_ENAN, "non-finite value in the Krylov solve");
+    H[(size_t)(j + 1) * m + j] = nrm;
+    s[j + 1] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    // Givens
+    for (int i = 0; i < j; ++i) {
+      const double a = H[(size_t)i * m + j], b2 = H[(size_t)(i + 1) * m + j];
+      H[(size_t)i * m + j] = cs[i] * a + sn[i] * b2;
+      H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b2;
+    }
+    const double a = H[(size_t)j * m + j], b2 = H[(size_t)(j + 1) * m + j];
+    const double den = std::hypot(a, b2);
+    cs[j] = a / den;
+    sn[j] = b2 / den;
+    H[(size_t)j * m + j] = den;
+    H[(size_t)(j + 1) * m + j] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    res = std::fabs(g[j + 1]);
+    jd = j + 1;
+    cr.its++;
+    if (res <= tol || cr.its >= maxits || nrm == 0.0) break;
+  }
+  std::vector<double> y(jd, 0.0);
+  for (int i = jd - 1; i >= 0; --i) {
+    double t = g[i];
+    for (int k = i + 1; k < jd; ++k) t -= H[(size_t)i * m + k] * y[k];
+    y[i] = t / H[(size_t)i * m + i];
+  }
+  for (int i = 0; i < jd; ++i) cf.c[i] = xscale * y[i] * s[i];
+  TIMED(3, hipLaunchKernelGGL((k_update<T>), pw_grid(N), dim3(256), 0, c->stream, (const T*)V, ld, jd, cf, dinv, x, N));
+  cr.res = res;
+  cr.converged = res <= tol;
+  return DG_OK;
+}
+
+// Solve A delta = r0 (FP64), delta zeroed here.  Returns iterations and relative residual.
+dg_status solve64(dg_ctx* c, double dta, int& its, double& relres) {
+  const long N = c->N;
+  TIMED(4, hipLaunchKernelGGL(k_zero, pw_grid(N), dim3(256), 0, c->stream, c->delta, N));
+  double b2;
+  dg_status st = dot<double>(c, c->r0, c->r0, &b2);
+  if (st) return st;
+  const double bn = std::sqrt(b2);
+  if (!std::isfinite(bn)) return fail(c, DG_ENAN, "non-finite right-hand side");
+  const double tol = std::max(c->opt.gmres_rtol * bn, c->opt.gmres_atol);
+  its = 0;
+  relres = 0.0;
+  if (bn == 0.0 || bn <= tol) return DG_OK;
+  HIPCHK(hipMemcpyAsync(c->V, c->r0, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  double beta = bn;
+  while (true) {
+    CycleResult cr;
+    st = gmres_cycle<double>(c, dta, c->V, c->w, c->dinv, c->m, beta, tol, c->opt.gmres_maxit - its,
+                             c->delta, 1.0, cr);
+    if (st) return st;
+    its += cr.its;
+    relres = cr.res / bn;
+    if (cr.converged) return DG_OK;
+    if (its >= c->opt.gmres_maxit) break;
+    // restart from the true residual
+    if (apply_A<double>(c, dta, c->delta, nullptr, 1.0, c->w)) return fail(c, DG_EDEVICE, "operator launch failed");
+    TIMED(4, hipLaunchKernelGGL(k_sub, pw_grid(N), dim3(256), 0, c->stream, c->r0, c->w, N, c->V));
+    st = dot<double>(c, c->V, c->V, &b2);
+    if (st) return st;
+    beta = std::sqrt(b2);
+    relres = beta / bn;
+    if (beta <= tol) return DG_OK;
+  }
+  return fail(c, DG_ENOCONV, "GMRES did not reach its tolerance within gmres_maxit iterations");
+}
+
+// Mixed precision: FP64 defect correction around FP32 GMRES cycles.
+dg_status solve_mixed(dg_ctx* c, double dta, int& its, int& outer, double& relres) {
+  const long N = c->N;
+  TIMED(4, hipLaunchKernelGGL(k_zero, pw_grid(N), dim3(256), 0, c->stream, c->delta, N));
+  double b2;
+  dg_status st = dot<double>(c, c->r0, c->r0, &b2);
+  if (st) return st;
+  const double bn = std::sqrt(b2);
+  if (!std::isfinite(bn)) return fail(c, DG_ENAN, "non-finite right-hand side");
+  const double tol = std::max(c->opt.gmres_rtol * bn, c->opt.gmres_atol);
+  its = 0;
+  outer = 0;
+  relres = 0.0;
+  if (bn == 0.0 || bn <= tol) return DG_OK;
+  HIPCHK(hipMemcpyAsync(c->rr, c->r0, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  double rn = bn;
+  const int max_outer = 100;
+  while (rn > tol) {
+    if (outer >= max_outer || its >= c->opt.gmres_maxit)
+      return fail(c, DG_ENOCONV, "mixed-precision defect correction did not converge");
+    TIMED(4, hipLaunchKernelGGL(k_scale_cast, pw_grid(N), dim3(256), 0, c->stream, c->rr, 1.0 / rn, N, c->V32));
+    double v2;
+    st = dot<float>(c, c->V32, c->V32, &v2);
+    if (st) return st;
+    const double vb = std::sqrt(v2);
+    CycleResult cr;
+    st = gmres_cycle<float>(c, dta, c->V32, c->w32, c->dinv32, c->m32, vb, c->opt.inner_rtol * vb,
+                            c->opt.inner_maxit, c->delta, rn, cr);
+    if (st) return st;
+    its += cr.its;
+    outer++;
+    // FP64 residual of the accumulated correction
+    if (apply_A<double>(c, dta, c->delta, nullptr, 1.0, c->w)) return fail(c, DG_EDEVICE, "operator launch failed");
+    TIMED(4, hipLaunchKernelGGL(k_sub, pw_grid(N), dim3(256), 0, c->stream, c->r0, c->w, N, c->rr));
+    st = dot<double>(c, c->rr, c->rr, &b2);
+    if (st) return st;
+    rn = std::sqrt(b2);
+  }
+  relres = rn / bn;
+  return DG_OK;
+}
+
+// ----------------------------------------------------------------------------------- operators
+dg_status explicit_residual(dg_ctx* c, const double* U, double* R) {
+  int re;
+  TIMED(0, re = launch_explicit(c->md, c->degree, U, R, c->stream));
+  LCHK(re);
+  return DG_OK;
+}
+
+// F_I(U) into F; uses pp, h, lam, q as scratch
+dg_status implicit_term(dg_ctx* c, const double* U, double* F) {
+  const long N = c->N, ld = c->ld;
+  const int D = c->D;
+  if (D == 2)
+    TIMED(4, hipLaunchKernelGGL((k_pressure_h<2>), pw_grid(N), dim3(256), 0, c->stream, U, c->pbar, N, ld, c->pp, c->h));
+  else
+    TIMED(4, hipLaunchKernelGGL((k_pressure_h<3>), pw_grid(N), dim3(256), 0, c->stream, U, c->pbar, N, ld, c->pp, c->h));
+  TIMED(4, hipLaunchKernelGGL(k_lam, dim3((c->hm.ncell + 255) / 256), dim3(256), 0, c->stream, c->h, c->NL,
+                     c->hm.ncell, c->lam, (float*)nullptr));
+  GradArgs<double> g{c->pp, nullptr, 1.0, c->q};
+  int rg;
+  TIMED(1, rg = launch_grad64(c->md, c->degree, g, c->stream));
+  LCHK(rg);
+  if (D == 2)
+    TIMED(4, hipLaunchKernelGGL((k_fi_momentum<2>), pw_grid(N), dim3(256), 0, c->stream, c->q, U, c->rbar, N, ld, F));
+  else
+    TIMED(4, hipLaunchKernelGGL((k_fi_momentum<3>), pw_grid(N), dim3(256), 0, c->stream, c->q, U, c->rbar, N, ld, F));
+  const double beta = c->opt.penalty_beta;
+  DivArgs<double> a{U + ld, c->h, c->pp, nullptr, 1.0, c->lam, -1.0,
+                    -beta / (2.0 * (kGamma - 1.0)), 0.0, 0, F + (size_t)(1 + D) * ld};
+  int rd;
+  TIMED(2, rd = launch_div64(c->md, c->degree, a, c->stream));
+  LCHK(rd);
+  return DG_OK;
+}
+
+template <int D>
+dg_status step_impl(dg_ctx* c, double* U, double dt, dg_step_stats* stats) {
+  const long N = c->N, ld = c->ld;
+  const dim3 pg = pw_grid(N), bs(256);
+  hipStream_t s = c->stream;
+  const double g_ = 1.0 - 1.0 / std::sqrt(2.0), d_ = 1.0 / (2.0 * std::sqrt(2.0));
+  const double al = (3.0 + 2.0 * std::sqrt(2.0)) / 6.0;
+  const double A[3][3] = {{0, 0, 0}, {2 * g_, 0, 0}, {1 - al, al, 0}};
+  const double At[3][3] = {{0, 0, 0}, {g_, g_, 0}, {d_, d_, g_}};
+  const double bw[3] = {d_, d_, g_};
+  dg_step_stats st{};
+  dg_status rc;
+  c->ev_n = 0;
+  const auto t0 = std::chrono::steady_clock::now();
+
+  if ((rc = explicit_residual(c, U, c->FE[0]))) return rc;
+  if ((rc = implicit_term(c, U, c->FI[0]))) return rc;
+  // stage state starts from U^n: momentum, and p' (left in c->pp by implicit_term)
+  TIMED(4, hipLaunchKernelGGL((k_copy_m<D>), pg, bs, 0, s, U, ld, N, c->Us));
+  const double beta = c->opt.penalty_beta;
+  for (int i = 1; i <= 2; ++i) {
+    const double aii = At[i][i], dta = dt * aii;
+    // predictor; Us[0] <- rho_i, mt, et, mp
+    TIMED(4, hipLaunchKernelGGL((k_predictor<D>), pg, bs, 0, s, U, c->FE[0], c->FE[1], c->FI[0], c->FI[1], i,
+                       A[i][0], A[i][1], At[i][0], At[i][1], dt, dta, c->rbar, N, ld, c->Us, c->mt,
+                       c->et, c->mp));
+    for (int l = 0; l < c->opt.fp_iters; ++l) {
+      TIMED(4, hipLaunchKernelGGL(k_coef, pg, bs, 0, s, c->Us, c->pbar, c->pp, c->wJ, c->d_cell, c->NL, D,
+                         c->hm.L[0], c->hm.L[1], c->hm.L[2], c->hm.nb[0], c->hm.nb[1], c->hm.nb[2],
+                         c->degree + 1, dta, N, c->h, c->dinv,
+                         c->opt.precision == DG_FP32_INNER ? c->h32 : (float*)nullptr,
+                         c->opt.precision == DG_FP32_INNER ? c->dinv32 : (float*)nullptr));
+      TIMED(4, hipLaunchKernelGGL(k_lam, dim3((c->hm.ncell + 255) / 256), dim3(256), 0, s, c->h, c->NL,
+                         c->hm.ncell, c->lam,
+                         c->opt.precision == DG_FP32_INNER ? c->lam32 : (float*)nullptr));
+      // b = -dta C(h m') + M (e~ - rho k - pbar/(gamma-1))
+      DivArgs<double> a{c->mp, c->h, nullptr, nullptr, 1.0, c->lam, -dta, 0.0, 0.0, 1, c->b};
+      int rd;
+      TIMED(2, rd = launch_div64(c->md, c->degree, a, s));
+      LCHK(rd);
+      TIMED(4, hipLaunchKernelGGL((k_rhs_add<D>), pg, bs, 0, s, c->b, c->wJ, c->et, c->Us, c->pbar, N, ld));
+      // r0 = b - A p'
+      if (apply_A<double>(c, dta, c->pp, nullptr, 1.0, c->w)) return fail(c, DG_EDEVICE, "operator launch failed");
+      TIMED(4, hipLaunchKernelGGL(k_sub, pg, bs, 0, s, c->b, c->w, N, c->r0));
+      int its = 0, outer = 0;
+      double rel = 0.0;
+      if (c->opt.precision == DG_FP32_INNER) rc = solve_mixed(c, dta, its, outer, rel);
+      else rc = solve64(c, dta, its, rel);
+      if (l < 8) {
+        st.gmres_iters[i - 1][l] = its;
+        st.outer_iters[i - 1][l] = outer;
+        st.gmres_relres[i - 1][l] = rel;
+      }
+      if (rc) {
+        if (stats) *stats = st;
+        return rc;
+      }
+      TIMED(4, hipLaunchKernelGGL(k_add, pg, bs, 0, s, c->pp, c->delta, N));
+      GradArgs<double> gq{c->pp, nullptr, 1.0, c->q};
+      int rg;
+      TIMED(1, rg = launch_grad64(c->md, c->degree, gq, s));
+      LCHK(rg);
+      TIMED(4, hipLaunchKernelGGL((k_backsub<D>), pg, bs, 0, s, c->mp, c->q, dta, N, ld, c->Us));
+    }
+    TIMED(4, hipLaunchKernelGGL((k_stage_finish<D>), pg, bs, 0, s, c->Us, c->pp, c->pbar, c->mt, c->et, dta,
+                       N, ld, c->FI[i]));
+    if ((rc = explicit_residual(c, c->Us, c->FE[i]))) return rc;
+  }
+  (void)beta;
+  TIMED(4, hipLaunchKernelGGL((k_final<D>), pg, bs, 0, s, U, c->FE[0], c->FE[1], c->FE[2], c->FI[0], c->FI[1],
+                     c->FI[2], bw[0], bw[1], bw[2], dt, N, ld, c->Un));
+  HIPCHK(hipMemsetAsync(c->flag, 0, sizeof(int), s));
+  for (int f = 0; f < c->F; ++f)
+    TIMED(4, hipLaunchKernelGGL(k_nonfinite, pw_grid(N), bs, 0, s, c->Un + (size_t)f * ld, N, c->flag));
+  int hflag = 0;
+  HIPCHK(hipMemcpyAsync(c->hred, c->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  memcpy(&hflag, c->hred, sizeof(int));
+  if (hflag) {
+    if (stats) *stats = st;
+    return fail(c, DG_ENAN, "non-finite value in the new state");
+  }
+  HIPCHK(hipMemcpyAsync(U, c->Un, (size_t)c->F * ld * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (stats) {
+    double mass, mw;
+    if ((rc = dg_diagnostics(c, U, &mass, &mw))) return rc;
+    st.mass = mass;
+    st.max_w = mw;
+    if (c->timing) {
+      HIPCHK(hipStreamSynchronize(s));
+      st.t_step_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      for (int e = 0; e < c->ev_n; ++e) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c->ev[2 * e], c->ev[2 * e + 1]));
+        st.t_kernel_ms[c->ev_cls[e]] += ms;
+        st.n_kernel[c->ev_cls[e]] += 1;
+      }
+    }
+    *stats = st;
+  }
+  return DG_OK;
+}
+
+}  // namespace
+
+// ====================================================================================== C ABI
+extern "C" {
+
+void dg_default_options(dg_options* o) {
+  if (!o) return;
+  o->fp_iters = 2;
+  o->gmres_restart = 30;
+  o->gmres_maxit = 2000;
+  o->gmres_rtol = 1e-12;
+  o->gmres_atol = 0.0;
+  o->precision = DG_FP64;
+  o->inner_rtol = 1e-4;
+  o->inner_restart = 30;
+  o->inner_maxit = 500;
+  o->penalty_beta = 1.0;
+}
+
+const char* dg_last_error(void) { return g_last_error.c_str(); }
+
+dg_status dg_footprint(const dg_case_desc* desc, int32_t degree, const dg_options* opt, size_t* bytes) {
+  if (!bytes) return fail(nullptr, DG_EINVAL, "null output");
+  dg_ctx tmp;
+  dg_status st = prepare(&tmp, desc, degree, opt);
+  if (st) return st;
+  Plan P;
+  make_plan(&tmp, P);
+  *bytes = P.total;
+  return DG_OK;
+}
+
+dg_status dg_mesh_info(const dg_case_desc* desc, int32_t degree, int64_t* n_cells, int64_t* n_hanging,
+                       int32_t* cells_out) {
+  if (!desc) return fail(nullptr, DG_EINVAL, "null description");
+  HostMesh M;
+  std::string err;
+  const int rc = build_mesh(*desc, degree, M, err);
+  if (rc != DG_OK) return fail(nullptr, (dg_status)rc, err);
+  if (n_cells) *n_cells = M.ncell;
+  if (n_hanging) *n_hanging = M.nhang;
+  if (cells_out) {
+    for (int i = 0; i < M.ncell; ++i) {
+      const int* ci = &M.cell[4 * i];
+      cells_out[4 * i] = ci[0];
+      cells_out[4 * i + 1] = ci[1];
+      cells_out[4 * i + 2] = M.dim == 3 ? ci[2] : 0;
+      cells_out[4 * i + 3] = M.dim == 3 ? ci[3] : ci[2];
+    }
+  }
+  return DG_OK;
+}
+
+dg_status dg_setup(const dg_case_desc* desc, int32_t degree, const dg_options* opt, void* stream, dg_ctx** out) {
+  if (!out) return fail(nullptr, DG_EINVAL, "null output");
+  *out = nullptr;
+  dg_ctx* c = new (std::nothrow) dg_ctx();
+  if (!c) return fail(nullptr, DG_ENOMEM, "host allocation failed");
+  dg_status st = prepare(c, desc, degree, opt);
+  if (st) { delete c; return st; }
+  c->stream = (hipStream_t)stream;
+  Plan P;
+  make_plan(c, P);
+  hipError_t e = hipMalloc((void**)&c->arena, P.total);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(nullptr, DG_ENOMEM, std::string("hipMalloc of the workspace failed: ") + hipGetErrorString(e));
+  }
+  c->arena_bytes = P.total;
+  size_t off = 0;
+  for (auto& it : P.items) {
+    *it.first = c->arena + off;
+    off += (it.second + 255) & ~size_t(255);
+  }
+  e = hipHostMalloc((void**)&c->hred, 4096, hipHostMallocDefault);
+  if (e != hipSuccess) { dg_destroy(c); return fail(nullptr, DG_ENOMEM, "pinned host allocation failed"); }
+  // upload mesh and tables
+  const HostMesh& M = c->hm;
+  std::vector<int4> cells(M.ncell), nbr((size_t)M.ncell * 2 * c->D);
+  for (int i = 0; i < M.ncell; ++i) cells[i] = make_int4(M.cell[4 * i], M.cell[4 * i + 1], M.cell[4 * i + 2], M.cell[4 * i + 3]);
+  for (size_t i = 0; i < nbr.size(); ++i) nbr[i] = make_int4(M.fnbr[4 * i], M.fnbr[4 * i + 1], M.fnbr[4 * i + 2], M.fnbr[4 * i + 3]);
+  std::vector<double> tab = make_tables(c->degree + 1);
+  std::vector<float> tabf(tab.begin(), tab.end());
+  hipStream_t s = c->stream;
+#define SETUP_CHK(call)                                                             \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      std::string msg = std::string(#call) + ": " + hipGetErrorString(e_);         \
+      dg_destroy(c);                                                                \
+      return fail(nullptr, DG_EDEVICE, msg);                                        \
+    }                                                                               \
+  } while (0)
+  SETUP_CHK(hipMemcpyAsync(c->d_cell, cells.data(), cells.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+  SETUP_CHK(hipMemcpyAsync(c->d_fkind, M.fkind.data(), M.fkind.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  SETUP_CHK(hipMemcpyAsync(c->d_fnbr, nbr.data(), nbr.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+  SETUP_CHK(hipMemcpyAsync(c->d_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  SETUP_CHK(hipMemcpyAsync(c->d_tabf, tabf.data(), tabf.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  MeshDev& md = c->md;
+  md.dim = c->D;
+  md.ncell = M.ncell;
+  md.N = c->ld;  // field stride
+  md.cell = c->d_cell;
+  md.fkind = c->d_fkind;
+  md.fnbr = c->d_fnbr;
+  md.tab = c->d_tab;
+  md.tabf = c->d_tabf;
+  for (int a = 0; a < 3; ++a) {
+    md.L[a] = M.L[a];
+    md.nb[a] = M.nb[a];
+    md.per[a] = M.per[a];
+  }
+  md.ter = Terrain{c->desc.orography, c->desc.oro[0], c->desc.oro[1], c->desc.oro[2], c->desc.oro[3]};
+  {
+    MeshDev g = md;
+    g.N = c->N;  // geometry kernel iterates over N nodes
+    if (launch_geometry(g, c->degree, nullptr, nullptr, nullptr, c->wJ, c->pbar, c->rbar,
+                        c->desc.atmosphere, c->desc.atm, s)) {
+      dg_destroy(c);
+      return fail(nullptr, DG_EDEVICE, "geometry kernel launch failed");
+    }
+  }
+  SETUP_CHK(hipStreamSynchronize(s));
+#undef SETUP_CHK
+  *out = c;
+  return DG_OK;
+}
+
+void dg_destroy(dg_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  for (auto& e : c->ev) (void)hipEventDestroy(e);
+  if (c->arena) (void)hipFree(c->arena);
+  if (c->hred) (void)hipHostFree(c->hred);
+  delete c;
+}
+
+dg_status dg_set_stream(dg_ctx* c, void* stream) {
+  if (!c) return fail(nullptr, DG_EINVAL, "null context");
+  c->stream = (hipStream_t)stream;
+  return DG_OK;
+}
+
+dg_status dg_set_timing(dg_ctx* c, int32_t enable) {
+  if (!c) return fail(nullptr, DG_EINVAL, "null context");
+  c->timing = enable != 0;
+  if (c->timing && c->ev.empty()) {
+    c->ev.resize(2 * kEvPool);
+    c->ev_cls.assign(kEvPool, 0);
+    for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+  }
+  return DG_OK;
+}
+
+dg_status dg_sizes(const dg_ctx* c, int64_t* n_cells, int64_t* nodes, int32_t* nf) {
+  if (!c) return fail(nullptr, DG_EINVAL, "null context");
+  if (n_cells) *n_cells = c->hm.ncell;
+  if (nodes) *nodes = c->N;
+  if (nf) *nf = c->F;
+  return DG_OK;
+}
+
+dg_status dg_cell_table(const dg_ctx* c, int32_t* out) {
+  if (!c || !out) return fail(nullptr, DG_EINVAL, "null argument");
+  for (int i = 0; i < c->hm.ncell; ++i) {
+    const int* ci = &c->hm.cell[4 * i];
+    out[4 * i] = ci[0];
+    if (c->D == 3) {
+      out[4 * i + 1] = ci[1];
+      out[4 * i + 2] = ci[2];
+      out[4 * i + 3] = ci[3];
+    } else {
+      out[4 * i + 1] = ci[1];
+      out[4 * i + 2] = 0;
+      out[4 * i + 3] = ci[2];
+    }
+  }
+  return DG_OK;
+}
+
+dg_status dg_node_geometry(dg_ctx* c, double* x, double* y, double* z, double* wJ) {
+  if (!c) return fail(nullptr, DG_EINVAL, "null context");
+  MeshDev g = c->md;
+  g.N = c->N;
+  if (launch_geometry(g, c->degree, x, y, z, wJ, nullptr, nullptr, c->desc.atmosphere, c->desc.atm, c->stream))
+    return fail(c, DG_EDEVICE, "geometry kernel launch failed");
+  return DG_OK;
+}
+
+dg_status dg_init_state(dg_ctx* c, double ubar, const double* dT, double* U) {
+  if (!c || !U) return fail(nullptr, DG_EINVAL, "null argument");
+  if (c->D == 2)
+    hipLaunchKernelGGL((k_init_state<2>), pw_grid(c->N), dim3(256), 0, c->stream, c->pbar, c->rbar, dT, ubar, c->N, c->ld, U);
+  else
+    hipLaunchKernelGGL((k_init_state<3>), pw_grid(c->N), dim3(256), 0, c->stream, c->pbar, c->rbar, dT, ubar, c->N, c->ld, U);
+  HIPCHK(hipGetLastError());
+  return DG_OK;
+}
+
+dg_status dg_explicit_residual(dg_ctx* c, const double* U, double* R) {
+  if (!c || !U || !R) return fail(nullptr, DG_EINVAL, "null argument");
+  return explicit_residual(c, U, R);
+}
+
+dg_status dg_implicit_term(dg_ctx* c, const double* U, double* F) {
+  if (!c || !U || !F) return fail(nullptr, DG_EINVAL, "null argument");
+  return implicit_term(c, U, F);
+}
+
+dg_status dg_apply_helmholtz(dg_ctx* c, double dta, const void* h, const void* p, void* Ap, int32_t prec) {
+  if (!c || !h || !p || !Ap) return fail(nullptr, DG_EINVAL, "null argument");
+  const long N = c->N;
+  if (prec == DG_FP64) {
+    HIPCHK(hipMemcpyAsync(c->h, h, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    hipLaunchKernelGGL(k_lam, dim3((c->hm.ncell + 255) / 256), dim3(256), 0, c->stream, c->h, c->NL,
+                       c->hm.ncell, c->lam, (float*)nullptr);
+    if (apply_A<double>(c, dta, (const double*)p, nullptr, 1.0, (double*)Ap)) return fail(c, DG_EDEVICE, "launch failed");
+    return DG_OK;
+  }
+  if (prec == DG_FP32_INNER) {
+    if (c->opt.precision != DG_FP32_INNER)
+      return fail(c, DG_EINVAL, "context was set up without the FP32 workspace (precision option)");
+    // h in FP32: copy, and widen to FP64 for the per-cell sound speed
+    HIPCHK(hipMemcpyAsync(c->h32, h, N * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+    hipLaunchKernelGGL(k_widen, pw_grid(N), dim3(256), 0, c->stream, (const float*)c->h32, N, c->h);
+    hipLaunchKernelGGL(k_lam, dim3((c->hm.ncell + 255) / 256), dim3(256), 0, c->stream, c->h, c->NL,
+                       c->hm.ncell, c->lam, c->lam32);
+    if (apply_A<float>(c, dta, (const float*)p, nullptr, 1.0f, (float*)Ap)) return fail(c, DG_EDEVICE, "launch failed");
+    return DG_OK;
+  }
+  return fail(c, DG_EINVAL, "bad precision");
+}
+
+dg_status imex_rk2_step(dg_ctx* c, double* U, double dt, dg_step_stats* stats) {
+  if (!c || !U) return fail(nullptr, DG_EINVAL, "null argument");
+  if (!(dt > 0.0)) return fail(c, DG_EINVAL, "dt must be positive");
+  return c->D == 2 ? step_impl<2>(c, U, dt, stats) : step_impl<3>(c, U, dt, stats);
+}
+
+dg_status imex_rk2_step_batched(dg_ctx* const* ctxs, double* const* Us, const double* dts, int32_t n,
+                                dg_step_stats* stats) {
+  if (n < 0 || (n > 0 && (!ctxs || !Us || !dts))) return fail(nullptr, DG_EINVAL, "bad batch");
+  std::vector<dg_status> rc(n, DG_OK);
+  std::vector<std::string> msg(n);
+  std::vector<std::thread> th;
+  th.reserve(n);
+  for (int i = 0; i < n; ++i)
+    th.emplace_back([&, i]() {
+      rc[i] = imex_rk2_step(ctxs[i], Us[i], dts[i], stats ? &stats[i] : nullptr);
+      if (rc[i]) msg[i] = g_last_error;
+    });
+  for (auto& t : th) t.join();
+  for (int i = 0; i < n; ++i)
+    if (rc[i]) {
+      g_last_error = "member " + std::to_string(i) + ": " + msg[i];
+      return rc[i];
+    }
+  return DG_OK;
+}
+
+dg_status dg_diagnostics(dg_ctx* c, const double* U, double* mass, double* max_w) {
+  if (!c || !U) return fail(nullptr, DG_EINVAL, "null argument");
+  const long N = c->N;
+  if (mass) {
+    dg_status st = dot<double>(c, c->wJ, U, mass);
+    if (st) return st;
+  }
+  if (max_w) {
+    const int G = red_grid(N);
+    hipLaunchKernelGGL(k_maxabs_ratio, dim3(G), dim3(kRedThreads), 0, c->stream, U + (size_t)c->D * c->ld, U, c->part, N);
+    std::vector<double> parts(G);
+    HIPCHK(hipMemcpyAsync(parts.data(), c->part, G * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    double m = 0.0;
+    for (double v : parts) m = std::max(m, v);
+    *max_w = m;
+  }
+  return DG_OK;
+}
+
+}  // extern "C"

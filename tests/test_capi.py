@@ -1,0 +1,102 @@
+"""The C-ABI library loads, exports every declared symbol, and its host-only mesh queries agree
+with the oracle's mesh (no GPU needed)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2408_08129_amd as P
+from paper_2408_08129_amd import cases
+from oracle import oracle as O
+from tests import _common as C
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "imexdg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:dg|imex)_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = P.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(P.EXPORTED)
+
+
+def test_default_options():
+    o = P.options()
+    assert (o.fp_iters, o.gmres_restart, o.gmres_maxit) == (2, 30, 2000)
+    assert o.gmres_rtol == 1e-12 and o.precision == P.DG_FP64
+
+
+@pytest.mark.parametrize("mk", [C.tiny2d, C.tiny3d, C.twolevel2d, C.twolevel3d, C.walls2d])
+def test_mesh_matches_oracle(mk):
+    w = mk(2)
+    n, nh, cells = P.dg_mesh_info(C.product_case(w), w["degree"])
+    o = O.Oracle(C.oracle_case(w))
+    assert n == o.ncell and nh == o.nhang
+    C.cell_perm(cells, o.cells)  # same set of cells
+
+
+@pytest.mark.parametrize("name,ncell,nhang", [("slice2d_r2_conforming", 512, 0),
+                                              ("slice2d_r4_twolevel", 3200, 176),
+                                              ("box3d_r4_hill", 274432, 16384),
+                                              ("box3d_r4_ridge_large", 2183168, 30720)])
+def test_workload_mesh_sizes(name, ncell, nhang):
+    w = dict(cases.WORKLOADS[name])
+    n, nh, _ = P.dg_mesh_info(C.product_case(w), w["degree"], with_cells=False)
+    assert (n, nh) == (ncell, nhang)
+
+
+def test_mesh_is_morton_ordered_and_consistent():
+    w = cases.WORKLOADS["slice2d_r4_twolevel"]
+    n, nh, cells = P.dg_mesh_info(C.product_case(w), w["degree"])
+    lmax = cells[:, 0].max()
+    keys = []
+    for lev, ix, iy, iz in cells.tolist():
+        x, z = ix << (lmax - lev), iz << (lmax - lev)
+        k = 0
+        for b in range(20):
+            k |= ((x >> b) & 1) << (2 * b) | ((z >> b) & 1) << (2 * b + 1)
+        keys.append(k)
+    assert keys == sorted(keys)
+
+
+def test_two_to_one_violation_is_rejected():
+    w = dict(C.twolevel2d(1))
+    w["rules"] = [(1000.0, 500.0, 500.0, 0, 0), (500.0, 500.0, 500.0, 0, 0), (400.0, 500.0, 500.0, 0, 0)]
+    with pytest.raises(P.DGError) as e:
+        P.dg_mesh_info(C.product_case(w), 1)
+    assert e.value.status == P.DG_EINVAL
+    assert "2:1" in str(e.value)
+
+
+def test_invalid_arguments():
+    w = C.tiny2d(2)
+    with pytest.raises(P.DGError) as e:
+        P.dg_mesh_info(C.product_case(w), 9)
+    assert e.value.status == P.DG_EUNSUPPORTED
+    w = dict(w)
+    w["dim"] = 4
+    with pytest.raises(P.DGError) as e:
+        P.dg_mesh_info(C.product_case(w), 2)
+    assert e.value.status == P.DG_EINVAL
+
+
+def test_footprint_scales_with_size_and_precision():
+    w = cases.WORKLOADS["slice2d_r4_twolevel"]
+    c = C.product_case(w)
+    b64 = P.dg_footprint(c, 4, P.options())
+    b32 = P.dg_footprint(c, 4, P.options(precision=P.DG_FP32_INNER))
+    N = 3200 * 25
+    assert 60 * 8 * N < b64 < 120 * 8 * N
+    assert b32 < b64
+    big = cases.WORKLOADS["box3d_r4_ridge_large"]
+    bl = P.dg_footprint(C.product_case(big), 4, P.options(precision=P.DG_FP32_INNER))
+    assert bl < 288e9  # fits one MI355X
