@@ -16,7 +16,10 @@ constexpr double kGamma = 1.4;
 struct Terrain {
   int kind;   // DG_ORO_*
   double h0, a, xc, yc;
+  double ia2; // 1 / a^2
 };
+
+constexpr int kMaxLev = 9;  // levels 0..8
 
 // Device view of the mesh.  Per cell: (level, i0, i1, i2) at its own level (axis order: 3D x,y,z,
 // 2D x,z); per face (2 d per cell, face f = 2 k + s): kind and up to 2^(d-1) neighbour ids.
@@ -33,6 +36,9 @@ struct MeshDev {
   int nb[3];
   int per[3];
   Terrain ter;
+  double invH;                 // 1 / lid height
+  double dxl[kMaxLev][3];      // cell size per level and axis
+  int nlev[kMaxLev][3];        // cells per axis at each level
 };
 
 // Offsets into the 1D table for NP = r + 1 points.
@@ -55,7 +61,9 @@ struct GradArgs {
   const T* p;         // p directly, or v with the Jacobi scaling below
   const T* dinv;      // if non-null: p = scale * dinv * v
   T scale;
-  T* q;               // out [d][N]
+  T* q;               // out [d][N]: M^{-1} B p, times h if h is non-null
+  const T* h;         // optional pointwise multiplier of the output
+  T* z;               // optional: the (scaled) p at the nodes
 };
 
 // Inputs of the weak divergence / Helmholtz pass:

@@ -67,32 +67,33 @@ template <class T>
 __device__ __forceinline__ void terrain(const Terrain& t, int dim, T x, T y, T& h, T& hx, T& hy) {
   const T dx = x - (T)t.xc;
   const T dy = (dim == 3) ? y - (T)t.yc : T(0);
-  const T a = (T)t.a, h0 = (T)t.h0;
+  const T h0 = (T)t.h0, ia2 = (T)t.ia2;
   h = hx = hy = T(0);
   switch (t.kind) {
-    case 1: {  // Witch of Agnesi
-      const T q = a * a + dx * dx;
-      h = h0 * a * a / q;
-      hx = T(-2) * dx * h / q;
+    case 1: {  // Witch of Agnesi: h0 a^2 / (a^2 + dx^2)
+      const T iq = T(1) / (T(1) + dx * dx * ia2);
+      h = h0 * iq;
+      hx = T(-2) * dx * ia2 * h * iq;
       break;
     }
-    case 2: {  // bell (Section 3.1, Eq. (3))
-      const T tt = T(1) + (dx * dx + dy * dy) / (a * a);
-      h = h0 / (tt * sqrt(tt));
-      const T c = T(-3) * h / (tt * a * a);
+    case 2: {  // bell (Section 3.1, Eq. (3)): h0 / (1 + (dx^2 + dy^2)/a^2)^(3/2)
+      const T tt = T(1) + (dx * dx + dy * dy) * ia2;
+      const T it = T(1) / tt;
+      h = h0 * it * sqrt(it);
+      const T c = T(-3) * h * it * ia2;
       hx = c * dx;
       hy = c * dy;
       break;
     }
-    case 3: {  // Gaussian hill
-      h = h0 * exp(-(dx * dx + dy * dy) / (T(2) * a * a));
-      hx = -dx / (a * a) * h;
-      hy = -dy / (a * a) * h;
+    case 3: {  // Gaussian hill: h0 exp(-(dx^2 + dy^2) / (2 sigma^2))
+      h = h0 * exp(-(dx * dx + dy * dy) * (T(0.5) * ia2));
+      hx = -dx * ia2 * h;
+      hy = -dy * ia2 * h;
       break;
     }
-    case 4: {  // Gaussian ridge along y
-      h = h0 * exp(-(dx * dx) / (a * a));
-      hx = T(-2) * dx / (a * a) * h;
+    case 4: {  // Gaussian ridge along y: h0 exp(-((x - xc)/a)^2)
+      h = h0 * exp(-(dx * dx) * ia2);
+      hx = T(-2) * dx * ia2 * h;
       break;
     }
     default:
@@ -100,31 +101,37 @@ __device__ __forceinline__ void terrain(const Terrain& t, int dim, T x, T y, T& 
   }
 }
 
-// Metric of the affine cell map at level lev composed with z = zeta + h (1 - zeta / H) at the
-// logical point X: Gam[k][l] = det(J) (J^{-1})_{kl} (row k = area-weighted normal of a face of
-// constant xi_k), J = det(J).
+// Metric of the cell map at level lev composed with z = zeta + h (1 - zeta / H), given the
+// terrain height and slopes at the point's horizontal position and its logical height zeta:
+// Gam[k][l] = det(J) (J^{-1})_{kl} (row k = area-weighted normal of a face of constant xi_k).
 template <int D, class T>
-__device__ __forceinline__ void metric(const MeshDev& m, int lev, const T* X, T (&Gam)[D][D], T& J) {
-  const T H = (T)m.L[D - 1];
-  T half[D];
-#pragma unroll
-  for (int a = 0; a < D; ++a) half[a] = (T)(0.5 * m.L[a] / (double)(m.nb[a] << lev));
-  T h, hx, hy;
-  terrain<T>(m.ter, D, X[0], D == 3 ? X[1] : T(0), h, hx, hy);
-  const T Jt = T(1) - h / H;
-  const T om = T(1) - X[D - 1] / H;
+__device__ __forceinline__ void metric_h(const MeshDev& m, int lev, T h, T hx, T hy, T zeta,
+                                         T (&Gam)[D][D], T& J) {
+  const T invH = (T)m.invH;
+  const T Jt = T(1) - h * invH;
+  const T om = T(1) - zeta * invH;
   if constexpr (D == 3) {
-    const T a = half[0], b = half[1], e = half[2], f = e * Jt;
+    const T a = T(0.5) * (T)m.dxl[lev][0], b = T(0.5) * (T)m.dxl[lev][1];
+    const T f = T(0.5) * (T)m.dxl[lev][2] * Jt;
     Gam[0][0] = b * f; Gam[0][1] = 0; Gam[0][2] = 0;
     Gam[1][0] = 0; Gam[1][1] = a * f; Gam[1][2] = 0;
     Gam[2][0] = -a * b * (hx * om); Gam[2][1] = -a * b * (hy * om); Gam[2][2] = a * b;
     J = a * b * f;
   } else {
-    const T a = half[0], e = half[1], f = e * Jt;
+    const T a = T(0.5) * (T)m.dxl[lev][0];
+    const T f = T(0.5) * (T)m.dxl[lev][1] * Jt;
     Gam[0][0] = f; Gam[0][1] = 0;
     Gam[1][0] = -a * (hx * om); Gam[1][1] = a;
     J = a * f;
   }
+}
+
+// Metric at a logical point X (terrain evaluated there).
+template <int D, class T>
+__device__ __forceinline__ void metric(const MeshDev& m, int lev, const T* X, T (&Gam)[D][D], T& J) {
+  T h, hx, hy;
+  terrain<T>(m.ter, D, X[0], D == 3 ? X[1] : T(0), h, hx, hy);
+  metric_h<D, T>(m, lev, h, hx, hy, X[D - 1], Gam, J);
 }
 
 // ----------------------------------------------------------------------------------- fluxes
@@ -173,13 +180,18 @@ template <int D>
 struct OpExplicit {
   using T = double;
   static constexpr int NIN = D + 2, NTR = D + 2, NOUT = D + 2;
+  // compact index of volume flux component (o, k); all are non-zero
+  static constexpr int NVOL = NOUT * D;
+  static constexpr int vidx(int o, int k) { return o * D + k; }
   const double* __restrict__ U;
   double* __restrict__ R;
-  long N;
-  __device__ __forceinline__ void load(long idx, T* in) const {
+  unsigned N;
+  __device__ __forceinline__ void load(unsigned idx, T* in) const {
 #pragma unroll
     for (int g = 0; g < NIN; ++g) in[g] = U[g * N + idx];
   }
+  __device__ __forceinline__ void load_face(unsigned idx, int, T* in) const { load(idx, in); }
+  static constexpr bool need(int, int) { return true; }
   __device__ __forceinline__ void transform(const T* in, T* tr) const {
 #pragma unroll
     for (int g = 0; g < NTR; ++g) tr[g] = in[g];
@@ -219,10 +231,11 @@ struct OpExplicit {
       for (int o = 0; o < NOUT; ++o) phi[o] = -sign * F[o];
     }
   }
-  __device__ __forceinline__ void finalize(long idx, const T* acc, T, T J, const T* tr) const {
+  __device__ __forceinline__ void finalize(unsigned idx, const T* acc, T, T J, const T* tr) const {
+    const T iJ = T(1) / J;
 #pragma unroll
-    for (int o = 0; o < NOUT; ++o) R[o * N + idx] = acc[o] / J;
-    R[(1 + D) * N + idx] = acc[1 + D] / J - kG * tr[D];
+    for (int o = 0; o < NOUT; ++o) R[o * N + idx] = acc[o] * iJ;
+    R[(1 + D) * N + idx] = acc[1 + D] * iJ - kG * tr[D];
   }
 };
 
@@ -230,12 +243,20 @@ template <int D, class TT>
 struct OpGrad {
   using T = TT;
   static constexpr int NIN = 2, NTR = 1, NOUT = D;
+  // -p Gam^T: the terrain-following map makes Gam[k][l] zero for k < d-1, l != k
+  static constexpr int NVOL = D == 3 ? 5 : 3;
+  static constexpr int vidx(int o, int k) {
+    return D == 3 ? (k == 0 ? (o == 0 ? 0 : -1) : k == 1 ? (o == 1 ? 1 : -1) : 2 + o)
+                  : (k == 0 ? (o == 0 ? 0 : -1) : 1 + o);
+  }
   GradArgs<T> a;
-  long N;
-  __device__ __forceinline__ void load(long idx, T* in) const {
+  unsigned N;
+  __device__ __forceinline__ void load(unsigned idx, T* in) const {
     in[0] = a.p[idx];
     in[1] = a.dinv ? a.dinv[idx] : T(1);
   }
+  __device__ __forceinline__ void load_face(unsigned idx, int, T* in) const { load(idx, in); }
+  static constexpr bool need(int, int) { return true; }
   __device__ __forceinline__ void transform(const T* in, T* tr) const {
     tr[0] = a.dinv ? a.scale * in[1] * in[0] : in[0];
   }
@@ -253,9 +274,12 @@ struct OpGrad {
 #pragma unroll
     for (int l = 0; l < D; ++l) phi[l] = sign * ph * Nv[l];
   }
-  __device__ __forceinline__ void finalize(long idx, const T* acc, T, T J, const T*) const {
+  __device__ __forceinline__ void finalize(unsigned idx, const T* acc, T, T J, const T* tr) const {
+    T iJ = T(1) / J;
+    if (a.h) iJ *= a.h[idx];
 #pragma unroll
-    for (int l = 0; l < D; ++l) a.q[l * N + idx] = acc[l] / J;
+    for (int l = 0; l < D; ++l) a.q[l * N + idx] = acc[l] * iJ;
+    if (a.z) a.z[idx] = tr[0];
   }
 };
 
@@ -263,11 +287,23 @@ template <int D, class TT>
 struct OpDiv {
   using T = TT;
   static constexpr int NIN = D + 3, NTR = D + 1, NOUT = 1;
+  static constexpr int NVOL = D;
+  static constexpr int vidx(int o, int k) { return o * D + k; }
   DivArgs<T> a;
-  long N;
-  __device__ __forceinline__ void load(long idx, T* in) const {
+  unsigned N;
+  __device__ __forceinline__ void load(unsigned idx, T* in) const {
 #pragma unroll
     for (int l = 0; l < D; ++l) in[l] = a.qv[l * N + idx];
+    in[D] = a.h ? a.h[idx] : T(1);
+    in[D + 1] = a.p ? a.p[idx] : T(0);
+    in[D + 2] = a.dinv ? a.dinv[idx] : T(1);
+  }
+  // Trace field g is needed on faces normal to axis k: for k < d-1 the area-weighted normal of
+  // the terrain-following map is (0..N_k..0), so only component k of the vector field enters.
+  static constexpr bool need(int k, int g) { return g >= D || k == D - 1 || g == k; }
+  __device__ __forceinline__ void load_face(unsigned idx, int k, T* in) const {
+#pragma unroll
+    for (int l = 0; l < D; ++l) in[l] = need(k, l) ? a.qv[l * N + idx] : T(0);
     in[D] = a.h ? a.h[idx] : T(1);
     in[D + 1] = a.p ? a.p[idx] : T(0);
     in[D + 2] = a.dinv ? a.dinv[idx] : T(1);
@@ -301,7 +337,7 @@ struct OpDiv {
     }
     phi[0] = v;
   }
-  __device__ __forceinline__ void finalize(long idx, const T* acc, T w, T J, const T* tr) const {
+  __device__ __forceinline__ void finalize(unsigned idx, const T* acc, T w, T J, const T* tr) const {
     if (a.weak) a.out[idx] = w * (acc[0] + a.amass * J * tr[D]);
     else a.out[idx] = acc[0] / J;
   }
@@ -312,33 +348,131 @@ template <class Op> struct HasLam { static constexpr bool value = false; };
 template <int D, class T> struct HasLam<OpDiv<D, T>> { static constexpr bool value = true; };
 
 // --------------------------------------------------------------------------------- the kernel
+// XCD-aware block order: the hardware hands consecutive workgroups to the 8 XCDs in turn; remap
+// so that each XCD walks a contiguous range of Morton-ordered cells and neighbour reads hit its L2.
+__device__ __forceinline__ int xcd_block(int b, int nblocks) {
+  constexpr int X = 8;
+  const int q = nblocks / X, r = nblocks % X;
+  const int x = b % X, i = b / X;
+  return x * q + (x < r ? x : r) + i;
+}
+
+// Coarse-face values at a fine sub-face point (tensor interpolation along the tangential axes).
+template <int D, int NP, class T>
+__device__ __forceinline__ T interp_sub(const T* Pi, const T* Tc, int c0, int c1, int j) {
+  T v = 0;
+  if constexpr (D == 3) {
+    const int j0 = j % NP, j1 = j / NP;
+#pragma unroll
+    for (int a1 = 0; a1 < NP; ++a1) {
+      T u = 0;
+#pragma unroll
+      for (int a0 = 0; a0 < NP; ++a0) u += Pi[(c0 * NP + j0) * NP + a0] * Tc[a0 + NP * a1];
+      v += Pi[(c1 * NP + j1) * NP + a1] * u;
+    }
+  } else {
+#pragma unroll
+    for (int a0 = 0; a0 < NP; ++a0) v += Pi[(c0 * NP + j) * NP + a0] * Tc[a0];
+  }
+  return v;
+}
+
+// Area-weighted normal (lower -> upper side along k) at face point j of the (sub)face of cell
+// (cl, cid) through face f (= 2k + s), evaluated from the integer description of the (sub)face;
+// for a coarse face, sub selects the fine sub-face.  Used on 2:1 faces.
+template <int D, int NP, class T>
+__device__ __forceinline__ void face_normal(const MeshDev& m, const T* Xi, int cl, const int* cid,
+                                            int k, int s, bool coarse, int sub, int j, T* Nv) {
+  int lf;
+  int P;
+  int Tt[3] = {0, 0, 0};
+  if (coarse) {
+    lf = cl + 1;
+    P = s ? 2 * (cid[k] + 1) : 2 * cid[k];
+    int tt = 0;
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax)
+      if (ax != k) { Tt[ax] = 2 * cid[ax] + ((sub >> tt) & 1); ++tt; }
+  } else {
+    lf = cl;
+    P = s ? cid[k] + 1 : cid[k];
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax)
+      if (ax != k) Tt[ax] = cid[ax];
+  }
+  if (m.per[k] && P >= m.nlev[lf][k]) P -= m.nlev[lf][k];
+  T X[D];
+  int tt = 0;
+  const int j0 = j % NP, j1 = j / NP;
+#pragma unroll
+  for (int ax = 0; ax < D; ++ax) {
+    const T dx = (T)m.dxl[lf][ax];
+    if (ax == k) {
+      X[ax] = dx * (T)P;
+    } else {
+      const int jj = tt == 0 ? j0 : j1;
+      X[ax] = dx * ((T)Tt[ax] + T(0.5) * (T(1) + Xi[jj]));
+      ++tt;
+    }
+  }
+  T Gam[D][D], Jf;
+  metric<D, T>(m, lf, X, Gam, Jf);
+#pragma unroll
+  for (int a = 0; a < D; ++a) Nv[a] = Gam[k][a];
+}
+
+// Terrain table of a cell: (h, h_x, h_y) at every horizontal position its nodes and its own
+// conforming-face points use: NHV volume columns, then the x faces (side, y index), then (3D)
+// the y faces (side, x index).  Face positions are reduced across periodic boundaries.
+template <int D, int NP>
+struct TerTab {
+  static constexpr int NHV = D == 3 ? NP * NP : NP;
+  static constexpr int NHX = D == 3 ? 2 * NP : 2;
+  static constexpr int NHY = D == 3 ? 2 * NP : 0;
+  static constexpr int NH = NHV + NHX + NHY;
+};
+
+// Phases of one workgroup (CPB cells, one thread per node):
+//   P0 own inputs -> trace fields in LDS; terrain table per cell;
+//   P1 volume fluxes and own traces of all faces;
+//   P2 volume contraction, and in the same phase the numerical flux at every point of every
+//      conforming or wall face (neighbour traces gathered along the neighbour's normal lines);
+//   P3 only for faces with a 2:1 neighbour: neighbour traces, sub-face fluxes, restriction
+//      (coarse side) / interpolation (fine side);
+//   P4 lift of all faces along the normal lines, finalize.
 template <int D, int NP, class Op>
 __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const MeshDev m) {
   using C = Cfg<D, NP>;
   using T = typename Op::T;
+  using TT = TerTab<D, NP>;
   constexpr int NL = C::NL, NFP = C::NFP, MS = C::MS, TPC = C::TPC, CPB = C::CPB, NT = C::NT;
+  constexpr int NF = 2 * D;
   constexpr int NTR = Op::NTR, NOUT = Op::NOUT, NIN = Op::NIN;
   constexpr TabLayout TL{NP};
-  constexpr int VOLSZ = CPB * NOUT * D * NL;
-  constexpr int O_TOWN = 0;
-  constexpr int O_NB = O_TOWN + CPB * NTR * NFP;
+  constexpr int NVOL = Op::NVOL;
+  constexpr int VOLSZ = CPB * NVOL * NL;
+  constexpr int O_NB = 0;
   constexpr int O_FL = O_NB + CPB * MS * NTR * NFP;
-  constexpr int O_FR = O_FL + CPB * MS * NOUT * NFP;
-  constexpr int FACESZ = O_FR + CPB * NOUT * NFP;
-  constexpr int SCR = VOLSZ > FACESZ ? VOLSZ : FACESZ;
+  constexpr int SLOWSZ = O_FL + CPB * MS * NOUT * NFP;
+  constexpr int SCR = VOLSZ > SLOWSZ ? VOLSZ : SLOWSZ;
+  constexpr int NH = TT::NH;
 
   __shared__ T sTab[TL.size()];
   __shared__ T sT[CPB * NTR * NL];
   __shared__ T sScr[SCR];
+  __shared__ T sTown[CPB * NF * NTR * NFP];
+  __shared__ T sFr[CPB * NF * NOUT * NFP];
+  __shared__ T sTer[CPB * NH * 3];
   __shared__ int4 sCell[CPB];
-  __shared__ int sKind[CPB][2 * D];
-  __shared__ int4 sNbr[CPB][2 * D];
+  __shared__ int sKind[CPB][NF];
+  __shared__ int4 sNbr[CPB][NF];
   __shared__ T sLam[CPB];
+  __shared__ int sHang[NF];
 
   const int tid = threadIdx.x;
   const int lc = tid / TPC;
   const int node = tid % TPC;
-  const int cell0 = blockIdx.x * CPB;
+  const int cell0 = xcd_block(blockIdx.x, gridDim.x) * CPB;
   const int cell = cell0 + lc;
   const bool active = (node < NL) && (cell < m.ncell);
 
@@ -346,27 +480,63 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
   if constexpr (sizeof(T) == 8) gtab = (const T*)m.tab;
   else gtab = (const T*)m.tabf;
   for (int t = tid; t < TL.size(); t += NT) sTab[t] = gtab[t];
-  if (tid < CPB * 2 * D) {
-    const int c = tid / (2 * D), f = tid % (2 * D);
+  if (tid < NF) sHang[tid] = 0;
+  if (tid < CPB) sCell[tid] = (cell0 + tid) < m.ncell ? m.cell[cell0 + tid] : make_int4(0, 0, 0, 0);
+  __syncthreads();
+  if (tid < CPB * NF) {
+    const int c = tid / NF, f = tid % NF;
     const int cc = cell0 + c;
+    int kind = kWall;
+    int4 nb = make_int4(-1, -1, -1, -1);
     if (cc < m.ncell) {
-      sKind[c][f] = m.fkind[cc * 2 * D + f];
-      sNbr[c][f] = m.fnbr[cc * 2 * D + f];
-    } else {
-      sKind[c][f] = kWall;
-      sNbr[c][f] = make_int4(-1, -1, -1, -1);
+      kind = m.fkind[cc * NF + f];
+      nb = m.fnbr[cc * NF + f];
     }
+    sKind[c][f] = kind;
+    sNbr[c][f] = nb;
+    if (kind == kFine || kind == kCoarse) atomicOr(&sHang[f], 1);
   }
   if (tid < CPB) {
-    const int cc = cell0 + tid;
-    sCell[tid] = cc < m.ncell ? m.cell[cc] : make_int4(0, 0, 0, 0);
-    if constexpr (HasLam<Op>::value) sLam[tid] = cc < m.ncell ? op.lam(cc) : T(0);
+    if constexpr (HasLam<Op>::value) sLam[tid] = (cell0 + tid) < m.ncell ? op.lam(cell0 + tid) : T(0);
   }
-  // own inputs -> trace fields at the nodes
+  // terrain table
+  for (int t = tid; t < CPB * NH; t += NT) {
+    const int c = t / NH, e = t % NH;
+    const int4 ci = sCell[c];
+    const int lev = ci.x;
+    T x, y = 0;
+    const T dx0 = (T)m.dxl[lev][0];
+    const T dx1 = (T)m.dxl[lev][1];
+    const T* xi = &sTab[TL.xi()];
+    if (e < TT::NHV) {
+      const int i0 = e % NP;
+      x = dx0 * ((T)ci.y + T(0.5) * (T(1) + xi[i0]));
+      if (D == 3) y = dx1 * ((T)ci.z + T(0.5) * (T(1) + xi[e / NP]));
+    } else if (e < TT::NHV + TT::NHX) {
+      const int ee = e - TT::NHV;
+      const int sd = ee / (TT::NHX / 2), j = ee % (TT::NHX / 2);
+      int P = sd ? ci.y + 1 : ci.y;
+      if (m.per[0] && P >= m.nlev[lev][0]) P -= m.nlev[lev][0];
+      x = dx0 * (T)P;
+      if (D == 3) y = dx1 * ((T)ci.z + T(0.5) * (T(1) + xi[j]));
+    } else {
+      const int ee = e - TT::NHV - TT::NHX;
+      const int sd = ee / NP, i = ee % NP;
+      int P = sd ? ci.z + 1 : ci.z;
+      if (m.per[1] && P >= m.nlev[lev][1]) P -= m.nlev[lev][1];
+      x = dx0 * ((T)ci.y + T(0.5) * (T(1) + xi[i]));
+      y = dx1 * (T)P;
+    }
+    T h, hx, hy;
+    terrain<T>(m.ter, D, x, y, h, hx, hy);
+    sTer[(c * NH + e) * 3 + 0] = h;
+    sTer[(c * NH + e) * 3 + 1] = hx;
+    sTer[(c * NH + e) * 3 + 2] = hy;
+  }
   T trn[NTR];
   if (active) {
     T in[NIN];
-    op.load((long)cell * NL + node, in);
+    op.load((unsigned)cell * NL + node, in);
     op.transform(in, trn);
 #pragma unroll
     for (int g = 0; g < NTR; ++g) sT[(lc * NTR + g) * NL + node] = trn[g];
@@ -381,74 +551,153 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
   const T* Pi = &sTab[TL.pi()];
   const T* Rw = &sTab[TL.rw()];
 
-  // ---------------------------------------------------------------- volume term
-  T acc[NOUT];
-#pragma unroll
-  for (int o = 0; o < NOUT; ++o) acc[o] = 0;
+  // ---------------------------------------------------------------- P1
   T Jn = 1, wn = 1;
-  const int4 ci = sCell[lc];
-  const int lev = ci.x;
-  const int cidx[3] = {ci.y, ci.z, ci.w};
-  if (active) {
-    T X[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      const int ia = along<D, NP>(node, a);
-      const T dx = (T)(m.L[a] / (double)(m.nb[a] << lev));
-      X[a] = dx * ((T)cidx[a] + T(0.5) * (T(1) + Xi[ia]));
-      wn *= Wt[ia];
-    }
-    T Gam[D][D];
-    metric<D, T>(m, lev, X, Gam, Jn);
-    T G[NOUT][D];
-    op.vol(trn, Gam, G);
-#pragma unroll
-    for (int o = 0; o < NOUT; ++o)
-#pragma unroll
-      for (int k = 0; k < D; ++k) sScr[((lc * NOUT + o) * D + k) * NL + node] = G[o][k];
-  }
-  __syncthreads();
-  if (active) {
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      const int ik = along<D, NP>(node, k);
-      const int ak = tang<D, NP>(node, k);
-#pragma unroll
-      for (int q = 0; q < NP; ++q) {
-        const T dq = Dt[ik * NP + q];
-        const int nq = compose<D, NP>(k, q, ak);
-#pragma unroll
-        for (int o = 0; o < NOUT; ++o) acc[o] += dq * sScr[((lc * NOUT + o) * D + k) * NL + nq];
+  {
+    const int4 ci = sCell[lc];
+    if (active) {
+      const int i0 = along<D, NP>(node, 0);
+      const int iz = along<D, NP>(node, D - 1);
+      int col = i0;
+      wn = Wt[i0] * Wt[iz];
+      if constexpr (D == 3) {
+        const int i1 = along<D, NP>(node, 1);
+        col += NP * i1;
+        wn *= Wt[i1];
       }
+      const T zeta = (T)m.dxl[ci.x][D - 1] * ((T)(D == 3 ? ci.w : ci.z) + T(0.5) * (T(1) + Xi[iz]));
+      const T* te = &sTer[(lc * NH + col) * 3];
+      T Gam[D][D];
+      metric_h<D, T>(m, ci.x, te[0], te[1], te[2], zeta, Gam, Jn);
+      T G[NOUT][D];
+      op.vol(trn, Gam, G);
+#pragma unroll
+      for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+          if (Op::vidx(o, k) >= 0) sScr[(lc * NVOL + Op::vidx(o, k)) * NL + node] = G[o][k];
+    }
+  }
+  for (int t = tid; t < CPB * NF * NFP; t += NT) {
+    const int c = t / (NF * NFP), f = (t / NFP) % NF, j = t % NFP;
+    if (cell0 + c >= m.ncell) continue;
+    const int k = f >> 1, s = f & 1;
+    const int base = compose<D, NP>(k, 0, j);
+    const int str = compose<D, NP>(k, 1, 0);
+#pragma unroll
+    for (int g = 0; g < NTR; ++g) {
+      T v = 0;
+      if (Op::need(k, g)) {
+        const T* src = &sT[(c * NTR + g) * NL + base];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) v += Lb[s * NP + q] * src[q * str];
+      }
+      sTown[((c * NF + f) * NTR + g) * NFP + j] = v;
     }
   }
   __syncthreads();
 
-  // ---------------------------------------------------------------- face terms
-  T* sTown = &sScr[O_TOWN];
-  T* sNb = &sScr[O_NB];
-  T* sFl = &sScr[O_FL];
-  T* sFr = &sScr[O_FR];
-  for (int f = 0; f < 2 * D; ++f) {
-    const int k = f >> 1, s = f & 1;
-    // (a) own traces and neighbour traces
-    for (int t = tid; t < CPB * NFP; t += NT) {
-      const int c = t / NFP, j = t % NFP;
-      if (cell0 + c >= m.ncell) continue;
+  // ---------------------------------------------------------------- P2
+  T acc[NOUT];
 #pragma unroll
-      for (int g = 0; g < NTR; ++g) {
-        T v = 0;
+  for (int o = 0; o < NOUT; ++o) acc[o] = 0;
+  if (active) {
 #pragma unroll
-        for (int q = 0; q < NP; ++q) v += Lb[s * NP + q] * sT[(c * NTR + g) * NL + compose<D, NP>(k, q, j)];
-        sTown[(c * NTR + g) * NFP + j] = v;
+    for (int k = 0; k < D; ++k) {
+      const int ik = along<D, NP>(node, k);
+      const int base = compose<D, NP>(k, 0, tang<D, NP>(node, k));
+      const int str = k == 0 ? 1 : (k == 1 ? NP : NP * NP);
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        const T dq = Dt[ik * NP + q];
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o)
+          if (Op::vidx(o, k) >= 0) acc[o] += dq * sScr[(lc * NVOL + Op::vidx(o, k)) * NL + base + q * str];
       }
     }
+  }
+  for (int t = tid; t < CPB * NF * NFP; t += NT) {
+    const int c = t / (NF * NFP), f = (t / NFP) % NF, j = t % NFP;
+    if (cell0 + c >= m.ncell) continue;
+    const int kind = sKind[c][f];
+    if (kind != kConf && kind != kWall) continue;
+    const int k = f >> 1, s = f & 1;
+    T tm[NTR], tn[NTR];
+#pragma unroll
+    for (int g = 0; g < NTR; ++g) tm[g] = sTown[((c * NF + f) * NTR + g) * NFP + j];
+    T ln = 0;
+    if (kind == kConf) {
+      const int nb = sNbr[c][f].x;
+      const unsigned base = (unsigned)nb * NL + compose<D, NP>(k, 0, j);
+      const int str = compose<D, NP>(k, 1, 0);
+#pragma unroll
+      for (int g = 0; g < NTR; ++g) tn[g] = 0;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        T in[NIN], tr[NTR];
+        op.load_face(base + q * str, k, in);
+        op.transform(in, tr);
+        const T lq = Lb[(1 - s) * NP + q];
+#pragma unroll
+        for (int g = 0; g < NTR; ++g) tn[g] += lq * tr[g];
+      }
+      if constexpr (HasLam<Op>::value) ln = op.lam(nb);
+    } else {
+#pragma unroll
+      for (int g = 0; g < NTR; ++g) tn[g] = tm[g];
+    }
+    // normal from the terrain table
+    const int4 ci = sCell[c];
+    const T* terc = &sTer[c * NH * 3];
+    T Nv[D];
+    const T invH = (T)m.invH;
+    if constexpr (D == 3) {
+      const T a = T(0.5) * (T)m.dxl[ci.x][0], b = T(0.5) * (T)m.dxl[ci.x][1];
+      const T e = T(0.5) * (T)m.dxl[ci.x][2];
+      if (k == 0) {
+        const T h = terc[(TT::NHV + s * NP + (j % NP)) * 3];
+        Nv[0] = b * e * (T(1) - h * invH); Nv[1] = 0; Nv[2] = 0;
+      } else if (k == 1) {
+        const T h = terc[(TT::NHV + TT::NHX + s * NP + (j % NP)) * 3];
+        Nv[0] = 0; Nv[1] = a * e * (T(1) - h * invH); Nv[2] = 0;
+      } else {
+        const T* te = &terc[j * 3];
+        const T zf = (T)m.dxl[ci.x][2] * (T)(s ? ci.w + 1 : ci.w);
+        const T om = T(1) - zf * invH;
+        Nv[0] = -a * b * (te[1] * om); Nv[1] = -a * b * (te[2] * om); Nv[2] = a * b;
+      }
+    } else {
+      const T a = T(0.5) * (T)m.dxl[ci.x][0], e = T(0.5) * (T)m.dxl[ci.x][1];
+      if (k == 0) {
+        const T h = terc[(TT::NHV + s) * 3];
+        Nv[0] = e * (T(1) - h * invH); Nv[1] = 0;
+      } else {
+        const T* te = &terc[j * 3];
+        const T zf = (T)m.dxl[ci.x][1] * (T)(s ? ci.z + 1 : ci.z);
+        const T om = T(1) - zf * invH;
+        Nv[0] = -a * (te[1] * om); Nv[1] = a;
+      }
+    }
+    T lm = 0;
+    if constexpr (HasLam<Op>::value) lm = sLam[c];
+    T phi[NOUT];
+    op.face(kind, s, tm, tn, Nv, lm, ln, phi);
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) sFr[((c * NF + f) * NOUT + o) * NFP + j] = phi[o];
+  }
+  __syncthreads();
+
+  // ---------------------------------------------------------------- P3 (2:1 faces only)
+  T* sNb = &sScr[O_NB];
+  T* sFl = &sScr[O_FL];
+  for (int f = 0; f < NF; ++f) {
+    if (!sHang[f]) continue;  // block-uniform
+    const int k = f >> 1, s = f & 1;
     for (int t = tid; t < CPB * MS * NFP; t += NT) {
       const int c = t / (MS * NFP), sub = (t / NFP) % MS, j = t % NFP;
       if (cell0 + c >= m.ncell) continue;
       const int kind = sKind[c][f];
-      if (kind == kWall) continue;
-      if (kind != kCoarse && sub > 0) continue;
+      if (!(kind == kCoarse || (kind == kFine && sub == 0))) continue;
       const int4 nb4 = sNbr[c][f];
       const int nb = sub == 0 ? nb4.x : sub == 1 ? nb4.y : sub == 2 ? nb4.z : nb4.w;
       T v[NTR];
@@ -457,7 +706,7 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
         T in[NIN], tr[NTR];
-        op.load((long)nb * NL + compose<D, NP>(k, q, j), in);
+        op.load((unsigned)nb * NL + compose<D, NP>(k, q, j), in);
         op.transform(in, tr);
         const T lq = Lb[(1 - s) * NP + q];
 #pragma unroll
@@ -467,123 +716,42 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
       for (int g = 0; g < NTR; ++g) sNb[((c * MS + sub) * NTR + g) * NFP + j] = v[g];
     }
     __syncthreads();
-    // (b) fluxes at the (sub)face points
     for (int t = tid; t < CPB * MS * NFP; t += NT) {
       const int c = t / (MS * NFP), sub = (t / NFP) % MS, j = t % NFP;
       if (cell0 + c >= m.ncell) continue;
       const int kind = sKind[c][f];
-      if (kind != kCoarse && sub > 0) continue;
+      if (!(kind == kCoarse || (kind == kFine && sub == 0))) continue;
       const int4 cc = sCell[c];
-      const int cl = cc.x;
       const int cid[3] = {cc.y, cc.z, cc.w};
       T tm[NTR], tn[NTR];
-      const int j0 = j % NP, j1 = j / NP;
+      const T* Town = &sTown[((c * NF + f) * NTR) * NFP];
       if (kind == kCoarse) {
-        // own (coarse) trace interpolated to the fine sub-face point
         const int c0 = sub & 1, c1 = sub >> 1;
 #pragma unroll
         for (int g = 0; g < NTR; ++g) {
-          const T* Tc = &sTown[(c * NTR + g) * NFP];
-          T v = 0;
-          if constexpr (D == 3) {
-#pragma unroll
-            for (int a1 = 0; a1 < NP; ++a1) {
-              T u = 0;
-#pragma unroll
-              for (int a0 = 0; a0 < NP; ++a0) u += Pi[(c0 * NP + j0) * NP + a0] * Tc[a0 + NP * a1];
-              v += Pi[(c1 * NP + j1) * NP + a1] * u;
-            }
-          } else {
-#pragma unroll
-            for (int a0 = 0; a0 < NP; ++a0) v += Pi[(c0 * NP + j) * NP + a0] * Tc[a0];
-          }
-          tm[g] = v;
+          tm[g] = interp_sub<D, NP, T>(Pi, Town + g * NFP, c0, c1, j);
           tn[g] = sNb[((c * MS + sub) * NTR + g) * NFP + j];
         }
       } else {
-#pragma unroll
-        for (int g = 0; g < NTR; ++g) tm[g] = sTown[(c * NTR + g) * NFP + j];
-        if (kind == kConf) {
-#pragma unroll
-          for (int g = 0; g < NTR; ++g) tn[g] = sNb[((c * MS) * NTR + g) * NFP + j];
-        } else if (kind == kFine) {
-          // neighbour (coarse) trace interpolated to my point; my position in its face
-          int cs[2] = {0, 0};
-          int tt = 0;
-#pragma unroll
-          for (int ax = 0; ax < D; ++ax)
-            if (ax != k) cs[tt++] = cid[ax] & 1;
-#pragma unroll
-          for (int g = 0; g < NTR; ++g) {
-            const T* Tc = &sNb[((c * MS) * NTR + g) * NFP];
-            T v = 0;
-            if constexpr (D == 3) {
-#pragma unroll
-              for (int a1 = 0; a1 < NP; ++a1) {
-                T u = 0;
-#pragma unroll
-                for (int a0 = 0; a0 < NP; ++a0) u += Pi[(cs[0] * NP + j0) * NP + a0] * Tc[a0 + NP * a1];
-                v += Pi[(cs[1] * NP + j1) * NP + a1] * u;
-              }
-            } else {
-#pragma unroll
-              for (int a0 = 0; a0 < NP; ++a0) v += Pi[(cs[0] * NP + j) * NP + a0] * Tc[a0];
-            }
-            tn[g] = v;
-          }
-        } else {
-#pragma unroll
-          for (int g = 0; g < NTR; ++g) tn[g] = tm[g];
-        }
-      }
-      // face geometry from the integer description of the (sub)face
-      int lf;
-      long P;
-      long Tt[3] = {0, 0, 0};
-      if (kind == kCoarse) {
-        lf = cl + 1;
-        P = s ? 2L * (cid[k] + 1) : 2L * cid[k];
+        int cs[2] = {0, 0};
         int tt = 0;
 #pragma unroll
         for (int ax = 0; ax < D; ++ax)
-          if (ax != k) { Tt[ax] = 2L * cid[ax] + ((sub >> tt) & 1); ++tt; }
-      } else {
-        lf = cl;
-        P = s ? (long)cid[k] + 1 : (long)cid[k];
+          if (ax != k) cs[tt++] = cid[ax] & 1;
 #pragma unroll
-        for (int ax = 0; ax < D; ++ax)
-          if (ax != k) Tt[ax] = cid[ax];
-      }
-      const long nk = (long)m.nb[k] << lf;
-      if (m.per[k] && P >= nk) P -= nk;
-      T X[D];
-      {
-        int tt = 0;
-#pragma unroll
-        for (int ax = 0; ax < D; ++ax) {
-          const T dx = (T)(m.L[ax] / (double)(m.nb[ax] << lf));
-          if (ax == k) {
-            X[ax] = dx * (T)P;
-          } else {
-            const int jj = tt == 0 ? j0 : j1;
-            X[ax] = dx * ((T)Tt[ax] + T(0.5) * (T(1) + Xi[jj]));
-            ++tt;
-          }
+        for (int g = 0; g < NTR; ++g) {
+          tm[g] = Town[g * NFP + j];
+          tn[g] = interp_sub<D, NP, T>(Pi, &sNb[((c * MS) * NTR + g) * NFP], cs[0], cs[1], j);
         }
       }
-      T Gam[D][D], Jf;
-      metric<D, T>(m, lf, X, Gam, Jf);
       T Nv[D];
-#pragma unroll
-      for (int a = 0; a < D; ++a) Nv[a] = Gam[k][a];
+      face_normal<D, NP, T>(m, Xi, cc.x, cid, k, s, kind == kCoarse, sub, j, Nv);
       T lm = 0, ln = 0;
       if constexpr (HasLam<Op>::value) {
+        const int4 nb4 = sNbr[c][f];
+        const int nb = sub == 0 ? nb4.x : sub == 1 ? nb4.y : sub == 2 ? nb4.z : nb4.w;
         lm = sLam[c];
-        if (kind != kWall) {
-          const int4 nb4 = sNbr[c][f];
-          const int nb = sub == 0 ? nb4.x : sub == 1 ? nb4.y : sub == 2 ? nb4.z : nb4.w;
-          ln = op.lam(nb);
-        }
+        ln = op.lam(nb);
       }
       T phi[NOUT];
       op.face(kind, s, tm, tn, Nv, lm, ln, phi);
@@ -591,11 +759,11 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
       for (int o = 0; o < NOUT; ++o) sFl[((c * MS + sub) * NOUT + o) * NFP + j] = phi[o];
     }
     __syncthreads();
-    // (c) collect; restrict the sub-face fluxes of a coarse face
     for (int t = tid; t < CPB * NFP; t += NT) {
       const int c = t / NFP, a = t % NFP;
       if (cell0 + c >= m.ncell) continue;
       const int kind = sKind[c][f];
+      if (kind != kCoarse && kind != kFine) continue;
       const int a0 = a % NP, a1 = a / NP;
 #pragma unroll
       for (int o = 0; o < NOUT; ++o) {
@@ -622,22 +790,25 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
         } else {
           v = sFl[((c * MS) * NOUT + o) * NFP + a];
         }
-        sFr[(c * NOUT + o) * NFP + a] = v;
+        sFr[((c * NF + f) * NOUT + o) * NFP + a] = v;
       }
-    }
-    __syncthreads();
-    // (d) lift along the normal lines
-    if (active) {
-      const int ik = along<D, NP>(node, k);
-      const int a = tang<D, NP>(node, k);
-      const T lw = Lbw[s * NP + ik];
-#pragma unroll
-      for (int o = 0; o < NOUT; ++o) acc[o] += lw * sFr[(lc * NOUT + o) * NFP + a];
     }
     __syncthreads();
   }
 
-  if (active) op.finalize((long)cell * NL + node, acc, wn, Jn, trn);
+  // ---------------------------------------------------------------- P4
+  if (active) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int k = f >> 1, s = f & 1;
+      const int ik = along<D, NP>(node, k);
+      const int a = tang<D, NP>(node, k);
+      const T lw = Lbw[s * NP + ik];
+#pragma unroll
+      for (int o = 0; o < NOUT; ++o) acc[o] += lw * sFr[((lc * NF + f) * NOUT + o) * NFP + a];
+    }
+    op.finalize((unsigned)cell * NL + node, acc, wn, Jn, trn);
+  }
 }
 
 template <int D, int NP, class Op>
@@ -663,10 +834,10 @@ int run(const Op& op, const MeshDev& m, hipStream_t s) {
 
 int launch_explicit(const MeshDev& m, int degree, const double* U, double* R, hipStream_t s) {
   if (m.dim == 2) {
-    OpExplicit<2> op{U, R, m.N};
+    OpExplicit<2> op{U, R, (unsigned)m.N};
     DG_DISPATCH(2, degree, return (run<2, NP>(op, m, s)));
   } else {
-    OpExplicit<3> op{U, R, m.N};
+    OpExplicit<3> op{U, R, (unsigned)m.N};
     DG_DISPATCH(3, degree, return (run<3, NP>(op, m, s)));
   }
 }
@@ -674,10 +845,10 @@ int launch_explicit(const MeshDev& m, int degree, const double* U, double* R, hi
 template <class T>
 static int grad_impl(const MeshDev& m, int degree, const GradArgs<T>& a, hipStream_t s) {
   if (m.dim == 2) {
-    OpGrad<2, T> op{a, m.N};
+    OpGrad<2, T> op{a, (unsigned)m.N};
     DG_DISPATCH(2, degree, return (run<2, NP>(op, m, s)));
   } else {
-    OpGrad<3, T> op{a, m.N};
+    OpGrad<3, T> op{a, (unsigned)m.N};
     DG_DISPATCH(3, degree, return (run<3, NP>(op, m, s)));
   }
 }
@@ -685,10 +856,10 @@ static int grad_impl(const MeshDev& m, int degree, const GradArgs<T>& a, hipStre
 template <class T>
 static int div_impl(const MeshDev& m, int degree, const DivArgs<T>& a, hipStream_t s) {
   if (m.dim == 2) {
-    OpDiv<2, T> op{a, m.N};
+    OpDiv<2, T> op{a, (unsigned)m.N};
     DG_DISPATCH(2, degree, return (run<2, NP>(op, m, s)));
   } else {
-    OpDiv<3, T> op{a, m.N};
+    OpDiv<3, T> op{a, (unsigned)m.N};
     DG_DISPATCH(3, degree, return (run<3, NP>(op, m, s)));
   }
 }
@@ -740,7 +911,7 @@ __global__ void k_geometry(const MeshDev m, const Atm at, double* x, double* y, 
   double X[D], w = 1.0;
   for (int a = 0; a < D; ++a) {
     const int ia = along<D, NP>(node, a);
-    const double dx = m.L[a] / (double)(m.nb[a] << ci.x);
+    const double dx = m.dxl[ci.x][a];
     X[a] = dx * (cidx[a] + 0.5 * (1.0 + Xi[ia]));
     w *= Wt[ia];
   }
@@ -748,8 +919,7 @@ __global__ void k_geometry(const MeshDev m, const Atm at, double* x, double* y, 
   metric<D, double>(m, ci.x, X, Gam, J);
   double h, hx, hy;
   terrain<double>(m.ter, D, X[0], D == 3 ? X[1] : 0.0, h, hx, hy);
-  const double H = m.L[D - 1];
-  const double zz = X[D - 1] + h * (1.0 - X[D - 1] / H);
+  const double zz = X[D - 1] + h * (1.0 - X[D - 1] * m.invH);
   if (x) x[gid] = X[0];
   if (y) y[gid] = D == 3 ? X[1] : 0.0;
   if (z) z[gid] = zz;

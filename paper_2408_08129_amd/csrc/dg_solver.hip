@@ -36,8 +36,9 @@ struct Coef { double c[kMaxV]; };
 
 inline int red_grid(long n) {
   long g = (n + kRedThreads - 1) / kRedThreads;
-  return (int)std::max(1L, std::min(1024L, g));
+  return (int)std::max(1L, std::min(2048L, g));
 }
+constexpr int kMaxGrid = 2048;
 
 // --------------------------------------------------------------------------- reduction helpers
 __device__ __forceinline__ double wave_sum(double v) {
@@ -46,19 +47,18 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Block-reduce nv per-thread sums (fixed order) and write part[i * gridDim.x + blockIdx.x].
-__device__ __forceinline__ void block_store(double (&acc)[kMaxV], int nv, double* part) {
-  __shared__ double s[kMaxV][kRedThreads / 64];
+// Block-reduce NV per-thread sums (fixed order) and write part[i * gridDim.x + blockIdx.x].
+template <int NV>
+__device__ __forceinline__ void block_store(const double (&acc)[NV], double* part) {
+  __shared__ double s[NV][kRedThreads / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int i = 0; i < kMaxV; ++i) {
-    if (i < nv) {
-      const double v = wave_sum(acc[i]);
-      if (lane == 0) s[i][wv] = v;
-    }
+  for (int i = 0; i < NV; ++i) {
+    const double v = wave_sum(acc[i]);
+    if (lane == 0) s[i][wv] = v;
   }
   __syncthreads();
-  if (threadIdx.x < nv) {
+  if (threadIdx.x < NV) {
     double t = 0.0;
 #pragma unroll
     for (int k = 0; k < kRedThreads / 64; ++k) t += s[threadIdx.x][k];
@@ -66,90 +66,102 @@ __device__ __forceinline__ void block_store(double (&acc)[kMaxV], int nv, double
   }
 }
 
+// Second stage: one wavefront per reduced value, fixed order.
 __global__ void k_reduce(const double* part, int nv, int G, double* out) {
-  __shared__ double s[kRedThreads];
-  for (int i = 0; i < nv; ++i) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i = wv; i < nv; i += kRedThreads / 64) {
     double t = 0.0;
-    for (int b = threadIdx.x; b < G; b += kRedThreads) t += part[(long)i * G + b];
-    s[threadIdx.x] = t;
-    __syncthreads();
-    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
-      if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) out[i] = s[0];
-    __syncthreads();
+    for (int b = lane; b < G; b += 64) t += part[(long)i * G + b];
+    t = wave_sum(t);
+    if (lane == 0) out[i] = t;
   }
 }
 
-// dots_i = sum_n V_i[n] w[n]
-template <class T>
-__global__ void __launch_bounds__(kRedThreads) k_mdot(const T* __restrict__ V, long ld, int nv,
-                                                      const T* __restrict__ w, double* part, long n) {
-  double acc[kMaxV];
+// dots_i = sum_n V_i[n] w[n] (i < NV) and, as value NV, |w|^2
+template <class T, int NV>
+__global__ void __launch_bounds__(kRedThreads) k_mdot_norm(const T* __restrict__ V, long ld,
+                                                           const T* __restrict__ w, double* part, long n) {
+  double acc[NV + 1];
 #pragma unroll
-  for (int i = 0; i < kMaxV; ++i) acc[i] = 0.0;
+  for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
     const double wv = (double)w[e];
+    T v[NV];
 #pragma unroll
-    for (int i = 0; i < kMaxV; ++i)
-      if (i < nv) acc[i] += (double)V[i * ld + e] * wv;
+    for (int i = 0; i < NV; ++i) v[i] = V[i * ld + e];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] += (double)v[i] * wv;
+    acc[NV] += wv * wv;
   }
-  block_store(acc, nv, part);
-}
-
-// w -= sum_i c_i V_i; then dots_i = sum V_i w
-template <class T>
-__global__ void __launch_bounds__(kRedThreads) k_axpy_mdot(const T* __restrict__ V, long ld, int nv,
-                                                           const Coef c, T* __restrict__ w,
-                                                           double* part, long n) {
-  double acc[kMaxV];
-#pragma unroll
-  for (int i = 0; i < kMaxV; ++i) acc[i] = 0.0;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-    T v[kMaxV];
-    double x = (double)w[e];
-#pragma unroll
-    for (int i = 0; i < kMaxV; ++i)
-      if (i < nv) { v[i] = V[i * ld + e]; x -= c.c[i] * (double)v[i]; }
-    const T xt = (T)x;
-    w[e] = xt;
-#pragma unroll
-    for (int i = 0; i < kMaxV; ++i)
-      if (i < nv) acc[i] += (double)v[i] * (double)xt;
-  }
-  block_store(acc, nv, part);
+  block_store<NV + 1>(acc, part);
 }
 
 // out = w - sum_i c_i V_i; part = |out|^2
-template <class T>
-__global__ void __launch_bounds__(kRedThreads) k_axpy_norm(const T* __restrict__ V, long ld, int nv,
+template <class T, int NV>
+__global__ void __launch_bounds__(kRedThreads) k_axpy_norm(const T* __restrict__ V, long ld,
                                                            const Coef c, const T* __restrict__ w,
                                                            T* __restrict__ out, double* part, long n) {
-  double acc[kMaxV];
-  acc[0] = 0.0;
+  double acc[1] = {0.0};
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    T v[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = V[i * ld + e];
     double x = (double)w[e];
 #pragma unroll
-    for (int i = 0; i < kMaxV; ++i)
-      if (i < nv) x -= c.c[i] * (double)V[i * ld + e];
+    for (int i = 0; i < NV; ++i) x -= c.c[i] * (double)v[i];
     const T xt = (T)x;
     out[e] = xt;
     acc[0] += (double)xt * (double)xt;
   }
-  block_store(acc, 1, part);
+  block_store<1>(acc, part);
 }
 
-// x += f dinv * sum_i c_i V_i  (FP64 accumulation)
-template <class T>
-__global__ void k_update(const T* __restrict__ V, long ld, int nv, const Coef c,
-                         const T* __restrict__ dinv, double* __restrict__ x, long n) {
+// x += dinv * sum_i c_i V_i  (FP64 accumulation)
+template <class T, int NV>
+__global__ void k_update(const T* __restrict__ V, long ld, const Coef c, const T* __restrict__ dinv,
+                         double* __restrict__ x, long n) {
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    T v[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = V[i * ld + e];
     double s = 0.0;
 #pragma unroll
-    for (int i = 0; i < kMaxV; ++i)
-      if (i < nv) s += c.c[i] * (double)V[i * ld + e];
+    for (int i = 0; i < NV; ++i) s += c.c[i] * (double)v[i];
     x[e] += (double)dinv[e] * s;
+  }
+}
+
+#define DG_NV_CASES(X) \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) \
+  X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31)
+
+template <class T>
+void launch_mdot_norm(int nv, int G, hipStream_t s, const T* V, long ld, const T* w, double* part, long n) {
+  switch (nv) {
+#define X(K) case K: hipLaunchKernelGGL((k_mdot_norm<T, K>), dim3(G), dim3(kRedThreads), 0, s, V, ld, w, part, n); break;
+    DG_NV_CASES(X)
+#undef X
+    default: break;
+  }
+}
+template <class T>
+void launch_axpy_norm(int nv, int G, hipStream_t s, const T* V, long ld, const Coef& c, const T* w, T* out,
+                      double* part, long n) {
+  switch (nv) {
+#define X(K) case K: hipLaunchKernelGGL((k_axpy_norm<T, K>), dim3(G), dim3(kRedThreads), 0, s, V, ld, c, w, out, part, n); break;
+    DG_NV_CASES(X)
+#undef X
+    default: break;
+  }
+}
+template <class T>
+void launch_update(int nv, dim3 g, hipStream_t s, const T* V, long ld, const Coef& c, const T* dinv, double* x,
+                   long n) {
+  switch (nv) {
+#define X(K) case K: hipLaunchKernelGGL((k_update<T, K>), g, dim3(256), 0, s, V, ld, c, dinv, x, n); break;
+    DG_NV_CASES(X)
+#undef X
+    default: break;
   }
 }
 
@@ -193,14 +205,20 @@ __global__ void k_pressure_h(const double* __restrict__ U, const double* __restr
   }
 }
 
-// per-cell maximum of c = sqrt((gamma - 1) h)
+// per-cell maximum of c = sqrt((gamma - 1) h): one wavefront per cell
 __global__ void k_lam(const double* __restrict__ h, int nloc, int ncell, double* lam, float* lam32) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (c >= ncell) return;
   double m = 0.0;
-  for (int i = 0; i < nloc; ++i) m = fmax(m, sqrt((kGamma - 1.0) * h[(long)c * nloc + i]));
-  lam[c] = m;
-  if (lam32) lam32[c] = (float)m;
+  for (int i = lane; i < nloc; i += 64) m = fmax(m, h[(long)c * nloc + i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if (lane == 0) {
+    const double v = sqrt((kGamma - 1.0) * m);
+    lam[c] = v;
+    if (lam32) lam32[c] = (float)v;
+  }
 }
 
 template <int D>
@@ -482,9 +500,10 @@ struct dg_ctx {
   double* FI[3] = {nullptr, nullptr, nullptr};
   double *Us = nullptr, *Un = nullptr, *mt = nullptr, *et = nullptr, *mp = nullptr;
   double *pp = nullptr, *h = nullptr, *dinv = nullptr, *q = nullptr, *b = nullptr, *r0 = nullptr;
-  double *delta = nullptr, *w = nullptr, *V = nullptr, *lam = nullptr;
+  double *delta = nullptr, *w = nullptr, *V = nullptr, *lam = nullptr, *z = nullptr;
   // mixed precision
   float *h32 = nullptr, *dinv32 = nullptr, *lam32 = nullptr, *q32 = nullptr, *w32 = nullptr, *V32 = nullptr;
+  float* z32 = nullptr;
   double* rr = nullptr;
   // reductions
   double* part = nullptr;
@@ -588,6 +607,7 @@ void make_plan(dg_ctx* c, Plan& P) {
   P.add((void**)&c->delta, ld * d8);
   P.add((void**)&c->w, ld * d8);
   P.add((void**)&c->lam, nc * d8);
+  P.add((void**)&c->z, ld * d8);
   if (c->opt.precision == DG_FP32_INNER) {
     P.add((void**)&c->V, 1 * ld * d8);  // outer residual work
     P.add((void**)&c->rr, ld * d8);
@@ -596,12 +616,13 @@ void make_plan(dg_ctx* c, Plan& P) {
     P.add((void**)&c->lam32, nc * f4);
     P.add((void**)&c->q32, D * ld * f4);
     P.add((void**)&c->w32, ld * f4);
+    P.add((void**)&c->z32, ld * f4);
     P.add((void**)&c->V32, (size_t)(c->m32 + 1) * ld * f4);
   } else {
     P.add((void**)&c->V, (size_t)(c->m + 1) * ld * d8);
   }
-  P.add((void**)&c->part, (size_t)kMaxV * 1024 * d8);
-  P.add((void**)&c->red, kMaxV * d8);
+  P.add((void**)&c->part, (size_t)(kMaxV + 1) * kMaxGrid * d8);
+  P.add((void**)&c->red, (kMaxV + 1) * d8);
   P.add((void**)&c->flag, 256);
 }
 
@@ -612,6 +633,8 @@ dg_status prepare(dg_ctx* c, const dg_case_desc* desc, int degree, const dg_opti
   else dg_default_options(&c->opt);
   const dg_options& o = c->opt;
   if (o.fp_iters < 1 || o.fp_iters > 8) return fail(c, DG_EINVAL, "fp_iters must be in [1, 8]");
+  if (desc->n_rules > kMaxLev - 1) return fail(c, DG_EINVAL, "at most 8 refinement levels");
+  if (!(desc->oro[1] > 0.0) && desc->orography != DG_ORO_FLAT) return fail(c, DG_EINVAL, "orography width must be positive");
   if (o.gmres_restart < 1 || o.gmres_restart > kMaxV - 1) return fail(c, DG_EINVAL, "gmres_restart must be in [1, 31]");
   if (o.inner_restart < 1 || o.inner_restart > kMaxV - 1) return fail(c, DG_EINVAL, "inner_restart must be in [1, 31]");
   if (o.precision != DG_FP64 && o.precision != DG_FP32_INNER) return fail(c, DG_EINVAL, "bad precision");
@@ -642,14 +665,16 @@ struct ApplyCtx {
 template <class T>
 int apply_A(dg_ctx* c, double dta, const T* v, const T* dinv, T scale, T* w);
 
+// Pass 1 writes w = h M^{-1} B p and z = p at the nodes; pass 2 takes C(w) and the penalty and
+// mass terms of z.
 template <>
 int apply_A<double>(dg_ctx* c, double dta, const double* v, const double* dinv, double scale, double* w) {
-  GradArgs<double> g{v, dinv, scale, c->q};
+  GradArgs<double> g{v, dinv, scale, c->q, c->h, c->z};
   int rg;
   TIMED(1, rg = launch_grad64(c->md, c->degree, g, c->stream));
   if (rg) return -1;
   const double beta = c->opt.penalty_beta;
-  DivArgs<double> a{c->q, c->h, v, dinv, scale, c->lam, -dta * dta,
+  DivArgs<double> a{c->q, nullptr, c->z, nullptr, 1.0, c->lam, -dta * dta,
                     dta * beta / (2.0 * (kGamma - 1.0)), 1.0 / (kGamma - 1.0), 1, w};
   int rd;
   TIMED(2, rd = launch_div64(c->md, c->degree, a, c->stream));
@@ -657,12 +682,12 @@ int apply_A<double>(dg_ctx* c, double dta, const double* v, const double* dinv, 
 }
 template <>
 int apply_A<float>(dg_ctx* c, double dta, const float* v, const float* dinv, float scale, float* w) {
-  GradArgs<float> g{v, dinv, scale, c->q32};
+  GradArgs<float> g{v, dinv, scale, c->q32, c->h32, c->z32};
   int rg;
   TIMED(1, rg = launch_grad32(c->md, c->degree, g, c->stream));
   if (rg) return -1;
   const double beta = c->opt.penalty_beta;
-  DivArgs<float> a{c->q32, c->h32, v, dinv, scale, c->lam32, (float)(-dta * dta),
+  DivArgs<float> a{c->q32, nullptr, c->z32, nullptr, 1.0f, c->lam32, (float)(-dta * dta),
                    (float)(dta * beta / (2.0 * (kGamma - 1.0))), (float)(1.0 / (kGamma - 1.0)), 1, w};
   int rd;
   TIMED(2, rd = launch_div32(c->md, c->degree, a, c->stream));
@@ -681,12 +706,16 @@ dg_status reduce_to_host(dg_ctx* c, int nv, int G, double* out) {
 template <class T>
 dg_status dot(dg_ctx* c, const T* a, const T* b, double* out) {
   const int G = red_grid(c->N);
-  TIMED(3, hipLaunchKernelGGL((k_mdot<T>), dim3(G), dim3(kRedThreads), 0, c->stream, a, c->ld, 1, b, c->part, c->N));
-  return reduce_to_host(c, 1, G, out);
+  TIMED(3, launch_mdot_norm<T>(1, G, c->stream, a, c->ld, b, c->part, c->N));
+  double r[2];
+  const dg_status st = reduce_to_host(c, 2, G, r);
+  *out = r[0];
+  return st;
 }
 
 struct CycleResult {
   int its = 0;
+  int reorth = 0;
   double res = 0.0;
   bool converged = false;
 };
@@ -705,32 +734,40 @@ dg_status gmres_cycle(dg_ctx* c, double dta, T* V, T* w, const T* dinv, int m, d
   int jd = 0;
   cr = CycleResult{};
   Coef cf{};
-  double dots[kMaxV];
+  double dots[kMaxV + 1];
   for (int j = 0; j < m; ++j) {
     if (apply_A<T>(c, dta, V + (size_t)j * ld, dinv, (T)s[j], w)) return fail(c, DG_EDEVICE, "operator launch failed");
     const int nv = j + 1;
-    // pass 1: classical Gram-Schmidt coefficients
-    TIMED(3, hipLaunchKernelGGL((k_mdot<T>), dim3(G), dim3(kRedThreads), 0, c->stream, V, ld, nv, (const T*)w, c->part, N));
-    dg_status st = reduce_to_host(c, nv, G, dots);
+    T* vnext = V + (size_t)(j + 1) * ld;
+    // classical Gram-Schmidt coefficients and |w|^2 in one pass
+    TIMED(3, launch_mdot_norm<T>(nv, G, c->stream, V, ld, (const T*)w, c->part, N));
+    dg_status st = reduce_to_host(c, nv + 1, G, dots);
     if (st) return st;
+    const double nw2 = dots[nv];
     for (int i = 0; i < nv; ++i) {
       H[(size_t)i * m + j] = dots[i] * s[i];
       cf.c[i] = H[(size_t)i * m + j] * s[i];
     }
-    // pass 2: subtract and re-orthogonalise (CGS2)
-    TIMED(3, hipLaunchKernelGGL((k_axpy_mdot<T>), dim3(G), dim3(kRedThreads), 0, c->stream, V, ld, nv, cf, w, c->part, N));
-    st = reduce_to_host(c, nv, G, dots);
-    if (st) return st;
-    for (int i = 0; i < nv; ++i) {
-      const double h2 = dots[i] * s[i];
-      H[(size_t)i * m + j] += h2;
-      cf.c[i] = h2 * s[i];
-    }
-    TIMED(3, hipLaunchKernelGGL((k_axpy_norm<T>), dim3(G), dim3(kRedThreads), 0, c->stream, V, ld, nv, cf,
-                       (const T*)w, V + (size_t)(j + 1) * ld, c->part, N));
+    TIMED(3, launch_axpy_norm<T>(nv, G, c->stream, V, ld, cf, (const T*)w, vnext, c->part, N));
     double nrm2;
     st = reduce_to_host(c, 1, G, &nrm2);
     if (st) return st;
+    // DGKS criterion: re-orthogonalise once when the projection removed more than half of |w|^2
+    if (nrm2 < 0.5 * nw2) {
+      TIMED(3, launch_mdot_norm<T>(nv, G, c->stream, V, ld, (const T*)vnext, c->part, N));
+      st = reduce_to_host(c, nv + 1, G, dots);
+      if (st) return st;
+      for (int i = 0; i < nv; ++i) {
+        const double h2 = dots[i] * s[i];
+        H[(size_t)i * m + j] += h2;
+        cf.c[i] = h2 * s[i];
+      }
+      TIMED(3, launch_axpy_norm<T>(nv, G, c->stream, V, ld, cf, (const T*)vnext, w, c->part, N));
+      st = reduce_to_host(c, 1, G, &nrm2);
+      if (st) return st;
+      HIPCHK(hipMemcpyAsync(vnext, w, N * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+      cr.reorth++;
+    }
     const double nrm = std::sqrt(nrm2);
     if (!std::isfinite(nrm)) return fail(c, DG_ENAN, "non-finite value in the Krylov solve");
     H[(size_t)(j + 1) * m + j] = nrm;
@@ -761,7 +798,7 @@ dg_status gmres_cycle(dg_ctx* c, double dta, T* V, T* w, const T* dinv, int m, d
     y[i] = t / H[(size_t)i * m + i];
   }
   for (int i = 0; i < jd; ++i) cf.c[i] = xscale * y[i] * s[i];
-  TIMED(3, hipLaunchKernelGGL((k_update<T>), pw_grid(N), dim3(256), 0, c->stream, (const T*)V, ld, jd, cf, dinv, x, N));
+  TIMED(3, launch_update<T>(jd, pw_grid(N), c->stream, (const T*)V, ld, cf, dinv, x, N));
   cr.res = res;
   cr.converged = res <= tol;
   return DG_OK;
@@ -861,9 +898,9 @@ dg_status implicit_term(dg_ctx* c, const double* U, double* F) {
     TIMED(4, hipLaunchKernelGGL((k_pressure_h<2>), pw_grid(N), dim3(256), 0, c->stream, U, c->pbar, N, ld, c->pp, c->h));
   else
     TIMED(4, hipLaunchKernelGGL((k_pressure_h<3>), pw_grid(N), dim3(256), 0, c->stream, U, c->pbar, N, ld, c->pp, c->h));
-  TIMED(4, hipLaunchKernelGGL(k_lam, dim3((c->hm.ncell + 255) / 256), dim3(256), 0, c->stream, c->h, c->NL,
+  TIMED(4, hipLaunchKernelGGL(k_lam, dim3((c->hm.ncell + 3) / 4), dim3(256), 0, c->stream, c->h, c->NL,
                      c->hm.ncell, c->lam, (float*)nullptr));
-  GradArgs<double> g{c->pp, nullptr, 1.0, c->q};
+  GradArgs<double> g{c->pp, nullptr, 1.0, c->q, nullptr, nullptr};
   int rg;
   TIMED(1, rg = launch_grad64(c->md, c->degree, g, c->stream));
   LCHK(rg);
@@ -912,7 +949,7 @@ dg_status step_impl(dg_ctx* c, double* U, double dt, dg_step_stats* stats) {
                          c->degree + 1, dta, N, c->h, c->dinv,
                          c->opt.precision == DG_FP32_INNER ? c->h32 : (float*)nullptr,
                          c->opt.precision == DG_FP32_INNER ? c->dinv32 : (float*)nullptr));
-      TIMED(4, hipLaunchKernelGGL(k_lam, dim3((c->hm.ncell + 255) / 256), dim3(256), 0, s, c->h, c->NL,
+      TIMED(4, hipLaunchKernelGGL(k_lam, dim3((c->hm.ncell + 3) / 4), dim3(256), 0, s, c->h, c->NL,
                          c->hm.ncell, c->lam,
                          c->opt.precision == DG_FP32_INNER ? c->lam32 : (float*)nullptr));
       // b = -dta C(h m') + M (e~ - rho k - pbar/(gamma-1))
@@ -938,7 +975,7 @@ dg_status step_impl(dg_ctx* c, double* U, double dt, dg_step_stats* stats) {
         return rc;
       }
       TIMED(4, hipLaunchKernelGGL(k_add, pg, bs, 0, s, c->pp, c->delta, N));
-      GradArgs<double> gq{c->pp, nullptr, 1.0, c->q};
+      GradArgs<double> gq{c->pp, nullptr, 1.0, c->q, nullptr, nullptr};
       int rg;
       TIMED(1, rg = launch_grad64(c->md, c->degree, gq, s));
       LCHK(rg);
@@ -1095,7 +1132,14 @@ dg_status dg_setup(const dg_case_desc* desc, int32_t degree, const dg_options* o
     md.nb[a] = M.nb[a];
     md.per[a] = M.per[a];
   }
-  md.ter = Terrain{c->desc.orography, c->desc.oro[0], c->desc.oro[1], c->desc.oro[2], c->desc.oro[3]};
+  md.ter = Terrain{c->desc.orography, c->desc.oro[0], c->desc.oro[1], c->desc.oro[2], c->desc.oro[3],
+                   1.0 / (c->desc.oro[1] * c->desc.oro[1])};
+  md.invH = 1.0 / M.L[c->D - 1];
+  for (int l = 0; l < kMaxLev; ++l)
+    for (int a = 0; a < 3; ++a) {
+      md.nlev[l][a] = M.nb[a] << l;
+      md.dxl[l][a] = M.L[a] / (double)(M.nb[a] << l);
+    }
   {
     MeshDev g = md;
     g.N = c->N;  // geometry kernel iterates over N nodes
@@ -1198,7 +1242,7 @@ dg_status dg_apply_helmholtz(dg_ctx* c, double dta, const void* h, const void* p
   const long N = c->N;
   if (prec == DG_FP64) {
     HIPCHK(hipMemcpyAsync(c->h, h, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    hipLaunchKernelGGL(k_lam, dim3((c->hm.ncell + 255) / 256), dim3(256), 0, c->stream, c->h, c->NL,
+    hipLaunchKernelGGL(k_lam, dim3((c->hm.ncell + 3) / 4), dim3(256), 0, c->stream, c->h, c->NL,
                        c->hm.ncell, c->lam, (float*)nullptr);
     if (apply_A<double>(c, dta, (const double*)p, nullptr, 1.0, (double*)Ap)) return fail(c, DG_EDEVICE, "launch failed");
     return DG_OK;
@@ -1209,7 +1253,7 @@ dg_status dg_apply_helmholtz(dg_ctx* c, double dta, const void* h, const void* p
     // h in FP32: copy, and widen to FP64 for the per-cell sound speed
     HIPCHK(hipMemcpyAsync(c->h32, h, N * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
     hipLaunchKernelGGL(k_widen, pw_grid(N), dim3(256), 0, c->stream, (const float*)c->h32, N, c->h);
-    hipLaunchKernelGGL(k_lam, dim3((c->hm.ncell + 255) / 256), dim3(256), 0, c->stream, c->h, c->NL,
+    hipLaunchKernelGGL(k_lam, dim3((c->hm.ncell + 3) / 4), dim3(256), 0, c->stream, c->h, c->NL,
                        c->hm.ncell, c->lam, c->lam32);
     if (apply_A<float>(c, dta, (const float*)p, nullptr, 1.0f, (float*)Ap)) return fail(c, DG_EDEVICE, "launch failed");
     return DG_OK;
