@@ -110,10 +110,14 @@ typedef struct {
   double gmres_relres[2][8];    /* final ||r|| / ||r0|| */
   double t_kernel_ms[8];        /* with dg_set_timing on: device time summed per kernel class,
                                    from HIP events around every launch on the context's stream:
-                                   0 explicit residual, 1 weak gradient M^-1 B, 2 weak divergence
-                                   with penalty (Helmholtz pass 2, right-hand side, implicit term),
-                                   3 Krylov orthogonalisation and update, 4 pointwise vector work */
+                                   0 explicit residual, 1 weak gradient M^-1 B (Helmholtz pass 1),
+                                   2 weak divergence with penalty (Helmholtz pass 2, right-hand
+                                   side, implicit term), 3 Gram-Schmidt dot products (k_mdot_norm),
+                                   4 pointwise vector work, 5 Gram-Schmidt update (k_axpy_norm),
+                                   6 Krylov solution update and final reductions */
   int32_t n_kernel[8];          /* launches per class (timing on) */
+  double bytes_kernel[8];       /* algorithmic HBM bytes per class (timing on): the arrays each
+                                   launch must read and write once, as the kernels are designed */
   double t_step_ms;             /* host wall time of the step (timing on) */
   double mass, max_w;           /* diagnostics of the new state */
 } dg_step_stats;
@@ -177,11 +181,13 @@ dg_status dg_apply_helmholtz(dg_ctx* ctx, double dt_a, const void* h_dev, const 
 /* One IMEX-RK2 step of size dt, in place.  On any error U is left unchanged.  stats may be NULL. */
 dg_status imex_rk2_step(dg_ctx* ctx, double* U_dev, double dt, dg_step_stats* stats);
 
-/* One step for each of n contexts (ensemble members of any sizes), their work interleaved on
- * the device; stats: array of n or NULL.  Returns the first error; members that failed keep
- * their state, the others advance. */
+/* One step for each of n contexts (ensemble members of any sizes): each member runs on its own
+ * context stream from its own host thread, so their kernels overlap on the device.  stats: array
+ * of n or NULL (t_step_ms = time from the call to the member's completion); status: array of n or
+ * NULL (per-member result).  Returns DG_OK or the first member error; a member that fails keeps its
+ * state, the others advance. */
 dg_status imex_rk2_step_batched(dg_ctx* const* ctxs, double* const* U_devs, const double* dts,
-                                int32_t n, dg_step_stats* stats);
+                                int32_t n, dg_step_stats* stats, int32_t* status);
 
 /* Total mass sum(w J rho) and max |w| (host outputs). */
 dg_status dg_diagnostics(dg_ctx* ctx, const double* U_dev, double* mass, double* max_w);

@@ -56,10 +56,12 @@ class dg_options(ctypes.Structure):
 class dg_step_stats(ctypes.Structure):
     _fields_ = [("gmres_iters", (ctypes.c_int32 * 8) * 2), ("outer_iters", (ctypes.c_int32 * 8) * 2),
                 ("gmres_relres", (ctypes.c_double * 8) * 2), ("t_kernel_ms", ctypes.c_double * 8),
-                ("n_kernel", ctypes.c_int32 * 8), ("t_step_ms", ctypes.c_double),
+                ("n_kernel", ctypes.c_int32 * 8), ("bytes_kernel", ctypes.c_double * 8),
+                ("t_step_ms", ctypes.c_double),
                 ("mass", ctypes.c_double), ("max_w", ctypes.c_double)]
 
-    KERNEL_CLASSES = ("explicit_residual", "weak_gradient", "weak_divergence", "krylov", "pointwise")
+    KERNEL_CLASSES = ("explicit_residual", "weak_gradient", "weak_divergence", "gs_dots",
+                      "pointwise", "gs_update", "krylov_other")
 
     def as_dict(self, fp_iters: int = 8) -> dict:
         return {
@@ -68,6 +70,7 @@ class dg_step_stats(ctypes.Structure):
             "gmres_relres": [[self.gmres_relres[s][l] for l in range(fp_iters)] for s in range(2)],
             "t_kernel_ms": {k: self.t_kernel_ms[i] for i, k in enumerate(self.KERNEL_CLASSES)},
             "n_kernel": {k: self.n_kernel[i] for i, k in enumerate(self.KERNEL_CLASSES)},
+            "bytes_kernel": {k: self.bytes_kernel[i] for i, k in enumerate(self.KERNEL_CLASSES)},
             "t_step_ms": self.t_step_ms, "mass": self.mass, "max_w": self.max_w,
         }
 
@@ -81,14 +84,35 @@ class DGError(RuntimeError):
 _lib = None
 
 
+def _hip_runtimes() -> set:
+    paths = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line:
+                    paths.add(line.split()[-1])
+    except OSError:
+        pass
+    return paths
+
+
 def lib():
-    """The loaded shared library; raises if it has not been built."""
+    """The loaded shared library; raises if it has not been built.
+
+    torch ships its own HIP runtime under the same soname as the system one the library is linked
+    against.  torch is imported first so that the library binds to torch's runtime; loading the
+    library first would map two HIP/HSA runtimes into the process, which crashes at the first
+    device call.  The load is checked for a single runtime."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("libimexdg.so is not built (run paper_2408_08129_amd/build.py); "
                               "there is no CPU fallback")
+        import torch  # noqa: F401  (binds the HIP runtime first)
         L = ctypes.CDLL(LIB_PATH)
+        rts = _hip_runtimes()
+        if len(rts) > 1:
+            raise ImportError("more than one HIP runtime is loaded in this process: %s" % sorted(rts))
         vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         L.dg_default_options.argtypes = [ctypes.POINTER(dg_options)]
         L.dg_default_options.restype = None
@@ -109,7 +133,8 @@ def lib():
         L.dg_apply_helmholtz.argtypes = [vp, d, vp, vp, vp, i32]
         L.imex_rk2_step.argtypes = [vp, vp, d, ctypes.POINTER(dg_step_stats)]
         L.imex_rk2_step_batched.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp),
-                                            ctypes.POINTER(d), i32, ctypes.POINTER(dg_step_stats)]
+                                            ctypes.POINTER(d), i32, ctypes.POINTER(dg_step_stats),
+                                            ctypes.POINTER(i32)]
         L.dg_diagnostics.argtypes = [vp, vp, ctypes.POINTER(d), ctypes.POINTER(d)]
         L.dg_last_error.argtypes = []
         L.dg_last_error.restype = ctypes.c_char_p
@@ -232,14 +257,18 @@ def imex_rk2_step(ctx: int, U, dt: float) -> dg_step_stats:
     return st
 
 
-def imex_rk2_step_batched(ctxs, Us, dts) -> list:
+def imex_rk2_step_batched(ctxs, Us, dts, raise_on_error: bool = True):
+    """One step for every member; returns (stats list, status list)."""
     n = len(ctxs)
     C = (ctypes.c_void_p * n)(*ctxs)
     P = (ctypes.c_void_p * n)(*[u.data_ptr() for u in Us])
     T = (ctypes.c_double * n)(*[float(x) for x in dts])
     S = (dg_step_stats * n)()
-    _check(lib().imex_rk2_step_batched(C, P, T, n, S))
-    return list(S)
+    R = (ctypes.c_int32 * n)()
+    rc = lib().imex_rk2_step_batched(C, P, T, n, S, R)
+    if raise_on_error:
+        _check(rc)
+    return list(S), list(R)
 
 
 def dg_diagnostics(ctx: int, U):

@@ -515,6 +515,7 @@ struct dg_ctx {
   std::vector<hipEvent_t> ev;
   std::vector<int> ev_cls;
   int ev_n = 0;
+  double kbytes[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -531,7 +532,8 @@ constexpr int kEvPool = 8192;
 struct Timed {
   dg_ctx* c;
   int slot = -1;
-  Timed(dg_ctx* c_, int cls) : c(c_) {
+  Timed(dg_ctx* c_, int cls, double bytes = 0.0) : c(c_) {
+    if (c->timing) c->kbytes[cls] += bytes;
     if (c->timing && c->ev_n < kEvPool) {
       slot = c->ev_n++;
       c->ev_cls[slot] = cls;
@@ -546,6 +548,12 @@ struct Timed {
   do {                   \
     Timed t_(c, cls);    \
     stmt;                \
+  } while (0)
+// with the algorithmic bytes of the launch
+#define TIMEDB(cls, bytes, stmt) \
+  do {                           \
+    Timed t_(c, cls, bytes);     \
+    stmt;                        \
   } while (0)
 
 #define HIPCHK(call)                                                              \
@@ -670,33 +678,37 @@ int apply_A(dg_ctx* c, double dta, const T* v, const T* dinv, T scale, T* w);
 template <>
 int apply_A<double>(dg_ctx* c, double dta, const double* v, const double* dinv, double scale, double* w) {
   GradArgs<double> g{v, dinv, scale, c->q, c->h, c->z};
+  const double nb8 = 8.0 * c->N;
   int rg;
-  TIMED(1, rg = launch_grad64(c->md, c->degree, g, c->stream));
+  // pass 1: v, dinv (if any), h in; w (d fields) and z out
+  TIMEDB(1, nb8 * ((dinv ? 2 : 1) + 1 + c->D + 1), rg = launch_grad64(c->md, c->degree, g, c->stream));
   if (rg) return -1;
   const double beta = c->opt.penalty_beta;
   DivArgs<double> a{c->q, nullptr, c->z, nullptr, 1.0, c->lam, -dta * dta,
                     dta * beta / (2.0 * (kGamma - 1.0)), 1.0 / (kGamma - 1.0), 1, w};
   int rd;
-  TIMED(2, rd = launch_div64(c->md, c->degree, a, c->stream));
+  // pass 2: w (d fields), z in; A p out
+  TIMEDB(2, nb8 * (c->D + 2), rd = launch_div64(c->md, c->degree, a, c->stream));
   return rd;
 }
 template <>
 int apply_A<float>(dg_ctx* c, double dta, const float* v, const float* dinv, float scale, float* w) {
   GradArgs<float> g{v, dinv, scale, c->q32, c->h32, c->z32};
+  const double nb4 = 4.0 * c->N;
   int rg;
-  TIMED(1, rg = launch_grad32(c->md, c->degree, g, c->stream));
+  TIMEDB(1, nb4 * ((dinv ? 2 : 1) + 1 + c->D + 1), rg = launch_grad32(c->md, c->degree, g, c->stream));
   if (rg) return -1;
   const double beta = c->opt.penalty_beta;
   DivArgs<float> a{c->q32, nullptr, c->z32, nullptr, 1.0f, c->lam32, (float)(-dta * dta),
                    (float)(dta * beta / (2.0 * (kGamma - 1.0))), (float)(1.0 / (kGamma - 1.0)), 1, w};
   int rd;
-  TIMED(2, rd = launch_div32(c->md, c->degree, a, c->stream));
+  TIMEDB(2, nb4 * (c->D + 2), rd = launch_div32(c->md, c->degree, a, c->stream));
   return rd;
 }
 
 // reduce nv partial sums to host
 dg_status reduce_to_host(dg_ctx* c, int nv, int G, double* out) {
-  TIMED(3, hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, c->stream, c->part, nv, G, c->red));
+  TIMED(6, hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, c->stream, c->part, nv, G, c->red));
   HIPCHK(hipMemcpyAsync(c->hred, c->red, nv * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   memcpy(out, c->hred, nv * sizeof(double));
@@ -706,7 +718,7 @@ dg_status reduce_to_host(dg_ctx* c, int nv, int G, double* out) {
 template <class T>
 dg_status dot(dg_ctx* c, const T* a, const T* b, double* out) {
   const int G = red_grid(c->N);
-  TIMED(3, launch_mdot_norm<T>(1, G, c->stream, a, c->ld, b, c->part, c->N));
+  TIMEDB(3, 2.0 * sizeof(T) * c->N, launch_mdot_norm<T>(1, G, c->stream, a, c->ld, b, c->part, c->N));
   double r[2];
   const dg_status st = reduce_to_host(c, 2, G, r);
   *out = r[0];
@@ -740,7 +752,7 @@ dg_status gmres_cycle(dg_ctx* c, double dta, T* V, T* w, const T* dinv, int m, d
     const int nv = j + 1;
     T* vnext = V + (size_t)(j + 1) * ld;
     // classical Gram-Schmidt coefficients and |w|^2 in one pass
-    TIMED(3, launch_mdot_norm<T>(nv, G, c->stream, V, ld, (const T*)w, c->part, N));
+    TIMEDB(3, (nv + 1.0) * sizeof(T) * N, launch_mdot_norm<T>(nv, G, c->stream, V, ld, (const T*)w, c->part, N));
     dg_status st = reduce_to_host(c, nv + 1, G, dots);
     if (st) return st;
     const double nw2 = dots[nv];
@@ -748,13 +760,13 @@ dg_status gmres_cycle(dg_ctx* c, double dta, T* V, T* w, const T* dinv, int m, d
       H[(size_t)i * m + j] = dots[i] * s[i];
       cf.c[i] = H[(size_t)i * m + j] * s[i];
     }
-    TIMED(3, launch_axpy_norm<T>(nv, G, c->stream, V, ld, cf, (const T*)w, vnext, c->part, N));
+    TIMEDB(5, (nv + 2.0) * sizeof(T) * N, launch_axpy_norm<T>(nv, G, c->stream, V, ld, cf, (const T*)w, vnext, c->part, N));
     double nrm2;
     st = reduce_to_host(c, 1, G, &nrm2);
     if (st) return st;
     // DGKS criterion: re-orthogonalise once when the projection removed more than half of |w|^2
     if (nrm2 < 0.5 * nw2) {
-      TIMED(3, launch_mdot_norm<T>(nv, G, c->stream, V, ld, (const T*)vnext, c->part, N));
+      TIMEDB(3, (nv + 1.0) * sizeof(T) * N, launch_mdot_norm<T>(nv, G, c->stream, V, ld, (const T*)vnext, c->part, N));
       st = reduce_to_host(c, nv + 1, G, dots);
       if (st) return st;
       for (int i = 0; i < nv; ++i) {
@@ -762,7 +774,7 @@ dg_status gmres_cycle(dg_ctx* c, double dta, T* V, T* w, const T* dinv, int m, d
         H[(size_t)i * m + j] += h2;
         cf.c[i] = h2 * s[i];
       }
-      TIMED(3, launch_axpy_norm<T>(nv, G, c->stream, V, ld, cf, (const T*)vnext, w, c->part, N));
+      TIMEDB(5, (nv + 2.0) * sizeof(T) * N, launch_axpy_norm<T>(nv, G, c->stream, V, ld, cf, (const T*)vnext, w, c->part, N));
       st = reduce_to_host(c, 1, G, &nrm2);
       if (st) return st;
       HIPCHK(hipMemcpyAsync(vnext, w, N * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
@@ -798,7 +810,7 @@ dg_status gmres_cycle(dg_ctx* c, double dta, T* V, T* w, const T* dinv, int m, d
     y[i] = t / H[(size_t)i * m + i];
   }
   for (int i = 0; i < jd; ++i) cf.c[i] = xscale * y[i] * s[i];
-  TIMED(3, launch_update<T>(jd, pw_grid(N), c->stream, (const T*)V, ld, cf, dinv, x, N));
+  TIMEDB(6, (jd + 1.0) * sizeof(T) * N + 16.0 * N, launch_update<T>(jd, pw_grid(N), c->stream, (const T*)V, ld, cf, dinv, x, N));
   cr.res = res;
   cr.converged = res <= tol;
   return DG_OK;
@@ -885,7 +897,7 @@ dg_status solve_mixed(dg_ctx* c, double dta, int& its, int& outer, double& relre
 // ----------------------------------------------------------------------------------- operators
 dg_status explicit_residual(dg_ctx* c, const double* U, double* R) {
   int re;
-  TIMED(0, re = launch_explicit(c->md, c->degree, U, R, c->stream));
+  TIMEDB(0, 16.0 * c->F * c->N, re = launch_explicit(c->md, c->degree, U, R, c->stream));
   LCHK(re);
   return DG_OK;
 }
@@ -930,6 +942,7 @@ dg_status step_impl(dg_ctx* c, double* U, double dt, dg_step_stats* stats) {
   dg_step_stats st{};
   dg_status rc;
   c->ev_n = 0;
+  for (double& b : c->kbytes) b = 0.0;
   const auto t0 = std::chrono::steady_clock::now();
 
   if ((rc = explicit_residual(c, U, c->FE[0]))) return rc;
@@ -1014,6 +1027,7 @@ dg_status step_impl(dg_ctx* c, double* U, double dt, dg_step_stats* stats) {
         st.t_kernel_ms[c->ev_cls[e]] += ms;
         st.n_kernel[c->ev_cls[e]] += 1;
       }
+      for (int k = 0; k < 8; ++k) st.bytes_kernel[k] = c->kbytes[k];
     }
     *stats = st;
   }
@@ -1268,24 +1282,31 @@ dg_status imex_rk2_step(dg_ctx* c, double* U, double dt, dg_step_stats* stats) {
 }
 
 dg_status imex_rk2_step_batched(dg_ctx* const* ctxs, double* const* Us, const double* dts, int32_t n,
-                                dg_step_stats* stats) {
+                                dg_step_stats* stats, int32_t* status) {
   if (n < 0 || (n > 0 && (!ctxs || !Us || !dts))) return fail(nullptr, DG_EINVAL, "bad batch");
   std::vector<dg_status> rc(n, DG_OK);
   std::vector<std::string> msg(n);
   std::vector<std::thread> th;
   th.reserve(n);
+  const auto t0 = std::chrono::steady_clock::now();
   for (int i = 0; i < n; ++i)
     th.emplace_back([&, i]() {
       rc[i] = imex_rk2_step(ctxs[i], Us[i], dts[i], stats ? &stats[i] : nullptr);
       if (rc[i]) msg[i] = g_last_error;
+      if (ctxs[i]) (void)hipStreamSynchronize(ctxs[i]->stream);
+      if (stats)
+        stats[i].t_step_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     });
   for (auto& t : th) t.join();
-  for (int i = 0; i < n; ++i)
-    if (rc[i]) {
+  dg_status first = DG_OK;
+  for (int i = 0; i < n; ++i) {
+    if (status) status[i] = rc[i];
+    if (rc[i] && first == DG_OK) {
+      first = rc[i];
       g_last_error = "member " + std::to_string(i) + ": " + msg[i];
-      return rc[i];
     }
-  return DG_OK;
+  }
+  return first;
 }
 
 dg_status dg_diagnostics(dg_ctx* c, const double* U, double* mass, double* max_w) {

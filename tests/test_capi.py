@@ -100,3 +100,14 @@ def test_footprint_scales_with_size_and_precision():
     big = cases.WORKLOADS["box3d_r4_ridge_large"]
     bl = P.dg_footprint(C.product_case(big), 4, P.options(precision=P.DG_FP32_INNER))
     assert bl < 288e9  # fits one MI355X
+
+
+def test_single_hip_runtime_after_loading():
+    """The binding binds the library to torch's HIP runtime: one libamdhip64 is mapped."""
+    import subprocess
+    import sys
+    code = ("import paper_2408_08129_amd as P; P.dg_mesh_info; P.lib(); "
+            "print(len(P._hip_runtimes()))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
