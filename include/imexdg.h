@@ -48,6 +48,7 @@ typedef enum {
 } dg_status;
 
 typedef enum { DG_FP64 = 0, DG_FP32_INNER = 1 } dg_precision;
+typedef enum { DG_PREC_DIAGONAL = 0, DG_PREC_CELL_FDM = 1 } dg_preconditioner;
 
 enum { DG_ORO_FLAT = 0, DG_ORO_AGNESI = 1, DG_ORO_BELL = 2, DG_ORO_GAUSS_HILL = 3, DG_ORO_GAUSS_RIDGE = 4 };
 enum { DG_ATM_ISOTHERMAL = 0, DG_ATM_STRATIFIED = 1 };
@@ -89,7 +90,10 @@ typedef struct {
  *     ||r||_2 <= max(rtol ||r0||_2, atol);
  *   precision: DG_FP64, or DG_FP32_INNER (FP64 defect correction around an FP32 GMRES whose
  *     operator, preconditioner and basis are FP32; inner_rtol / inner_restart / inner_maxit);
- *   penalty_beta: weight of the pressure-jump penalty in the implicit energy flux. */
+ *   penalty_beta: weight of the pressure-jump penalty in the implicit energy flux;
+ *   preconditioner: DG_PREC_DIAGONAL (a diagonal scaling) or DG_PREC_CELL_FDM (cell-wise fast
+ *     diagonalisation of a separable approximation of the cell block); changes iteration counts
+ *     only, not the converged solution. */
 typedef struct {
   int32_t fp_iters;
   int32_t gmres_restart;
@@ -101,6 +105,7 @@ typedef struct {
   int32_t inner_restart;
   int32_t inner_maxit;
   double penalty_beta;
+  int32_t preconditioner;
 } dg_options;
 
 /* Per-step statistics ([implicit stage][fixed-point iteration]). */
@@ -125,7 +130,7 @@ typedef struct {
 typedef struct dg_ctx dg_ctx;
 
 /* Fills *opt with the defaults: fp_iters 2, GMRES(30), rtol 1e-12, atol 0, maxit 2000, FP64,
- * inner_rtol 1e-4, inner_restart 30, inner_maxit 500, penalty_beta 1. */
+ * inner_rtol 1e-4, inner_restart 30, inner_maxit 500, penalty_beta 1, DG_PREC_CELL_FDM. */
 void dg_default_options(dg_options* opt);
 
 /* Builds the mesh (refinement by rules, 2:1 balance check, Morton order), uploads it, and

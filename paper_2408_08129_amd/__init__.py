@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libimexdg.so")
 
 DG_OK, DG_EINVAL, DG_ENOMEM, DG_EDEVICE, DG_ENOCONV, DG_ENAN, DG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 DG_FP64, DG_FP32_INNER = 0, 1
+DG_PREC_DIAGONAL, DG_PREC_CELL_FDM = 0, 1
 ORO_FLAT, ORO_AGNESI, ORO_BELL, ORO_GAUSS_HILL, ORO_GAUSS_RIDGE = range(5)
 ATM_ISOTHERMAL, ATM_STRATIFIED = range(2)
 MAX_RULES = 8
@@ -50,7 +51,8 @@ class dg_options(ctypes.Structure):
                 ("gmres_maxit", ctypes.c_int32), ("gmres_rtol", ctypes.c_double),
                 ("gmres_atol", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("inner_rtol", ctypes.c_double), ("inner_restart", ctypes.c_int32),
-                ("inner_maxit", ctypes.c_int32), ("penalty_beta", ctypes.c_double)]
+                ("inner_maxit", ctypes.c_int32), ("penalty_beta", ctypes.c_double),
+                ("preconditioner", ctypes.c_int32)]
 
 
 class dg_step_stats(ctypes.Structure):

@@ -51,7 +51,9 @@ struct TabLayout {
   __host__ __device__ constexpr int lbw() const { return 4 * np + np * np; }       // lb/w
   __host__ __device__ constexpr int pi() const { return 6 * np + np * np; }        // Pi[c][j][a]
   __host__ __device__ constexpr int rw() const { return 6 * np + 3 * np * np; }    // Rw[c][a][j]
-  __host__ __device__ constexpr int size() const { return 6 * np + 5 * np * np; }
+  __host__ __device__ constexpr int fds() const { return 6 * np + 5 * np * np; }   // S[i][a]
+  __host__ __device__ constexpr int fdmu() const { return 6 * np + 6 * np * np; }  // mu[a]
+  __host__ __device__ constexpr int size() const { return 7 * np + 6 * np * np; }
 };
 
 // ----------------------------------------------------------------------- operator parameters
@@ -82,12 +84,28 @@ struct DivArgs {
   T* out;
 };
 
+// Cell-wise fast-diagonalisation preconditioner: z = P^{-1} (scale v) with, per cell,
+// P = Jbar (S^-T (x) ...) [1/(gamma-1) + sum_k alpha_k mu] (S^-1 (x) ...); coef[cell] holds
+// (1/Jbar, alpha_0, alpha_1, alpha_2).
+template <class T>
+struct FdmArgs {
+  const T* v;
+  T scale;
+  const T* coef;
+  T* z;
+};
+
 // --------------------------------------------------------------------------------- launchers
 int launch_explicit(const MeshDev& m, int degree, const double* U, double* R, hipStream_t s);
 int launch_grad64(const MeshDev& m, int degree, const GradArgs<double>& a, hipStream_t s);
 int launch_div64(const MeshDev& m, int degree, const DivArgs<double>& a, hipStream_t s);
 int launch_grad32(const MeshDev& m, int degree, const GradArgs<float>& a, hipStream_t s);
 int launch_div32(const MeshDev& m, int degree, const DivArgs<float>& a, hipStream_t s);
+int launch_fdm64(const MeshDev& m, int degree, const FdmArgs<double>& a, hipStream_t s);
+int launch_fdm32(const MeshDev& m, int degree, const FdmArgs<float>& a, hipStream_t s);
+// per-cell sound speed (lam) and preconditioner coefficients from h and w J
+int launch_cellcoef(const MeshDev& m, int degree, const double* h, const double* wJ, double dta,
+                    double* lam, float* lam32, double* coef, float* coef32, hipStream_t s);
 
 // node geometry: physical coordinates, w J, background p and rho per node
 int launch_geometry(const MeshDev& m, int degree, double* x, double* y, double* z, double* wJ,

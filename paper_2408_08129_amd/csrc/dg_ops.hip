@@ -877,6 +877,175 @@ int launch_div32(const MeshDev& m, int degree, const DivArgs<float>& a, hipStrea
   return div_impl<float>(m, degree, a, s);
 }
 
+// ---------------------------------------------------------------- fast-diagonalisation kernel
+// z = P^{-1}(scale v) per cell: 1D transforms with S^T along every axis, division by the
+// separable eigenvalues, transforms back with S, times 1/Jbar.  One thread per node, LDS staging.
+namespace {
+template <int D, int NP, class T>
+__global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_fdm(const FdmArgs<T> a, const MeshDev m) {
+  using C = Cfg<D, NP>;
+  constexpr int NL = C::NL, TPC = C::TPC, CPB = C::CPB, NT = C::NT;
+  constexpr TabLayout TL{NP};
+  __shared__ T sS[NP * NP];
+  __shared__ T sMu[NP];
+  __shared__ T sA[CPB * NL];
+  __shared__ T sB[CPB * NL];
+  __shared__ T sCoef[CPB][4];
+  const int tid = threadIdx.x;
+  const int lc = tid / TPC, node = tid % TPC;
+  const int cell0 = blockIdx.x * CPB;
+  const int cell = cell0 + lc;
+  const bool active = node < NL && cell < m.ncell;
+  const T* gtab;
+  if constexpr (sizeof(T) == 8) gtab = (const T*)m.tab;
+  else gtab = (const T*)m.tabf;
+  for (int t = tid; t < NP * NP; t += NT) sS[t] = gtab[TL.fds() + t];
+  if (tid < NP) sMu[tid] = gtab[TL.fdmu() + tid];
+  if (tid < CPB * 4) {
+    const int c = tid / 4, k = tid % 4;
+    sCoef[c][k] = (cell0 + c) < m.ncell ? a.coef[(cell0 + c) * 4 + k] : T(0);
+  }
+  if (active) sA[lc * NL + node] = a.scale * a.v[(unsigned)cell * NL + node];
+  __syncthreads();
+  int ii[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < D; ++k) ii[k] = along<D, NP>(node, k);
+  T* src = sA;
+  T* dst = sB;
+  // forward: S^T along each axis
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    if (active) {
+      const int base = compose<D, NP>(k, 0, tang<D, NP>(node, k));
+      const int str = k == 0 ? 1 : (k == 1 ? NP : NP * NP);
+      T u = 0;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) u += sS[q * NP + ii[k]] * src[lc * NL + base + q * str];
+      dst[lc * NL + node] = u;
+    }
+    __syncthreads();
+    T* t = src;
+    src = dst;
+    dst = t;
+  }
+  if (active) {
+    T lam = T(1) / T(kGamma - 1.0);
+#pragma unroll
+    for (int k = 0; k < D; ++k) lam += sCoef[lc][1 + k] * sMu[ii[k]];
+    src[lc * NL + node] /= lam;
+  }
+  __syncthreads();
+  // backward: S along each axis
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    if (active) {
+      const int base = compose<D, NP>(k, 0, tang<D, NP>(node, k));
+      const int str = k == 0 ? 1 : (k == 1 ? NP : NP * NP);
+      T u = 0;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) u += sS[ii[k] * NP + q] * src[lc * NL + base + q * str];
+      dst[lc * NL + node] = u;
+    }
+    __syncthreads();
+    T* t = src;
+    src = dst;
+    dst = t;
+  }
+  if (active) a.z[(unsigned)cell * NL + node] = src[lc * NL + node] * sCoef[lc][0];
+}
+
+// One wavefront per cell: lam = sqrt((gamma-1) max h); hbar, Jbar (J = wJ / w); coefficients of
+// the fast-diagonalisation preconditioner alpha_k = (dt a)^2 hbar (2 / D_k)^2 with the vertical
+// size scaled by the cell's mean terrain stretching.
+template <int D, int NP>
+__global__ void k_cellcoef(const MeshDev m, const double* __restrict__ h, const double* __restrict__ wJ,
+                           double dta, double* lam, float* lam32, double* coef, float* coef32) {
+  constexpr int NL = ipow(NP, D);
+  constexpr TabLayout TL{NP};
+  const int c = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= m.ncell) return;
+  const double* w1 = m.tab + TL.w();
+  double hmax = 0.0, hsum = 0.0, jsum = 0.0;
+  for (int i = lane; i < NL; i += 64) {
+    const double hv = h[(unsigned)c * NL + i];
+    double wi = 1.0;
+    for (int k = 0; k < D; ++k) wi *= w1[along<D, NP>(i, k)];
+    hmax = fmax(hmax, hv);
+    hsum += hv;
+    jsum += wJ[(unsigned)c * NL + i] / wi;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    hmax = fmax(hmax, __shfl_xor(hmax, o, 64));
+    hsum += __shfl_xor(hsum, o, 64);
+    jsum += __shfl_xor(jsum, o, 64);
+  }
+  if (lane != 0) return;
+  const double l = sqrt((kGamma - 1.0) * hmax);
+  lam[c] = l;
+  if (lam32) lam32[c] = (float)l;
+  if (!coef) return;
+  const int lev = m.cell[c].x;
+  const double hb = hsum / NL, Jb = jsum / NL;
+  double half = 1.0;
+  for (int k = 0; k < D; ++k) half *= 0.5 * m.dxl[lev][k];
+  const double stretch = Jb / half;  // mean (1 - h / H)
+  double cf[4] = {1.0 / Jb, 0.0, 0.0, 0.0};
+  for (int k = 0; k < D; ++k) {
+    const double dk = m.dxl[lev][k] * (k == D - 1 ? stretch : 1.0);
+    cf[1 + k] = dta * dta * hb * (2.0 / dk) * (2.0 / dk);
+  }
+  for (int k = 0; k < 4; ++k) {
+    coef[c * 4 + k] = cf[k];
+    if (coef32) coef32[c * 4 + k] = (float)cf[k];
+  }
+}
+}  // namespace
+
+namespace {
+template <int D, int NP, class T>
+int run_fdm(const MeshDev& m, const FdmArgs<T>& a, hipStream_t s) {
+  using C = Cfg<D, NP>;
+  hipLaunchKernelGGL((k_fdm<D, NP, T>), dim3((m.ncell + C::CPB - 1) / C::CPB), dim3(C::NT), 0, s, a, m);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+template <int D, int NP>
+int run_cellcoef(const MeshDev& m, const double* h, const double* wJ, double dta, double* lam,
+                 float* lam32, double* coef, float* coef32, hipStream_t s) {
+  hipLaunchKernelGGL((k_cellcoef<D, NP>), dim3((m.ncell + 3) / 4), dim3(256), 0, s, m, h, wJ, dta, lam,
+                     lam32, coef, coef32);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+}  // namespace
+
+template <class T>
+static int fdm_impl(const MeshDev& m, int degree, const FdmArgs<T>& a, hipStream_t s) {
+  if (m.ncell == 0) return 0;
+  if (m.dim == 2) {
+    DG_DISPATCH(2, degree, return (run_fdm<2, NP, T>(m, a, s)));
+  } else {
+    DG_DISPATCH(3, degree, return (run_fdm<3, NP, T>(m, a, s)));
+  }
+}
+
+int launch_fdm64(const MeshDev& m, int degree, const FdmArgs<double>& a, hipStream_t s) {
+  return fdm_impl<double>(m, degree, a, s);
+}
+int launch_fdm32(const MeshDev& m, int degree, const FdmArgs<float>& a, hipStream_t s) {
+  return fdm_impl<float>(m, degree, a, s);
+}
+
+int launch_cellcoef(const MeshDev& m, int degree, const double* h, const double* wJ, double dta,
+                    double* lam, float* lam32, double* coef, float* coef32, hipStream_t s) {
+  if (m.ncell == 0) return 0;
+  if (m.dim == 2) {
+    DG_DISPATCH(2, degree, return (run_cellcoef<2, NP>(m, h, wJ, dta, lam, lam32, coef, coef32, s)));
+  } else {
+    DG_DISPATCH(3, degree, return (run_cellcoef<3, NP>(m, h, wJ, dta, lam, lam32, coef, coef32, s)));
+  }
+}
+
 // ------------------------------------------------------------------------------- node geometry
 namespace {
 

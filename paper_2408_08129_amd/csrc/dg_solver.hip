@@ -127,7 +127,7 @@ __global__ void k_update(const T* __restrict__ V, long ld, const Coef c, const T
     double s = 0.0;
 #pragma unroll
     for (int i = 0; i < NV; ++i) s += c.c[i] * (double)v[i];
-    x[e] += (double)dinv[e] * s;
+    x[e] += dinv ? (double)dinv[e] * s : s;
   }
 }
 
@@ -442,6 +442,75 @@ long double lagrange_d(const std::vector<long double>& xs, int j, long double t)
   return s;
 }
 
+// Local block of the 1D second-order operator B^T W^-1 B of the weak gradient with central
+// fluxes (the 1D analogue of -C M^-1 B at h = 1) on the reference cell [-1, 1], taken from a
+// periodic row of three cells, and the generalised eigenpairs L s = mu W s (S^T W S = I) by
+// Jacobi rotations on W^-1/2 L W^-1/2.
+void fdm_eigen(int np, const std::vector<long double>& x, const std::vector<long double>& w,
+               std::vector<double>& S, std::vector<double>& mu) {
+  const int nc = 3, n = nc * np;
+  std::vector<long double> B((size_t)n * n, 0.0L), lm(np), lp(np);
+  for (int a = 0; a < np; ++a) {
+    lm[a] = lagrange(x, a, -1.0L);
+    lp[a] = lagrange(x, a, 1.0L);
+  }
+  for (int K = 0; K < nc; ++K) {
+    const int Kp = (K + 1) % nc, Km = (K + nc - 1) % nc;
+    for (int i = 0; i < np; ++i)
+      for (int j = 0; j < np; ++j) {
+        B[(size_t)(K * np + i) * n + K * np + j] += -w[j] * lagrange_d(x, i, x[j]) + 0.5L * (lp[i] * lp[j] - lm[i] * lm[j]);
+        B[(size_t)(K * np + i) * n + Kp * np + j] += 0.5L * lp[i] * lm[j];
+        B[(size_t)(K * np + i) * n + Km * np + j] -= 0.5L * lm[i] * lp[j];
+      }
+  }
+  // L = (B^T W^-1 B) restricted to the middle cell
+  std::vector<long double> A((size_t)np * np, 0.0L);
+  for (int i = 0; i < np; ++i)
+    for (int j = 0; j < np; ++j) {
+      long double t = 0.0L;
+      for (int r = 0; r < n; ++r)
+        t += B[(size_t)r * n + np + i] * B[(size_t)r * n + np + j] / w[r % np];
+      A[(size_t)i * np + j] = t / std::sqrt(w[i] * w[j]);  // W^-1/2 L W^-1/2
+    }
+  std::vector<long double> V((size_t)np * np, 0.0L);
+  for (int i = 0; i < np; ++i) V[(size_t)i * np + i] = 1.0L;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    long double off = 0.0L;
+    for (int p = 0; p < np; ++p)
+      for (int q = p + 1; q < np; ++q) off += A[(size_t)p * np + q] * A[(size_t)p * np + q];
+    if (off < 1e-36L) break;
+    for (int p = 0; p < np; ++p)
+      for (int q = p + 1; q < np; ++q) {
+        const long double apq = A[(size_t)p * np + q];
+        if (std::fabs((double)apq) < 1e-300) continue;
+        const long double th = (A[(size_t)q * np + q] - A[(size_t)p * np + p]) / (2.0L * apq);
+        const long double t = (th >= 0 ? 1.0L : -1.0L) / (std::fabs((double)th) + std::sqrt(th * th + 1.0L));
+        const long double c = 1.0L / std::sqrt(t * t + 1.0L), sn = t * c;
+        for (int k = 0; k < np; ++k) {  // rotate columns p, q
+          const long double akp = A[(size_t)k * np + p], akq = A[(size_t)k * np + q];
+          A[(size_t)k * np + p] = c * akp - sn * akq;
+          A[(size_t)k * np + q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < np; ++k) {  // rotate rows p, q
+          const long double apk = A[(size_t)p * np + k], aqk = A[(size_t)q * np + k];
+          A[(size_t)p * np + k] = c * apk - sn * aqk;
+          A[(size_t)q * np + k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < np; ++k) {
+          const long double vkp = V[(size_t)k * np + p], vkq = V[(size_t)k * np + q];
+          V[(size_t)k * np + p] = c * vkp - sn * vkq;
+          V[(size_t)k * np + q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+  S.assign((size_t)np * np, 0.0);
+  mu.assign(np, 0.0);
+  for (int a = 0; a < np; ++a) {
+    mu[a] = (double)A[(size_t)a * np + a];
+    for (int i = 0; i < np; ++i) S[(size_t)i * np + a] = (double)(V[(size_t)i * np + a] / std::sqrt(w[i]));
+  }
+}
+
 std::vector<double> make_tables(int np) {
   TabLayout TL{np};
   std::vector<double> t(TL.size(), 0.0);
@@ -467,6 +536,10 @@ std::vector<double> make_tables(int np) {
         t[TL.pi() + (c * np + j) * np + a] = (double)v;
         t[TL.rw() + (c * np + a) * np + j] = (double)(w[j] / w[a] * v);
       }
+  std::vector<double> S, mu;
+  fdm_eigen(np, x, w, S, mu);
+  for (int i = 0; i < np * np; ++i) t[TL.fds() + i] = S[i];
+  for (int a = 0; a < np; ++a) t[TL.fdmu() + a] = mu[a];
   return t;
 }
 
@@ -504,6 +577,8 @@ struct dg_ctx {
   // mixed precision
   float *h32 = nullptr, *dinv32 = nullptr, *lam32 = nullptr, *q32 = nullptr, *w32 = nullptr, *V32 = nullptr;
   float* z32 = nullptr;
+  double *coef = nullptr, *u = nullptr;
+  float *coef32 = nullptr, *u32 = nullptr;
   double* rr = nullptr;
   // reductions
   double* part = nullptr;
@@ -616,6 +691,8 @@ void make_plan(dg_ctx* c, Plan& P) {
   P.add((void**)&c->w, ld * d8);
   P.add((void**)&c->lam, nc * d8);
   P.add((void**)&c->z, ld * d8);
+  P.add((void**)&c->coef, nc * 4 * d8);
+  P.add((void**)&c->u, ld * d8);
   if (c->opt.precision == DG_FP32_INNER) {
     P.add((void**)&c->V, 1 * ld * d8);  // outer residual work
     P.add((void**)&c->rr, ld * d8);
@@ -625,6 +702,8 @@ void make_plan(dg_ctx* c, Plan& P) {
     P.add((void**)&c->q32, D * ld * f4);
     P.add((void**)&c->w32, ld * f4);
     P.add((void**)&c->z32, ld * f4);
+    P.add((void**)&c->coef32, nc * 4 * f4);
+    P.add((void**)&c->u32, ld * f4);
     P.add((void**)&c->V32, (size_t)(c->m32 + 1) * ld * f4);
   } else {
     P.add((void**)&c->V, (size_t)(c->m + 1) * ld * d8);
@@ -646,6 +725,8 @@ dg_status prepare(dg_ctx* c, const dg_case_desc* desc, int degree, const dg_opti
   if (o.gmres_restart < 1 || o.gmres_restart > kMaxV - 1) return fail(c, DG_EINVAL, "gmres_restart must be in [1, 31]");
   if (o.inner_restart < 1 || o.inner_restart > kMaxV - 1) return fail(c, DG_EINVAL, "inner_restart must be in [1, 31]");
   if (o.precision != DG_FP64 && o.precision != DG_FP32_INNER) return fail(c, DG_EINVAL, "bad precision");
+  if (o.preconditioner != DG_PREC_DIAGONAL && o.preconditioner != DG_PREC_CELL_FDM)
+    return fail(c, DG_EINVAL, "bad preconditioner");
   if (desc->orography < 0 || desc->orography > 4) return fail(c, DG_EINVAL, "bad orography kind");
   if (desc->atmosphere < 0 || desc->atmosphere > 1) return fail(c, DG_EINVAL, "bad atmosphere kind");
   if (desc->oro[0] >= desc->length[2]) return fail(c, DG_EINVAL, "orography higher than the lid");
@@ -669,41 +750,65 @@ struct ApplyCtx {
   double dta;
 };
 
-// w = A(h) (scale * dinv * v) in precision T (dinv may be null: plain v)
-template <class T>
-int apply_A(dg_ctx* c, double dta, const T* v, const T* dinv, T scale, T* w);
+// Precision-dependent buffers and launchers.
+template <class T> struct PrecBuf;
+template <> struct PrecBuf<double> {
+  static double* q(dg_ctx* c) { return c->q; }
+  static double* h(dg_ctx* c) { return c->h; }
+  static double* z(dg_ctx* c) { return c->z; }
+  static double* lam(dg_ctx* c) { return c->lam; }
+  static double* coef(dg_ctx* c) { return c->coef; }
+  static int grad(const MeshDev& m, int deg, const GradArgs<double>& a, hipStream_t s) { return launch_grad64(m, deg, a, s); }
+  static int div(const MeshDev& m, int deg, const DivArgs<double>& a, hipStream_t s) { return launch_div64(m, deg, a, s); }
+  static int fdm(const MeshDev& m, int deg, const FdmArgs<double>& a, hipStream_t s) { return launch_fdm64(m, deg, a, s); }
+};
+template <> struct PrecBuf<float> {
+  static float* q(dg_ctx* c) { return c->q32; }
+  static float* h(dg_ctx* c) { return c->h32; }
+  static float* z(dg_ctx* c) { return c->z32; }
+  static float* lam(dg_ctx* c) { return c->lam32; }
+  static float* coef(dg_ctx* c) { return c->coef32; }
+  static int grad(const MeshDev& m, int deg, const GradArgs<float>& a, hipStream_t s) { return launch_grad32(m, deg, a, s); }
+  static int div(const MeshDev& m, int deg, const DivArgs<float>& a, hipStream_t s) { return launch_div32(m, deg, a, s); }
+  static int fdm(const MeshDev& m, int deg, const FdmArgs<float>& a, hipStream_t s) { return launch_fdm32(m, deg, a, s); }
+};
 
-// Pass 1 writes w = h M^{-1} B p and z = p at the nodes; pass 2 takes C(w) and the penalty and
-// mass terms of z.
-template <>
-int apply_A<double>(dg_ctx* c, double dta, const double* v, const double* dinv, double scale, double* w) {
-  GradArgs<double> g{v, dinv, scale, c->q, c->h, c->z};
-  const double nb8 = 8.0 * c->N;
+// w = A(h) p in precision T.  With dinv == null and scale == 1, p = v is taken as given; else
+// p = scale * dinv * v is formed on the fly and written to the z buffer by pass 1.
+// Pass 1 writes h M^{-1} B p (and p); pass 2 takes C of it and the penalty and mass terms of p.
+template <class T>
+int apply_A(dg_ctx* c, double dta, const T* v, const T* dinv, T scale, T* w) {
+  using PB = PrecBuf<T>;
+  const bool given = (dinv == nullptr && scale == T(1));
+  T* zout = given ? nullptr : PB::z(c);
+  const T* p = given ? v : PB::z(c);
+  GradArgs<T> g{v, dinv, scale, PB::q(c), PB::h(c), zout};
+  const double nb = (double)sizeof(T) * c->N;
   int rg;
-  // pass 1: v, dinv (if any), h in; w (d fields) and z out
-  TIMEDB(1, nb8 * ((dinv ? 2 : 1) + 1 + c->D + 1), rg = launch_grad64(c->md, c->degree, g, c->stream));
+  // pass 1: v (and dinv), h in; h M^-1 B p (d fields) and, if formed here, p out
+  TIMEDB(1, nb * ((dinv ? 2 : 1) + 1 + c->D + (given ? 0 : 1)), rg = PB::grad(c->md, c->degree, g, c->stream));
   if (rg) return -1;
   const double beta = c->opt.penalty_beta;
-  DivArgs<double> a{c->q, nullptr, c->z, nullptr, 1.0, c->lam, -dta * dta,
-                    dta * beta / (2.0 * (kGamma - 1.0)), 1.0 / (kGamma - 1.0), 1, w};
+  DivArgs<T> a{PB::q(c), nullptr, p, nullptr, T(1), PB::lam(c), (T)(-dta * dta),
+               (T)(dta * beta / (2.0 * (kGamma - 1.0))), (T)(1.0 / (kGamma - 1.0)), 1, w};
   int rd;
-  // pass 2: w (d fields), z in; A p out
-  TIMEDB(2, nb8 * (c->D + 2), rd = launch_div64(c->md, c->degree, a, c->stream));
+  // pass 2: d fields and p in; A p out
+  TIMEDB(2, nb * (c->D + 2), rd = PB::div(c->md, c->degree, a, c->stream));
   return rd;
 }
-template <>
-int apply_A<float>(dg_ctx* c, double dta, const float* v, const float* dinv, float scale, float* w) {
-  GradArgs<float> g{v, dinv, scale, c->q32, c->h32, c->z32};
-  const double nb4 = 4.0 * c->N;
-  int rg;
-  TIMEDB(1, nb4 * ((dinv ? 2 : 1) + 1 + c->D + 1), rg = launch_grad32(c->md, c->degree, g, c->stream));
-  if (rg) return -1;
-  const double beta = c->opt.penalty_beta;
-  DivArgs<float> a{c->q32, nullptr, c->z32, nullptr, 1.0f, c->lam32, (float)(-dta * dta),
-                   (float)(dta * beta / (2.0 * (kGamma - 1.0))), (float)(1.0 / (kGamma - 1.0)), 1, w};
-  int rd;
-  TIMEDB(2, nb4 * (c->D + 2), rd = launch_div32(c->md, c->degree, a, c->stream));
-  return rd;
+
+// w = A P^{-1} (scale v): the right-preconditioned operator of the Krylov solve.
+template <class T>
+int apply_AP(dg_ctx* c, double dta, const T* v, const T* dinv, T scale, T* w) {
+  using PB = PrecBuf<T>;
+  if (c->opt.preconditioner == DG_PREC_CELL_FDM) {
+    FdmArgs<T> f{v, scale, PB::coef(c), PB::z(c)};
+    int rf;
+    TIMEDB(4, 2.0 * sizeof(T) * c->N, rf = PB::fdm(c->md, c->degree, f, c->stream));
+    if (rf) return -1;
+    return apply_A<T>(c, dta, PB::z(c), (const T*)nullptr, T(1), w);
+  }
+  return apply_A<T>(c, dta, v, dinv, scale, w);
 }
 
 // reduce nv partial sums to host
@@ -748,7 +853,7 @@ dg_status gmres_cycle(dg_ctx* c, double dta, T* V, T* w, const T* dinv, int m, d
   Coef cf{};
   double dots[kMaxV + 1];
   for (int j = 0; j < m; ++j) {
-    if (apply_A<T>(c, dta, V + (size_t)j * ld, dinv, (T)s[j], w)) return fail(c, DG_EDEVICE, "operator launch failed");
+    if (apply_AP<T>(c, dta, V + (size_t)j * ld, dinv, (T)s[j], w)) return fail(c, DG_EDEVICE, "operator launch failed");
     const int nv = j + 1;
     T* vnext = V + (size_t)(j + 1) * ld;
     // classical Gram-Schmidt coefficients and |w|^2 in one pass
@@ -810,7 +915,18 @@ dg_status gmres_cycle(dg_ctx* c, double dta, T* V, T* w, const T* dinv, int m, d
     y[i] = t / H[(size_t)i * m + i];
   }
   for (int i = 0; i < jd; ++i) cf.c[i] = xscale * y[i] * s[i];
-  TIMEDB(6, (jd + 1.0) * sizeof(T) * N + 16.0 * N, launch_update<T>(jd, pw_grid(N), c->stream, (const T*)V, ld, cf, dinv, x, N));
+  if (c->opt.preconditioner == DG_PREC_CELL_FDM) {
+    // x += P^{-1} (V y): combine in FP64, precondition in FP64, add
+    TIMED(4, hipLaunchKernelGGL(k_zero, pw_grid(N), dim3(256), 0, c->stream, c->u, N));
+    TIMEDB(6, jd * (double)sizeof(T) * N + 16.0 * N, launch_update<T>(jd, pw_grid(N), c->stream, (const T*)V, ld, cf, (const T*)nullptr, c->u, N));
+    FdmArgs<double> f{c->u, 1.0, c->coef, c->z};
+    int rf;
+    TIMEDB(4, 16.0 * N, rf = launch_fdm64(c->md, c->degree, f, c->stream));
+    if (rf) return fail(c, DG_EDEVICE, "preconditioner launch failed");
+    TIMED(4, hipLaunchKernelGGL(k_add, pw_grid(N), dim3(256), 0, c->stream, x, c->z, N));
+  } else {
+    TIMEDB(6, (jd + 1.0) * sizeof(T) * N + 16.0 * N, launch_update<T>(jd, pw_grid(N), c->stream, (const T*)V, ld, cf, dinv, x, N));
+  }
   cr.res = res;
   cr.converged = res <= tol;
   return DG_OK;
@@ -962,9 +1078,13 @@ dg_status step_impl(dg_ctx* c, double* U, double dt, dg_step_stats* stats) {
                          c->degree + 1, dta, N, c->h, c->dinv,
                          c->opt.precision == DG_FP32_INNER ? c->h32 : (float*)nullptr,
                          c->opt.precision == DG_FP32_INNER ? c->dinv32 : (float*)nullptr));
-      TIMED(4, hipLaunchKernelGGL(k_lam, dim3((c->hm.ncell + 3) / 4), dim3(256), 0, s, c->h, c->NL,
-                         c->hm.ncell, c->lam,
-                         c->opt.precision == DG_FP32_INNER ? c->lam32 : (float*)nullptr));
+      {
+        const bool mixed = c->opt.precision == DG_FP32_INNER;
+        int rcc;
+        TIMED(4, rcc = launch_cellcoef(c->md, c->degree, c->h, c->wJ, dta, c->lam, mixed ? c->lam32 : nullptr,
+                                       c->coef, mixed ? c->coef32 : nullptr, s));
+        LCHK(rcc);
+      }
       // b = -dta C(h m') + M (e~ - rho k - pbar/(gamma-1))
       DivArgs<double> a{c->mp, c->h, nullptr, nullptr, 1.0, c->lam, -dta, 0.0, 0.0, 1, c->b};
       int rd;
@@ -1051,6 +1171,7 @@ void dg_default_options(dg_options* o) {
   o->inner_restart = 30;
   o->inner_maxit = 500;
   o->penalty_beta = 1.0;
+  o->preconditioner = DG_PREC_CELL_FDM;
 }
 
 const char* dg_last_error(void) { return g_last_error.c_str(); }
