@@ -76,7 +76,33 @@ KERNEL_NAMES = {
 }
 
 
-def roofline(res):
+PROFILE_KEYS = {
+    "explicit_residual": "k_cell<OpExplicit>",
+    "weak_gradient": "k_cell<OpGrad<double>>",
+    "weak_divergence": "k_cell<OpDiv<double>>",
+    "gs_dots": "k_mdot_norm<double>",
+    "gs_update": "k_axpy_norm<double>",
+}
+
+
+def measured_traffic(cls, workload):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary (calibrated against a plain copy), or None if absent or if the kernel sources changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = b"".join(open(os.path.join(ROOT, "paper_2408_08129_amd", "csrc", f), "rb").read()
+                   for f in ("dg_ops.hip", "dg_solver.hip", "dg_internal.hpp"))
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    k = rec["kernels"].get(PROFILE_KEYS.get(cls, ""))
+    return k["hbm_bytes_per_launch"] if k else None
+
+
+def roofline(res, workload="box3d_r4_hill"):
     """Dominant kernel over the timed region: its algorithmic bytes (reported by the library per
     launch, as designed) over its HIP-event-measured device time."""
     st = res["stats"]
@@ -89,7 +115,7 @@ def roofline(res):
     bytes_per_launch = bk[dom] / nk[dom]
     achieved = bk[dom] / (tk[dom] * 1e-3) / 1e9
     out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, workload),
            "kernel": KERNEL_NAMES[dom], "avg_launch_ms": round(avg_ms, 4), "launches": nk[dom],
            "algorithmic_bytes_per_launch": round(bytes_per_launch)}
     out["by_class"] = {k: {"ms": round(tk[k], 2), "launches": nk[k],
@@ -130,6 +156,8 @@ def main():
     ap.add_argument("--workload", default="box3d_r4_hill")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -161,7 +189,7 @@ def main():
         "p99_step_ms": round(percentile(r64["lat"], 99), 3),
         "gmres_iters": [s["gmres_iters"] for s in r64["stats"]],
     }
-    line["roofline"] = roofline(r64)
+    line["roofline"] = roofline(r64, args.workload)
     if not args.no_mixed:
         U64 = r64["U"]
         ref = U64.clone()
@@ -185,6 +213,13 @@ def main():
             "outer_iters": [s["outer_iters"] for s in r32["stats"]],
         }
         del r32
+    if args.calibrate_copy:
+        a = torch.empty(128 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line), flush=True)
