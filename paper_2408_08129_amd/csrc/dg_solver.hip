@@ -77,41 +77,65 @@ __global__ void k_reduce(const double* part, int nv, int G, double* out) {
   }
 }
 
-// dots_i = sum_n V_i[n] w[n] (i < NV) and, as value NV, |w|^2
-template <class T, int NV>
-__global__ void __launch_bounds__(kRedThreads) k_mdot_norm(const T* __restrict__ V, long ld,
-                                                           const T* __restrict__ w, double* part, long n) {
-  double acc[NV + 1];
+// Reduction pass of the Gram-Schmidt step: for i < NV the products V_i.x and (HASY) V_i.y,
+// then x.x and (HASY) x.y, y.y, accumulated in FP64.  Value order in part:
+// [V_i.x]_i, [V_i.y]_i, x.x, x.y, y.y (without y: [V_i.x]_i, x.x).
+template <class T, int NV, bool HASY>
+__global__ void __launch_bounds__(kRedThreads) k_gs_dots(const T* __restrict__ V, long ld,
+                                                         const T* __restrict__ x, const T* __restrict__ y,
+                                                         double* part, long n) {
+  constexpr int NA = HASY ? 2 * NV + 3 : NV + 1;
+  double acc[NA];
 #pragma unroll
-  for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
+  for (int i = 0; i < NA; ++i) acc[i] = 0.0;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-    const double wv = (double)w[e];
-    T v[NV];
+    const double xv = (double)x[e];
+    const double yv = HASY ? (double)y[e] : 0.0;
+    T v[NV > 0 ? NV : 1];
 #pragma unroll
     for (int i = 0; i < NV; ++i) v[i] = V[i * ld + e];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] += (double)v[i] * wv;
-    acc[NV] += wv * wv;
+    for (int i = 0; i < NV; ++i) {
+      acc[i] += (double)v[i] * xv;
+      if constexpr (HASY) acc[NV + i] += (double)v[i] * yv;
+    }
+    if constexpr (HASY) {
+      acc[2 * NV] += xv * xv;
+      acc[2 * NV + 1] += xv * yv;
+      acc[2 * NV + 2] += yv * yv;
+    } else {
+      acc[NV] += xv * xv;
+    }
   }
-  block_store<NV + 1>(acc, part);
+  block_store<NA>(acc, part);
 }
 
-// out = w - sum_i c_i V_i; part = |out|^2
+// Update pass of the Gram-Schmidt step, FP64 arithmetic:
+//   z = y - sum_i b_i V_i - g x      (x as read on entry)
+//   x = x - sum_i a_i V_i            (only when NV > 0; in place)
+// and part = |z|^2.
 template <class T, int NV>
-__global__ void __launch_bounds__(kRedThreads) k_axpy_norm(const T* __restrict__ V, long ld,
-                                                           const Coef c, const T* __restrict__ w,
-                                                           T* __restrict__ out, double* part, long n) {
+__global__ void __launch_bounds__(kRedThreads) k_gs_update(const T* __restrict__ V, long ld, const Coef a,
+                                                           const Coef b, double g, T* __restrict__ x,
+                                                           const T* __restrict__ y, T* __restrict__ z,
+                                                           double* part, long n) {
   double acc[1] = {0.0};
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-    T v[NV];
+    T v[NV > 0 ? NV : 1];
 #pragma unroll
     for (int i = 0; i < NV; ++i) v[i] = V[i * ld + e];
-    double x = (double)w[e];
+    const double xo = (double)x[e];
+    double zv = (double)y[e] - g * xo;
+    double xn = xo;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) x -= c.c[i] * (double)v[i];
-    const T xt = (T)x;
-    out[e] = xt;
-    acc[0] += (double)xt * (double)xt;
+    for (int i = 0; i < NV; ++i) {
+      zv -= b.c[i] * (double)v[i];
+      xn -= a.c[i] * (double)v[i];
+    }
+    const T zt = (T)zv;
+    z[e] = zt;
+    if (NV > 0) x[e] = (T)xn;
+    acc[0] += (double)zt * (double)zt;
   }
   block_store<1>(acc, part);
 }
@@ -135,21 +159,33 @@ __global__ void k_update(const T* __restrict__ V, long ld, const Coef c, const T
   X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) \
   X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31)
 
+#define DG_NV_CASES0(X) X(0) DG_NV_CASES(X)
+
 template <class T>
-void launch_mdot_norm(int nv, int G, hipStream_t s, const T* V, long ld, const T* w, double* part, long n) {
-  switch (nv) {
-#define X(K) case K: hipLaunchKernelGGL((k_mdot_norm<T, K>), dim3(G), dim3(kRedThreads), 0, s, V, ld, w, part, n); break;
-    DG_NV_CASES(X)
+void launch_gs_dots(int nv, int G, hipStream_t s, const T* V, long ld, const T* x, const T* y, double* part,
+                    long n) {
+  if (y) {
+    switch (nv) {
+#define X(K) case K: hipLaunchKernelGGL((k_gs_dots<T, K, true>), dim3(G), dim3(kRedThreads), 0, s, V, ld, x, y, part, n); break;
+      DG_NV_CASES0(X)
 #undef X
-    default: break;
+      default: break;
+    }
+  } else {
+    switch (nv) {
+#define X(K) case K: hipLaunchKernelGGL((k_gs_dots<T, K, false>), dim3(G), dim3(kRedThreads), 0, s, V, ld, x, y, part, n); break;
+      DG_NV_CASES0(X)
+#undef X
+      default: break;
+    }
   }
 }
 template <class T>
-void launch_axpy_norm(int nv, int G, hipStream_t s, const T* V, long ld, const Coef& c, const T* w, T* out,
-                      double* part, long n) {
+void launch_gs_update(int nv, int G, hipStream_t s, const T* V, long ld, const Coef& a, const Coef& b, double g,
+                      T* x, const T* y, T* z, double* part, long n) {
   switch (nv) {
-#define X(K) case K: hipLaunchKernelGGL((k_axpy_norm<T, K>), dim3(G), dim3(kRedThreads), 0, s, V, ld, c, w, out, part, n); break;
-    DG_NV_CASES(X)
+#define X(K) case K: hipLaunchKernelGGL((k_gs_update<T, K>), dim3(G), dim3(kRedThreads), 0, s, V, ld, a, b, g, x, y, z, part, n); break;
+    DG_NV_CASES0(X)
 #undef X
     default: break;
   }
@@ -708,8 +744,8 @@ void make_plan(dg_ctx* c, Plan& P) {
   } else {
     P.add((void**)&c->V, (size_t)(c->m + 1) * ld * d8);
   }
-  P.add((void**)&c->part, (size_t)(kMaxV + 1) * kMaxGrid * d8);
-  P.add((void**)&c->red, (kMaxV + 1) * d8);
+  P.add((void**)&c->part, (size_t)(2 * kMaxV + 3) * kMaxGrid * d8);
+  P.add((void**)&c->red, (2 * kMaxV + 3) * d8);
   P.add((void**)&c->flag, 256);
 }
 
@@ -823,109 +859,204 @@ dg_status reduce_to_host(dg_ctx* c, int nv, int G, double* out) {
 template <class T>
 dg_status dot(dg_ctx* c, const T* a, const T* b, double* out) {
   const int G = red_grid(c->N);
-  TIMEDB(3, 2.0 * sizeof(T) * c->N, launch_mdot_norm<T>(1, G, c->stream, a, c->ld, b, c->part, c->N));
-  double r[2];
-  const dg_status st = reduce_to_host(c, 2, G, r);
-  *out = r[0];
+  TIMEDB(3, 2.0 * sizeof(T) * c->N, launch_gs_dots<T>(0, G, c->stream, (const T*)nullptr, c->ld, a, b, c->part, c->N));
+  double r[3];
+  const dg_status st = reduce_to_host(c, 3, G, r);
+  *out = r[1];
   return st;
 }
 
 struct CycleResult {
   int its = 0;
-  int reorth = 0;
   double res = 0.0;
   bool converged = false;
 };
 
+// Hessenberg bookkeeping of one GMRES cycle: the raw Arnoldi coefficients (needed to correct the
+// next column for the delayed re-orthogonalisation) and their Givens-rotated copy.
+struct Arnoldi {
+  int m;
+  std::vector<double> Hr, R, cs, sn, g;
+  Arnoldi(int m_, double beta) : m(m_), Hr((size_t)(m_ + 1) * m_, 0.0), R((size_t)(m_ + 1) * m_, 0.0),
+                                 cs(m_, 0.0), sn(m_, 0.0), g(m_ + 1, 0.0) { g[0] = beta; }
+  double& hr(int i, int j) { return Hr[(size_t)i * m + j]; }
+  double& r(int i, int j) { return R[(size_t)i * m + j]; }
+  // Rotate column j (entries 0..j+1 given in col) with the rotations 0..j-1, then form rotation j.
+  // Returns |residual| after column j; with commit the rotation and the right-hand side are kept.
+  double rotate(int j, std::vector<double>& col, bool commit) {
+    for (int i = 0; i < j; ++i) {
+      const double a = col[i], b = col[i + 1];
+      col[i] = cs[i] * a + sn[i] * b;
+      col[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double den = std::hypot(a, b);
+    const double c = den > 0.0 ? a / den : 1.0, s = den > 0.0 ? b / den : 0.0;
+    if (commit) {
+      for (int i = 0; i <= j; ++i) r(i, j) = col[i];
+      r(j, j) = den;
+      cs[j] = c;
+      sn[j] = s;
+      g[j + 1] = -s * g[j];
+      g[j] = c * g[j];
+      return std::fabs(g[j + 1]);
+    }
+    return std::fabs(s * g[j]);
+  }
+};
+
 // One GMRES(m) cycle on V[0] (unnormalised, norm beta), stopping at residual <= tol or maxits;
-// accumulates x += xscale * dinv * V y into the FP64 vector x.
+// accumulates x += xscale * P^{-1} V y into the FP64 vector x.
+//
+// Arnoldi with classical Gram-Schmidt and one re-orthogonalisation, the latter delayed by one
+// step so that every step costs one reduction pass and one update pass over the basis:
+// step j applies the operator to the candidate u_j (projected once), and a single pass returns
+// Q^T u_j, Q^T w, u_j.u_j, u_j.w.  From these the candidate is re-orthogonalised and normalised
+// (Pythagoras), the previous Hessenberg column receives its correction, the coefficients of
+// A q_j follow without touching the vectors again, and one update pass writes both q_j and the
+// next candidate.  Basis vectors are stored unnormalised with scale s_i (q_i = s_i V_i).  The
+// residual after column j is estimated from the candidate's norm; once it meets the tolerance
+// (or the cycle ends) one more reduction pass finalises column j exactly.
 template <class T>
 dg_status gmres_cycle(dg_ctx* c, double dta, T* V, T* w, const T* dinv, int m, double beta,
                       double tol, int maxits, double* x, double xscale, CycleResult& cr) {
   const long ld = c->ld, N = c->N;
   const int G = red_grid(N);
-  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m, 0.0), sn(m, 0.0), g(m + 1, 0.0), s(m + 1, 0.0);
-  s[0] = 1.0 / beta;
-  g[0] = beta;
-  double res = beta;
+  const double tsz = (double)sizeof(T) * N;
+  Arnoldi H(m, beta);
+  std::vector<double> s(m + 1, 0.0), col(m + 1, 0.0), a(m + 1, 0.0), t(m + 1, 0.0), h(m + 1, 0.0);
+  double dots[2 * kMaxV + 3];
+  double sigma = 1.0 / beta;  // scale of the current candidate (1 / its norm)
+  double kappa = 1.0;         // candidate = kappa (A q_{j-1} - Q h_{j-1})
+  int done = -1;              // last column finalised
   int jd = 0;
+  double res = beta;
   cr = CycleResult{};
-  Coef cf{};
-  double dots[kMaxV + 1];
+  Coef ca{}, cb{};
+  auto nonfinite = [&](int n) {
+    for (int i = 0; i < n; ++i)
+      if (!std::isfinite(dots[i])) return true;
+    return false;
+  };
+  // Column col of the Hessenberg matrix receives the re-orthogonalisation of the candidate that
+  // followed it (coefficients av, norm rho of the re-orthogonalised candidate).
+  auto finalize = [&](int j, const double* av, double rho) {
+    const double f = 1.0 / (sigma * kappa);
+    for (int i = 0; i <= j; ++i) H.hr(i, j) += av ? av[i] * f : 0.0;
+    H.hr(j + 1, j) = rho * f;
+    for (int i = 0; i <= j + 1; ++i) col[i] = H.hr(i, j);
+    res = H.rotate(j, col, true);
+    done = j;
+  };
   for (int j = 0; j < m; ++j) {
-    if (apply_AP<T>(c, dta, V + (size_t)j * ld, dinv, (T)s[j], w)) return fail(c, DG_EDEVICE, "operator launch failed");
-    const int nv = j + 1;
-    T* vnext = V + (size_t)(j + 1) * ld;
-    // classical Gram-Schmidt coefficients and |w|^2 in one pass
-    TIMEDB(3, (nv + 1.0) * sizeof(T) * N, launch_mdot_norm<T>(nv, G, c->stream, V, ld, (const T*)w, c->part, N));
-    dg_status st = reduce_to_host(c, nv + 1, G, dots);
-    if (st) return st;
-    const double nw2 = dots[nv];
-    for (int i = 0; i < nv; ++i) {
-      H[(size_t)i * m + j] = dots[i] * s[i];
-      cf.c[i] = H[(size_t)i * m + j] * s[i];
-    }
-    TIMEDB(5, (nv + 2.0) * sizeof(T) * N, launch_axpy_norm<T>(nv, G, c->stream, V, ld, cf, (const T*)w, vnext, c->part, N));
-    double nrm2;
-    st = reduce_to_host(c, 1, G, &nrm2);
-    if (st) return st;
-    // DGKS criterion: re-orthogonalise once when the projection removed more than half of |w|^2
-    if (nrm2 < 0.5 * nw2) {
-      TIMEDB(3, (nv + 1.0) * sizeof(T) * N, launch_mdot_norm<T>(nv, G, c->stream, V, ld, (const T*)vnext, c->part, N));
-      st = reduce_to_host(c, nv + 1, G, dots);
-      if (st) return st;
-      for (int i = 0; i < nv; ++i) {
-        const double h2 = dots[i] * s[i];
-        H[(size_t)i * m + j] += h2;
-        cf.c[i] = h2 * s[i];
-      }
-      TIMEDB(5, (nv + 2.0) * sizeof(T) * N, launch_axpy_norm<T>(nv, G, c->stream, V, ld, cf, (const T*)vnext, w, c->part, N));
-      st = reduce_to_host(c, 1, G, &nrm2);
-      if (st) return st;
-      HIPCHK(hipMemcpyAsync(vnext, w, N * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
-      cr.reorth++;
-    }
-    const double nrm = std::sqrt(nrm2);
-    if (!std::isfinite(nrm)) return fail(c, DG_ENAN, "non-finite value in the Krylov solve");
-    H[(size_t)(j + 1) * m + j] = nrm;
-    s[j + 1] = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    // Givens
-    for (int i = 0; i < j; ++i) {
-      const double a = H[(size_t)i * m + j], b2 = H[(size_t)(i + 1) * m + j];
-      H[(size_t)i * m + j] = cs[i] * a + sn[i] * b2;
-      H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b2;
-    }
-    const double a = H[(size_t)j * m + j], b2 = H[(size_t)(j + 1) * m + j];
-    const double den = std::hypot(a, b2);
-    cs[j] = a / den;
-    sn[j] = b2 / den;
-    H[(size_t)j * m + j] = den;
-    H[(size_t)(j + 1) * m + j] = 0.0;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
-    res = std::fabs(g[j + 1]);
-    jd = j + 1;
+    T* Vj = V + (size_t)j * ld;
+    if (apply_AP<T>(c, dta, Vj, dinv, (T)sigma, w)) return fail(c, DG_EDEVICE, "operator launch failed");
     cr.its++;
-    if (res <= tol || cr.its >= maxits || nrm == 0.0) break;
+    // one reduction: Q_j^T V_j, Q_j^T w, V_j.V_j, V_j.w, w.w
+    TIMEDB(3, (j + 2.0) * tsz, launch_gs_dots<T>(j, G, c->stream, V, ld, Vj, w, c->part, N));
+    dg_status st = reduce_to_host(c, 2 * j + 3, G, dots);
+    if (st) return st;
+    if (nonfinite(2 * j + 3)) return fail(c, DG_ENAN, "non-finite value in the Krylov solve");
+    double aa = 0.0, ab = 0.0;
+    for (int i = 0; i < j; ++i) {
+      a[i] = s[i] * sigma * dots[i];       // q_i . (sigma V_j)
+      t[i] = s[i] * dots[j + i];           // q_i . w   (kept in t until the correction below)
+      aa += a[i] * a[i];
+      ab += a[i] * t[i];
+    }
+    const double cc = sigma * sigma * dots[2 * j];
+    const double dd = sigma * dots[2 * j + 1];
+    const double rho2 = cc - aa;
+    if (j > 0 && !(rho2 > 1e-26 * cc)) {
+      // the candidate lies in span(Q_j): lucky breakdown, column j-1 is exact with a zero
+      if (done < j - 1) finalize(j - 1, a.data(), 0.0);
+      jd = j;
+      break;
+    }
+    const double rho = std::sqrt(rho2);
+    if (j > 0 && done < j - 1) {
+      finalize(j - 1, a.data(), rho);
+      if (res <= tol) {
+        jd = j;
+        break;
+      }
+    }
+    // coefficients of A q_j on Q_{j+1}: (w - A Q_j a) / rho with A Q_j = Q_{j+1} Hr
+    for (int i = 0; i <= j; ++i) {
+      double ti = 0.0;
+      for (int k = 0; k < j; ++k) ti += H.hr(i, k) * a[k];
+      h[i] = ti;  // (Hr a)_i
+    }
+    for (int i = 0; i < j; ++i) {
+      const double bi = t[i];
+      t[i] = (bi - h[i]) / rho;  // h_j[i]
+    }
+    t[j] = ((dd - ab) / rho - h[j]) / rho;  // h_j[j]
+    // next candidate V_{j+1} = rho (A q_j - Q_{j+1} h_j) = w - rho Q_{j+1} gv,  gv = (Hr a)/rho + h_j
+    const double gj = h[j] / rho + t[j];
+    for (int i = 0; i < j; ++i) {
+      const double gi = h[i] / rho + t[i];
+      cb.c[i] = (rho * gi - gj * a[i]) * s[i];
+      ca.c[i] = a[i] * s[i] / sigma;
+    }
+    T* Vn = V + (size_t)(j + 1) * ld;
+    TIMEDB(5, (j + 3.0 + (j > 0 ? 1.0 : 0.0)) * tsz,
+           launch_gs_update<T>(j, G, c->stream, V, ld, ca, cb, gj * sigma, Vj, (const T*)w, Vn, c->part, N));
+    double nn;
+    st = reduce_to_host(c, 1, G, &nn);
+    if (st) return st;
+    if (!std::isfinite(nn)) return fail(c, DG_ENAN, "non-finite value in the Krylov solve");
+    s[j] = sigma / rho;
+    kappa = rho;
+    for (int i = 0; i <= j; ++i) H.hr(i, j) = t[i];
+    jd = j + 1;
+    if (nn == 0.0) {
+      // A q_j lies in span(Q_{j+1}) exactly
+      sigma = 1.0;
+      finalize(j, nullptr, 0.0);
+      break;
+    }
+    sigma = 1.0 / std::sqrt(nn);
+    // estimate with the candidate's norm, finalise when it meets the tolerance or the cycle ends
+    for (int i = 0; i <= j; ++i) col[i] = t[i];
+    col[j + 1] = std::sqrt(nn) / rho;
+    const double est = H.rotate(j, col, false);
+    if (est <= tol || j + 1 == m || cr.its >= maxits) {
+      TIMEDB(3, (j + 2.0) * tsz, launch_gs_dots<T>(j + 1, G, c->stream, V, ld, Vn, (const T*)nullptr, c->part, N));
+      st = reduce_to_host(c, j + 2, G, dots);
+      if (st) return st;
+      if (nonfinite(j + 2)) return fail(c, DG_ENAN, "non-finite value in the Krylov solve");
+      double a2 = 0.0;
+      for (int i = 0; i <= j; ++i) {
+        a[i] = s[i] * sigma * dots[i];
+        a2 += a[i] * a[i];
+      }
+      const double c2 = sigma * sigma * dots[j + 1];
+      finalize(j, a.data(), std::sqrt(std::max(c2 - a2, 0.0)));
+      if (res <= tol || j + 1 == m || cr.its >= maxits) break;
+    }
   }
   std::vector<double> y(jd, 0.0);
   for (int i = jd - 1; i >= 0; --i) {
-    double t = g[i];
-    for (int k = i + 1; k < jd; ++k) t -= H[(size_t)i * m + k] * y[k];
-    y[i] = t / H[(size_t)i * m + i];
+    double v = H.g[i];
+    for (int k = i + 1; k < jd; ++k) v -= H.r(i, k) * y[k];
+    y[i] = v / H.r(i, i);
   }
+  Coef cf{};
   for (int i = 0; i < jd; ++i) cf.c[i] = xscale * y[i] * s[i];
-  if (c->opt.preconditioner == DG_PREC_CELL_FDM) {
-    // x += P^{-1} (V y): combine in FP64, precondition in FP64, add
-    TIMED(4, hipLaunchKernelGGL(k_zero, pw_grid(N), dim3(256), 0, c->stream, c->u, N));
-    TIMEDB(6, jd * (double)sizeof(T) * N + 16.0 * N, launch_update<T>(jd, pw_grid(N), c->stream, (const T*)V, ld, cf, (const T*)nullptr, c->u, N));
-    FdmArgs<double> f{c->u, 1.0, c->coef, c->z};
-    int rf;
-    TIMEDB(4, 16.0 * N, rf = launch_fdm64(c->md, c->degree, f, c->stream));
-    if (rf) return fail(c, DG_EDEVICE, "preconditioner launch failed");
-    TIMED(4, hipLaunchKernelGGL(k_add, pw_grid(N), dim3(256), 0, c->stream, x, c->z, N));
-  } else {
-    TIMEDB(6, (jd + 1.0) * sizeof(T) * N + 16.0 * N, launch_update<T>(jd, pw_grid(N), c->stream, (const T*)V, ld, cf, dinv, x, N));
+  if (jd > 0) {
+    if (c->opt.preconditioner == DG_PREC_CELL_FDM) {
+      // x += P^{-1} (V y): combine in FP64, precondition in FP64, add
+      TIMED(4, hipLaunchKernelGGL(k_zero, pw_grid(N), dim3(256), 0, c->stream, c->u, N));
+      TIMEDB(6, jd * tsz + 16.0 * N, launch_update<T>(jd, pw_grid(N), c->stream, (const T*)V, ld, cf, (const T*)nullptr, c->u, N));
+      FdmArgs<double> f{c->u, 1.0, c->coef, c->z};
+      int rf;
+      TIMEDB(4, 16.0 * N, rf = launch_fdm64(c->md, c->degree, f, c->stream));
+      if (rf) return fail(c, DG_EDEVICE, "preconditioner launch failed");
+      TIMED(4, hipLaunchKernelGGL(k_add, pw_grid(N), dim3(256), 0, c->stream, x, c->z, N));
+    } else {
+      TIMEDB(6, (jd + 1.0) * tsz + 16.0 * N, launch_update<T>(jd, pw_grid(N), c->stream, (const T*)V, ld, cf, dinv, x, N));
+    }
   }
   cr.res = res;
   cr.converged = res <= tol;
