@@ -1,0 +1,481 @@
+// Column kernels of the two Helmholtz passes (arXiv 2408.08129, Section 3.2: the weak gradient
+// M^{-1} B and the weak divergence C with the pressure-jump penalty) on the cells whose faces are
+// all conforming or walls.  Cells with a 2:1 face go through the general cell kernel.
+//
+// Layout: one thread owns one vertical column of a cell (NP nodes, the last, vertical axis is the
+// slowest in the node order), so a cell is NP^(d-1) threads and a 256-thread workgroup holds
+// 256 / NP^(d-1) cells.  The column is held in registers: the vertical contraction, the traces on
+// the horizontal faces (bottom / top) and their lift never leave the thread.  The contractions
+// along x (and y) and the traces on the x (and y) faces read the exchanged fields from LDS; the
+// thread that owns column c also owns face point c of every x / y face, evaluates the flux there
+// and passes it through LDS to the threads whose nodes it lifts onto.  Two workgroup barriers.
+//
+// The terrain-following map keeps the x and y face normals axis aligned (Gam[k][l] = 0 for
+// k < d-1, l != k) and its metric constant along a column except for the slope terms of the
+// vertical row, which is what lets the x / y passes exchange only the fields they need.
+#include "dg_device.hpp"
+
+namespace dg {
+namespace {
+using namespace dev;
+
+template <int D, int NP>
+struct Col {
+  static constexpr int NC = ipow(NP, D - 1);  // columns per cell = points per face
+  static constexpr int NL = NC * NP;
+  static constexpr int NF = 2 * D;
+  static constexpr int CPB = 256 / NC;         // cells per workgroup
+  static constexpr int NTA = CPB * NC;         // threads that own a column
+  static constexpr int NT = 256;
+  static constexpr int NHC = D == 3 ? NP : 1;  // terrain samples per x / y face
+};
+
+// Input fields at node idx.  These kernels take p as given (no Jacobi scaling) and, for the
+// divergence, the vector field already multiplied by h; the general cell kernel covers the rest.
+template <class T>
+__device__ __forceinline__ T grad_in(const GradArgs<T>& a, unsigned idx) {
+  return a.p[idx];
+}
+template <int D, class T>
+__device__ __forceinline__ void div_in(const DivArgs<T>& a, unsigned N, unsigned idx, int mask, T* w, T& p) {
+#pragma unroll
+  for (int l = 0; l < D; ++l) w[l] = ((mask >> l) & 1) ? a.qv[l * N + idx] : T(0);
+  p = a.p[idx];
+}
+
+// Materialise a value at this point of the program: keeps the compiler from sinking arithmetic
+// past a barrier and holding every operand it read live until the end of the kernel.
+template <class T>
+__device__ __forceinline__ void pin(T& v) {
+  asm volatile("" : "+v"(v));
+}
+
+// node offset inside a cell of point q along the normal of face axis k at face point a
+template <int D, int NP>
+__device__ __forceinline__ int offs(int k, int q, int a) {
+  return compose<D, NP>(k, q, a);
+}
+
+template <int D, int NP, class T, bool DIV, class A>
+__global__ void __launch_bounds__(256) k_col(const A a, const MeshDev m) {
+  using C = Col<D, NP>;
+  constexpr int NC = C::NC, NL = C::NL, NF = C::NF, CPB = C::CPB, NHC = C::NHC;
+  constexpr TabLayout TL{NP};
+  constexpr int NX = DIV ? D : 1;  // exchanged fields: grad p; div w_0 .. w_{d-2}, p
+  constexpr int NH = D - 1;        // horizontal axes
+
+  __shared__ T sTab[TL.size()];
+  __shared__ T sX[CPB][NX][NL];
+  __shared__ T sFc[CPB][NC];               // e (1 - h/H) per column
+  __shared__ T sHf[CPB][NH][2][NHC];       // e (1 - h/H) at the x / y face samples
+  __shared__ T sPhi[CPB][2 * NH][NC];      // fluxes on the x / y faces
+
+  const int tid = threadIdx.x;
+  const bool lane = tid < C::NTA;
+  const int lc = lane ? tid / NC : CPB - 1;
+  const int c = tid % NC;
+  const int pos = xcd_block(blockIdx.x, gridDim.x) * CPB + lc;
+  const bool active = lane && pos < m.nreg;
+  const int cell = active ? m.reg[pos] : m.reg[0];
+  const unsigned N = (unsigned)m.N;
+  const int i0 = c % NP;
+  const int i1 = D == 3 ? c / NP : 0;
+
+  const T* gtab;
+  if constexpr (sizeof(T) == 8) gtab = (const T*)m.tab;
+  else gtab = (const T*)m.tabf;
+  for (int t = tid; t < TL.size(); t += C::NT) sTab[t] = gtab[t];
+
+  // ---------------------------------------------------------------- loads
+  const int4 ci = m.cell[cell];
+  int kind[NF], nb[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    kind[f] = m.fkind[cell * NF + f];
+    nb[f] = m.fnbr[cell * NF + f].x;
+  }
+  const unsigned base = (unsigned)cell * NL + c;
+  T pv[NP];            // grad: p; div: p (penalty / mass)
+  T wv[D][NP];         // div: h qv
+#pragma unroll
+  for (int z = 0; z < NP; ++z) {
+    if constexpr (DIV) {
+      T w[D];
+      div_in<D, T>(a, N, base + NC * z, (1 << D) - 1, w, pv[z]);
+#pragma unroll
+      for (int l = 0; l < D; ++l) wv[l][z] = w[l];
+    } else {
+      pv[z] = grad_in<T>(a, base + NC * z);
+    }
+  }
+  // neighbour traces at this thread's point of every face (tn[f][0..D-1] = w, tn[f][D] = p)
+  T tn[NF][D + 1];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    const int k = f >> 1, s = f & 1;
+#pragma unroll
+    for (int g = 0; g <= D; ++g) tn[f][g] = 0;
+    if (kind[f] != kConf) continue;
+    const unsigned nbase = (unsigned)nb[f] * NL;
+    const int mask = k == D - 1 ? (1 << D) - 1 : (1 << k);
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const T lq = gtab[TL.lb() + (1 - s) * NP + q];
+      const unsigned idx = nbase + offs<D, NP>(k, q, c);
+      if constexpr (DIV) {
+        T w[D], p;
+        div_in<D, T>(a, N, idx, mask, w, p);
+#pragma unroll
+        for (int l = 0; l < D; ++l) tn[f][l] += lq * w[l];
+        tn[f][D] += lq * p;
+      } else {
+        tn[f][D] += lq * grad_in<T>(a, idx);
+      }
+    }
+  }
+  T lam_own = 0, lam_nb[NF];
+  if constexpr (DIV) {
+    lam_own = a.lam ? a.lam[cell] : T(0);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) lam_nb[f] = (a.lam && kind[f] == kConf) ? a.lam[nb[f]] : T(0);
+  }
+
+  // ---------------------------------------------------------------- geometry
+  const int lev = ci.x;
+  const int iz = D == 3 ? ci.w : ci.z;
+  const T dx0 = (T)m.dxl[lev][0], dx1 = (T)m.dxl[lev][1], dxz = (T)m.dxl[lev][D - 1];
+  const T invH = (T)m.invH;
+  const T ha = T(0.5) * dx0, hb = T(0.5) * dx1, he = T(0.5) * dxz;
+  const T* xi = gtab + TL.xi();
+  T h, hx, hy;
+  {
+    const T x = dx0 * ((T)ci.y + T(0.5) * (T(1) + xi[i0]));
+    const T y = D == 3 ? dx1 * ((T)ci.z + T(0.5) * (T(1) + xi[i1])) : T(0);
+    terrain<T>(m.ter, D, x, y, h, hx, hy);
+  }
+  const T fcol = he * (T(1) - h * invH);
+  // face samples of e (1 - h/H): x faces (side, y index), then (3D) y faces (side, x index)
+  for (int e = c; e < NH * 2 * NHC; e += NC) {
+    const int ax = e / (2 * NHC), sd = (e / NHC) & 1, j = e % NHC;
+    T x, y = 0;
+    if (ax == 0) {
+      int P = ci.y + sd;
+      if (m.per[0] && P >= m.nlev[lev][0]) P -= m.nlev[lev][0];
+      x = dx0 * (T)P;
+      if (D == 3) y = dx1 * ((T)ci.z + T(0.5) * (T(1) + xi[j]));
+    } else {
+      int P = ci.z + sd;
+      if (m.per[1] && P >= m.nlev[lev][1]) P -= m.nlev[lev][1];
+      x = dx0 * ((T)ci.y + T(0.5) * (T(1) + xi[j]));
+      y = dx1 * (T)P;
+    }
+    T hf, d1, d2;
+    terrain<T>(m.ter, D, x, y, hf, d1, d2);
+    if (lane) sHf[lc][ax][sd][j] = he * (T(1) - hf * invH);
+  }
+  // neighbour traces complete before the barrier (their loads have been in flight since the top)
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+#pragma unroll
+    for (int g = 0; g <= D; ++g)
+      if (DIV || g == D) pin(tn[f][g]);
+  if (lane) {
+    sFc[lc][c] = fcol;
+#pragma unroll
+    for (int z = 0; z < NP; ++z) {
+      if constexpr (DIV) {
+#pragma unroll
+        for (int l = 0; l < D - 1; ++l) sX[lc][l][c + NC * z] = wv[l][z];
+        sX[lc][D - 1][c + NC * z] = pv[z];
+      } else {
+        sX[lc][0][c + NC * z] = pv[z];
+      }
+    }
+  }
+  __syncthreads();
+
+  // tables indexed by the thread's column (LDS) and by compile-time indices (scalar loads)
+  const T* Dt = &sTab[TL.dt()];
+  const T* Lbw = &sTab[TL.lbw()];
+  const T* Wt = &sTab[TL.w()];
+  const T* Dtu = gtab + TL.dt();
+  const T* Lbu = gtab + TL.lb();
+  const T* Lbwu = gtab + TL.lbw();
+  const T* Wtu = gtab + TL.w();
+  constexpr int NO = DIV ? 1 : D;
+  T acc[NO][NP];
+#pragma unroll
+  for (int o = 0; o < NO; ++o)
+#pragma unroll
+    for (int z = 0; z < NP; ++z) acc[o][z] = 0;
+
+  // ---------------------------------------------------------------- horizontal contractions
+  // Gam[0][0] = b f (3D) / f (2D) and Gam[1][1] = a f depend on the column only.
+  const T g00 = D == 3 ? hb : T(1);
+#pragma unroll
+  for (int z = 0; z < NP; ++z) {
+    T sx = 0;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const int col = q + NP * i1;
+      sx += Dt[i0 * NP + q] * (sFc[lc][col] * sX[lc][0][col + NC * z]);
+    }
+    if constexpr (DIV) acc[0][z] += -a.adiv * g00 * sx;
+    else acc[0][z] += -g00 * sx;
+    if constexpr (D == 3) {
+      T sy = 0;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        const int col = i0 + NP * q;
+        sy += Dt[i1 * NP + q] * (sFc[lc][col] * sX[lc][DIV ? 1 : 0][col + NC * z]);
+      }
+      if constexpr (DIV) acc[0][z] += -a.adiv * ha * sy;
+      else acc[1][z] += -ha * sy;
+    }
+#pragma unroll
+    for (int o = 0; o < NO; ++o) pin(acc[o][z]);
+  }
+  // ---------------------------------------------------------------- vertical contraction
+  // vertical row of Gam: 3D (-a b h_x om, -a b h_y om, a b), 2D (-a h_x om, a), om = 1 - zeta/H
+  const T gzz = D == 3 ? ha * hb : ha;
+  T gvz[NP];  // per node: the vertical flux components before the contraction
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    const T zeta = dxz * ((T)iz + T(0.5) * (T(1) + xi[q]));
+    const T om = T(1) - zeta * invH;
+    if constexpr (DIV) {
+      T gw = gzz * wv[D - 1][q] - gzz * (hx * om) * wv[0][q];
+      if constexpr (D == 3) gw -= gzz * (hy * om) * wv[1][q];
+      gvz[q] = -a.adiv * gw;
+    } else {
+      gvz[q] = om;  // the slope terms are formed below per component
+    }
+  }
+#pragma unroll
+  for (int z = 0; z < NP; ++z) {
+    if constexpr (DIV) {
+      T s = 0;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) s += Dtu[z * NP + q] * gvz[q];
+      acc[0][z] += s;
+    } else {
+      T s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        const T d = Dtu[z * NP + q] * pv[q];
+        s0 += d * gvz[q];
+        s2 += d;
+      }
+      // G[l][d-1] = -Gam[d-1][l] p
+      acc[0][z] += gzz * hx * s0;
+      if constexpr (D == 3) {
+        s1 = s0;
+        acc[1][z] += gzz * hy * s1;
+      }
+      acc[D - 1][z] += -gzz * s2;
+    }
+  }
+
+  // ---------------------------------------------------------------- vertical faces (registers)
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int f = 2 * (D - 1) + s;
+    T tm[D + 1];
+#pragma unroll
+    for (int g = 0; g <= D; ++g) tm[g] = 0;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const T lq = Lbu[s * NP + q];
+      if constexpr (DIV) {
+#pragma unroll
+        for (int l = 0; l < D; ++l) tm[l] += lq * wv[l][q];
+      }
+      tm[D] += lq * pv[q];
+    }
+    const T zf = dxz * (T)(iz + s);
+    const T omf = T(1) - zf * invH;
+    T Nv[D];
+    Nv[0] = -gzz * (hx * omf);
+    if constexpr (D == 3) Nv[1] = -gzz * (hy * omf);
+    Nv[D - 1] = gzz;
+    const T sign = s ? T(1) : T(-1);
+    const bool conf = kind[f] == kConf;
+    if constexpr (DIV) {
+      T v = 0;
+      if (conf) {
+        T wm = 0, wn = 0, nn = 0;
+#pragma unroll
+        for (int l = 0; l < D; ++l) { wm += Nv[l] * tm[l]; wn += Nv[l] * tn[f][l]; nn += Nv[l] * Nv[l]; }
+        const T wh = s ? T(0.5) * (wm + wn) : T(0.5) * (wn + wm);
+        v = a.adiv * sign * wh;
+        if (a.apen != T(0)) {
+          const T lf = lam_own > lam_nb[f] ? lam_own : lam_nb[f];
+          v += a.apen * (lf * sqrt(nn) * (tm[D] - tn[f][D]));
+        }
+      }
+#pragma unroll
+      for (int z = 0; z < NP; ++z) acc[0][z] += Lbwu[s * NP + z] * v;
+    } else {
+      T ph = tm[D];
+      if (conf) ph = s ? T(0.5) * (tm[D] + tn[f][D]) : T(0.5) * (tn[f][D] + tm[D]);
+#pragma unroll
+      for (int l = 0; l < D; ++l) {
+        const T phi = sign * ph * Nv[l];
+#pragma unroll
+        for (int z = 0; z < NP; ++z) acc[l][z] += Lbwu[s * NP + z] * phi;
+      }
+    }
+  }
+
+  // ---------------------------------------------------------------- x / y faces: flux at point c
+#pragma unroll
+  for (int k = 0; k < NH; ++k) {
+    // nodes of the normal line through face point c, and the terrain sample of that point
+    const int jt = c % NP;  // 3D: the other horizontal index of the point; 2D: unused
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int f = 2 * k + s;
+      T tmw = 0, tmp = 0;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        const int node = offs<D, NP>(k, q, c);
+        const T lq = Lbu[s * NP + q];
+        if constexpr (DIV) {
+          tmw += lq * sX[lc][k][node];
+          tmp += lq * sX[lc][D - 1][node];
+        } else {
+          tmp += lq * sX[lc][0][node];
+        }
+      }
+      const T Nk = (D == 3 ? (k == 0 ? hb : ha) : T(1)) * sHf[lc][k][s][D == 3 ? jt : 0];
+      const T sign = s ? T(1) : T(-1);
+      const bool conf = kind[f] == kConf;
+      T phi;
+      if constexpr (DIV) {
+        phi = 0;
+        if (conf) {
+          const T wm = Nk * tmw, wn = Nk * tn[f][k];
+          const T wh = s ? T(0.5) * (wm + wn) : T(0.5) * (wn + wm);
+          phi = a.adiv * sign * wh;
+          if (a.apen != T(0)) {
+            const T lf = lam_own > lam_nb[f] ? lam_own : lam_nb[f];
+            phi += a.apen * (lf * sqrt(Nk * Nk) * (tmp - tn[f][D]));
+          }
+        }
+      } else {
+        T ph = tmp;
+        if (conf) ph = s ? T(0.5) * (tmp + tn[f][D]) : T(0.5) * (tn[f][D] + tmp);
+        phi = sign * ph * Nk;
+      }
+      if (lane) sPhi[lc][f][c] = phi;
+    }
+  }
+  __syncthreads();
+
+  // ---------------------------------------------------------------- lift of the x / y faces
+#pragma unroll
+  for (int k = 0; k < NH; ++k) {
+    const int ik = k == 0 ? i0 : i1;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const T lw = Lbw[s * NP + ik];
+#pragma unroll
+      for (int z = 0; z < NP; ++z) {
+        // face point of node (i0, i1, z) on an x face: (i1, z); on a y face: (i0, z)
+        const int ap = D == 3 ? (k == 0 ? i1 : i0) + NP * z : z;
+        acc[DIV ? 0 : k][z] += lw * sPhi[lc][2 * k + s][ap];
+      }
+    }
+  }
+
+  // ---------------------------------------------------------------- finalize
+  if (!active) return;
+  const T J = (D == 3 ? ha * hb : ha) * fcol;
+  if constexpr (DIV) {
+    const T wc = D == 3 ? Wt[i0] * Wt[i1] : Wt[i0];
+#pragma unroll
+    for (int z = 0; z < NP; ++z) {
+      const unsigned idx = base + NC * z;
+      if (a.weak) a.out[idx] = (wc * Wtu[z]) * (acc[0][z] + a.amass * J * pv[z]);
+      else a.out[idx] = acc[0][z] / J;
+    }
+  } else {
+    const T iJ0 = T(1) / J;
+#pragma unroll
+    for (int z = 0; z < NP; ++z) {
+      const unsigned idx = base + NC * z;
+      T iJ = iJ0;
+      if (a.h) iJ *= a.h[idx];
+#pragma unroll
+      for (int l = 0; l < D; ++l) a.q[l * N + idx] = acc[l][z] * iJ;
+    }
+  }
+}
+
+template <int D, int NP, class T, bool DIV, class A>
+int run_col(const A& a, const MeshDev& m, hipStream_t s) {
+  using C = Col<D, NP>;
+  if (m.nreg <= 0) return 0;
+  const int grid = (m.nreg + C::CPB - 1) / C::CPB;
+  hipLaunchKernelGGL((k_col<D, NP, T, DIV, A>), dim3(grid), dim3(C::NT), 0, s, a, m);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+#define DG_COL_DISPATCH(EXPR)                 \
+  switch (degree) {                           \
+    case 1: { constexpr int NP = 2; EXPR; }   \
+    case 2: { constexpr int NP = 3; EXPR; }   \
+    case 3: { constexpr int NP = 4; EXPR; }   \
+    case 4: { constexpr int NP = 5; EXPR; }   \
+    case 5: { constexpr int NP = 6; EXPR; }   \
+    default: return -6;                       \
+  }
+
+template <class T>
+int grad_col(const MeshDev& m, int degree, const GradArgs<T>& a, hipStream_t s) {
+  if (m.dim == 2) {
+    DG_COL_DISPATCH(return (run_col<2, NP, T, false>(a, m, s)));
+  } else {
+    DG_COL_DISPATCH(return (run_col<3, NP, T, false>(a, m, s)));
+  }
+}
+template <class T>
+int div_col(const MeshDev& m, int degree, const DivArgs<T>& a, hipStream_t s) {
+  if (m.dim == 2) {
+    DG_COL_DISPATCH(return (run_col<2, NP, T, true>(a, m, s)));
+  } else {
+    DG_COL_DISPATCH(return (run_col<3, NP, T, true>(a, m, s)));
+  }
+}
+
+}  // namespace
+
+// p given (no Jacobi scaling, no copy of p requested) and, for the divergence, h folded into the
+// vector field: column kernel on the conforming cells, cell kernel on the rest; otherwise the
+// cell kernel on every cell.
+int launch_grad64(const MeshDev& m, int degree, const GradArgs<double>& a, hipStream_t s) {
+  if (a.dinv || a.z) return launch_grad_cells64(m, degree, a, nullptr, m.ncell, s);
+  int r = grad_col<double>(m, degree, a, s);
+  if (r == 0) r = launch_grad_cells64(m, degree, a, m.irr, m.nirr, s);
+  return r;
+}
+int launch_div64(const MeshDev& m, int degree, const DivArgs<double>& a, hipStream_t s) {
+  if (a.dinv || a.h || !a.p) return launch_div_cells64(m, degree, a, nullptr, m.ncell, s);
+  int r = div_col<double>(m, degree, a, s);
+  if (r == 0) r = launch_div_cells64(m, degree, a, m.irr, m.nirr, s);
+  return r;
+}
+int launch_grad32(const MeshDev& m, int degree, const GradArgs<float>& a, hipStream_t s) {
+  if (a.dinv || a.z) return launch_grad_cells32(m, degree, a, nullptr, m.ncell, s);
+  int r = grad_col<float>(m, degree, a, s);
+  if (r == 0) r = launch_grad_cells32(m, degree, a, m.irr, m.nirr, s);
+  return r;
+}
+int launch_div32(const MeshDev& m, int degree, const DivArgs<float>& a, hipStream_t s) {
+  if (a.dinv || a.h || !a.p) return launch_div_cells32(m, degree, a, nullptr, m.ncell, s);
+  int r = div_col<float>(m, degree, a, s);
+  if (r == 0) r = launch_div_cells32(m, degree, a, m.irr, m.nirr, s);
+  return r;
+}
+
+}  // namespace dg

@@ -39,6 +39,12 @@ struct MeshDev {
   double invH;                 // 1 / lid height
   double dxl[kMaxLev][3];      // cell size per level and axis
   int nlev[kMaxLev][3];        // cells per axis at each level
+  // cells whose faces are all conforming or walls (reg) and cells with a 2:1 face (irr), each
+  // in mesh order
+  const int* reg;
+  int nreg;
+  const int* irr;
+  int nirr;
 };
 
 // Offsets into the 1D table for NP = r + 1 points.
@@ -96,6 +102,12 @@ struct FdmArgs {
 };
 
 // --------------------------------------------------------------------------------- launchers
+// Weak gradient / divergence: the column kernel on the cells with conforming faces, the general
+// cell kernel on the cells with 2:1 faces.
+int launch_grad_cells64(const MeshDev& m, int degree, const GradArgs<double>& a, const int* list, int n, hipStream_t s);
+int launch_div_cells64(const MeshDev& m, int degree, const DivArgs<double>& a, const int* list, int n, hipStream_t s);
+int launch_grad_cells32(const MeshDev& m, int degree, const GradArgs<float>& a, const int* list, int n, hipStream_t s);
+int launch_div_cells32(const MeshDev& m, int degree, const DivArgs<float>& a, const int* list, int n, hipStream_t s);
 int launch_explicit(const MeshDev& m, int degree, const double* U, double* R, hipStream_t s);
 int launch_grad64(const MeshDev& m, int degree, const GradArgs<double>& a, hipStream_t s);
 int launch_div64(const MeshDev& m, int degree, const DivArgs<double>& a, hipStream_t s);

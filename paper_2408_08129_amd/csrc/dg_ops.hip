@@ -13,126 +13,11 @@
 //   (d) lift along the normal lines with l(+-1)/w.
 // The face geometry is evaluated from the integer description of the (sub)face so that both
 // sides of a face see the same normal.
-#include "dg_internal.hpp"
+#include "dg_device.hpp"
 
 namespace dg {
 namespace {
-
-constexpr int ipow(int b, int e) {
-  int r = 1;
-  for (int i = 0; i < e; ++i) r *= b;
-  return r;
-}
-constexpr int p2ceil(int x) {
-  int r = 1;
-  while (r < x) r <<= 1;
-  return r;
-}
-
-template <int D, int NP>
-struct Cfg {
-  static constexpr int NL = ipow(NP, D);
-  static constexpr int NFP = ipow(NP, D - 1);
-  static constexpr int MS = 1 << (D - 1);
-  static constexpr int TPC = p2ceil(NL);
-  static constexpr int NT = TPC > 256 ? TPC : 256;
-  static constexpr int CPB = NT / TPC;
-};
-
-// ------------------------------------------------------------------------------- node indexing
-template <int D, int NP>
-__device__ __forceinline__ int along(int node, int k) {
-  if (k == 0) return node % NP;
-  if (D == 3 && k == 1) return (node / NP) % NP;
-  return node / ipow(NP, D - 1);
-}
-// tangential (face-point) index of a node w.r.t. axis k: tangential axes ascending, first fastest
-template <int D, int NP>
-__device__ __forceinline__ int tang(int node, int k) {
-  if (D == 2) return k == 0 ? node / NP : node % NP;
-  if (k == 0) return node / NP;
-  if (k == 1) return (node % NP) + NP * (node / (NP * NP));
-  return node % (NP * NP);
-}
-template <int D, int NP>
-__device__ __forceinline__ int compose(int k, int q, int a) {
-  if (D == 2) return k == 0 ? q + NP * a : a + NP * q;
-  if (k == 0) return q + NP * a;
-  if (k == 1) return (a % NP) + NP * (q + NP * (a / NP));
-  return a + NP * NP * q;
-}
-
-// ---------------------------------------------------------------------------------- geometry
-template <class T>
-__device__ __forceinline__ void terrain(const Terrain& t, int dim, T x, T y, T& h, T& hx, T& hy) {
-  const T dx = x - (T)t.xc;
-  const T dy = (dim == 3) ? y - (T)t.yc : T(0);
-  const T h0 = (T)t.h0, ia2 = (T)t.ia2;
-  h = hx = hy = T(0);
-  switch (t.kind) {
-    case 1: {  // Witch of Agnesi: h0 a^2 / (a^2 + dx^2)
-      const T iq = T(1) / (T(1) + dx * dx * ia2);
-      h = h0 * iq;
-      hx = T(-2) * dx * ia2 * h * iq;
-      break;
-    }
-    case 2: {  // bell (Section 3.1, Eq. (3)): h0 / (1 + (dx^2 + dy^2)/a^2)^(3/2)
-      const T tt = T(1) + (dx * dx + dy * dy) * ia2;
-      const T it = T(1) / tt;
-      h = h0 * it * sqrt(it);
-      const T c = T(-3) * h * it * ia2;
-      hx = c * dx;
-      hy = c * dy;
-      break;
-    }
-    case 3: {  // Gaussian hill: h0 exp(-(dx^2 + dy^2) / (2 sigma^2))
-      h = h0 * exp(-(dx * dx + dy * dy) * (T(0.5) * ia2));
-      hx = -dx * ia2 * h;
-      hy = -dy * ia2 * h;
-      break;
-    }
-    case 4: {  // Gaussian ridge along y: h0 exp(-((x - xc)/a)^2)
-      h = h0 * exp(-(dx * dx) * ia2);
-      hx = T(-2) * dx * ia2 * h;
-      break;
-    }
-    default:
-      break;
-  }
-}
-
-// Metric of the cell map at level lev composed with z = zeta + h (1 - zeta / H), given the
-// terrain height and slopes at the point's horizontal position and its logical height zeta:
-// Gam[k][l] = det(J) (J^{-1})_{kl} (row k = area-weighted normal of a face of constant xi_k).
-template <int D, class T>
-__device__ __forceinline__ void metric_h(const MeshDev& m, int lev, T h, T hx, T hy, T zeta,
-                                         T (&Gam)[D][D], T& J) {
-  const T invH = (T)m.invH;
-  const T Jt = T(1) - h * invH;
-  const T om = T(1) - zeta * invH;
-  if constexpr (D == 3) {
-    const T a = T(0.5) * (T)m.dxl[lev][0], b = T(0.5) * (T)m.dxl[lev][1];
-    const T f = T(0.5) * (T)m.dxl[lev][2] * Jt;
-    Gam[0][0] = b * f; Gam[0][1] = 0; Gam[0][2] = 0;
-    Gam[1][0] = 0; Gam[1][1] = a * f; Gam[1][2] = 0;
-    Gam[2][0] = -a * b * (hx * om); Gam[2][1] = -a * b * (hy * om); Gam[2][2] = a * b;
-    J = a * b * f;
-  } else {
-    const T a = T(0.5) * (T)m.dxl[lev][0];
-    const T f = T(0.5) * (T)m.dxl[lev][1] * Jt;
-    Gam[0][0] = f; Gam[0][1] = 0;
-    Gam[1][0] = -a * (hx * om); Gam[1][1] = a;
-    J = a * f;
-  }
-}
-
-// Metric at a logical point X (terrain evaluated there).
-template <int D, class T>
-__device__ __forceinline__ void metric(const MeshDev& m, int lev, const T* X, T (&Gam)[D][D], T& J) {
-  T h, hx, hy;
-  terrain<T>(m.ter, D, X[0], D == 3 ? X[1] : T(0), h, hx, hy);
-  metric_h<D, T>(m, lev, h, hx, hy, X[D - 1], Gam, J);
-}
+using namespace dev;
 
 // ----------------------------------------------------------------------------------- fluxes
 template <int D>
@@ -348,15 +233,6 @@ template <class Op> struct HasLam { static constexpr bool value = false; };
 template <int D, class T> struct HasLam<OpDiv<D, T>> { static constexpr bool value = true; };
 
 // --------------------------------------------------------------------------------- the kernel
-// XCD-aware block order: the hardware hands consecutive workgroups to the 8 XCDs in turn; remap
-// so that each XCD walks a contiguous range of Morton-ordered cells and neighbour reads hit its L2.
-__device__ __forceinline__ int xcd_block(int b, int nblocks) {
-  constexpr int X = 8;
-  const int q = nblocks / X, r = nblocks % X;
-  const int x = b % X, i = b / X;
-  return x * q + (x < r ? x : r) + i;
-}
-
 // Coarse-face values at a fine sub-face point (tensor interpolation along the tangential axes).
 template <int D, int NP, class T>
 __device__ __forceinline__ T interp_sub(const T* Pi, const T* Tc, int c0, int c1, int j) {
@@ -441,7 +317,8 @@ struct TerTab {
 //      (coarse side) / interpolation (fine side);
 //   P4 lift of all faces along the normal lines, finalize.
 template <int D, int NP, class Op>
-__global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const MeshDev m) {
+__global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const MeshDev m,
+                                                             const int* __restrict__ list, int n) {
   using C = Cfg<D, NP>;
   using T = typename Op::T;
   using TT = TerTab<D, NP>;
@@ -468,27 +345,33 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
   __shared__ int4 sNbr[CPB][NF];
   __shared__ T sLam[CPB];
   __shared__ int sHang[NF];
+  __shared__ int sId[CPB];
 
   const int tid = threadIdx.x;
   const int lc = tid / TPC;
   const int node = tid % TPC;
-  const int cell0 = xcd_block(blockIdx.x, gridDim.x) * CPB;
-  const int cell = cell0 + lc;
-  const bool active = (node < NL) && (cell < m.ncell);
+  const int pos0 = xcd_block(blockIdx.x, gridDim.x) * CPB;  // position in the cell list
 
   const T* gtab;
   if constexpr (sizeof(T) == 8) gtab = (const T*)m.tab;
   else gtab = (const T*)m.tabf;
   for (int t = tid; t < TL.size(); t += NT) sTab[t] = gtab[t];
   if (tid < NF) sHang[tid] = 0;
-  if (tid < CPB) sCell[tid] = (cell0 + tid) < m.ncell ? m.cell[cell0 + tid] : make_int4(0, 0, 0, 0);
+  if (tid < CPB) {
+    const int i = pos0 + tid;
+    const int id = i < n ? (list ? list[i] : i) : -1;
+    sId[tid] = id;
+    sCell[tid] = id >= 0 ? m.cell[id] : make_int4(0, 0, 0, 0);
+  }
   __syncthreads();
+  const int cell = sId[lc];
+  const bool active = (node < NL) && (cell >= 0);
   if (tid < CPB * NF) {
     const int c = tid / NF, f = tid % NF;
-    const int cc = cell0 + c;
+    const int cc = sId[c];
     int kind = kWall;
     int4 nb = make_int4(-1, -1, -1, -1);
-    if (cc < m.ncell) {
+    if (cc >= 0) {
       kind = m.fkind[cc * NF + f];
       nb = m.fnbr[cc * NF + f];
     }
@@ -497,7 +380,7 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
     if (kind == kFine || kind == kCoarse) atomicOr(&sHang[f], 1);
   }
   if (tid < CPB) {
-    if constexpr (HasLam<Op>::value) sLam[tid] = (cell0 + tid) < m.ncell ? op.lam(cell0 + tid) : T(0);
+    if constexpr (HasLam<Op>::value) sLam[tid] = sId[tid] >= 0 ? op.lam(sId[tid]) : T(0);
   }
   // terrain table
   for (int t = tid; t < CPB * NH; t += NT) {
@@ -580,7 +463,7 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
   }
   for (int t = tid; t < CPB * NF * NFP; t += NT) {
     const int c = t / (NF * NFP), f = (t / NFP) % NF, j = t % NFP;
-    if (cell0 + c >= m.ncell) continue;
+    if (sId[c] < 0) continue;
     const int k = f >> 1, s = f & 1;
     const int base = compose<D, NP>(k, 0, j);
     const int str = compose<D, NP>(k, 1, 0);
@@ -618,7 +501,7 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
   }
   for (int t = tid; t < CPB * NF * NFP; t += NT) {
     const int c = t / (NF * NFP), f = (t / NFP) % NF, j = t % NFP;
-    if (cell0 + c >= m.ncell) continue;
+    if (sId[c] < 0) continue;
     const int kind = sKind[c][f];
     if (kind != kConf && kind != kWall) continue;
     const int k = f >> 1, s = f & 1;
@@ -695,7 +578,7 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
     const int k = f >> 1, s = f & 1;
     for (int t = tid; t < CPB * MS * NFP; t += NT) {
       const int c = t / (MS * NFP), sub = (t / NFP) % MS, j = t % NFP;
-      if (cell0 + c >= m.ncell) continue;
+      if (sId[c] < 0) continue;
       const int kind = sKind[c][f];
       if (!(kind == kCoarse || (kind == kFine && sub == 0))) continue;
       const int4 nb4 = sNbr[c][f];
@@ -718,7 +601,7 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
     __syncthreads();
     for (int t = tid; t < CPB * MS * NFP; t += NT) {
       const int c = t / (MS * NFP), sub = (t / NFP) % MS, j = t % NFP;
-      if (cell0 + c >= m.ncell) continue;
+      if (sId[c] < 0) continue;
       const int kind = sKind[c][f];
       if (!(kind == kCoarse || (kind == kFine && sub == 0))) continue;
       const int4 cc = sCell[c];
@@ -761,7 +644,7 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
     __syncthreads();
     for (int t = tid; t < CPB * NFP; t += NT) {
       const int c = t / NFP, a = t % NFP;
-      if (cell0 + c >= m.ncell) continue;
+      if (sId[c] < 0) continue;
       const int kind = sKind[c][f];
       if (kind != kCoarse && kind != kFine) continue;
       const int a0 = a % NP, a1 = a / NP;
@@ -812,11 +695,11 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
 }
 
 template <int D, int NP, class Op>
-int run(const Op& op, const MeshDev& m, hipStream_t s) {
+int run(const Op& op, const MeshDev& m, const int* list, int n, hipStream_t s) {
   using C = Cfg<D, NP>;
-  if (m.ncell == 0) return 0;
-  const int grid = (m.ncell + C::CPB - 1) / C::CPB;
-  hipLaunchKernelGGL((k_cell<D, NP, Op>), dim3(grid), dim3(C::NT), 0, s, op, m);
+  if (n <= 0) return 0;
+  const int grid = (n + C::CPB - 1) / C::CPB;
+  hipLaunchKernelGGL((k_cell<D, NP, Op>), dim3(grid), dim3(C::NT), 0, s, op, m, list, n);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -833,48 +716,50 @@ int run(const Op& op, const MeshDev& m, hipStream_t s) {
   }
 
 int launch_explicit(const MeshDev& m, int degree, const double* U, double* R, hipStream_t s) {
+  const int* list = nullptr;
+  const int n = m.ncell;
   if (m.dim == 2) {
     OpExplicit<2> op{U, R, (unsigned)m.N};
-    DG_DISPATCH(2, degree, return (run<2, NP>(op, m, s)));
+    DG_DISPATCH(2, degree, return (run<2, NP>(op, m, list, n, s)));
   } else {
     OpExplicit<3> op{U, R, (unsigned)m.N};
-    DG_DISPATCH(3, degree, return (run<3, NP>(op, m, s)));
+    DG_DISPATCH(3, degree, return (run<3, NP>(op, m, list, n, s)));
   }
 }
 
 template <class T>
-static int grad_impl(const MeshDev& m, int degree, const GradArgs<T>& a, hipStream_t s) {
+static int grad_impl(const MeshDev& m, int degree, const GradArgs<T>& a, const int* list, int n, hipStream_t s) {
   if (m.dim == 2) {
     OpGrad<2, T> op{a, (unsigned)m.N};
-    DG_DISPATCH(2, degree, return (run<2, NP>(op, m, s)));
+    DG_DISPATCH(2, degree, return (run<2, NP>(op, m, list, n, s)));
   } else {
     OpGrad<3, T> op{a, (unsigned)m.N};
-    DG_DISPATCH(3, degree, return (run<3, NP>(op, m, s)));
+    DG_DISPATCH(3, degree, return (run<3, NP>(op, m, list, n, s)));
   }
 }
 
 template <class T>
-static int div_impl(const MeshDev& m, int degree, const DivArgs<T>& a, hipStream_t s) {
+static int div_impl(const MeshDev& m, int degree, const DivArgs<T>& a, const int* list, int n, hipStream_t s) {
   if (m.dim == 2) {
     OpDiv<2, T> op{a, (unsigned)m.N};
-    DG_DISPATCH(2, degree, return (run<2, NP>(op, m, s)));
+    DG_DISPATCH(2, degree, return (run<2, NP>(op, m, list, n, s)));
   } else {
     OpDiv<3, T> op{a, (unsigned)m.N};
-    DG_DISPATCH(3, degree, return (run<3, NP>(op, m, s)));
+    DG_DISPATCH(3, degree, return (run<3, NP>(op, m, list, n, s)));
   }
 }
 
-int launch_grad64(const MeshDev& m, int degree, const GradArgs<double>& a, hipStream_t s) {
-  return grad_impl<double>(m, degree, a, s);
+int launch_grad_cells64(const MeshDev& m, int degree, const GradArgs<double>& a, const int* list, int n, hipStream_t s) {
+  return grad_impl<double>(m, degree, a, list, n, s);
 }
-int launch_div64(const MeshDev& m, int degree, const DivArgs<double>& a, hipStream_t s) {
-  return div_impl<double>(m, degree, a, s);
+int launch_div_cells64(const MeshDev& m, int degree, const DivArgs<double>& a, const int* list, int n, hipStream_t s) {
+  return div_impl<double>(m, degree, a, list, n, s);
 }
-int launch_grad32(const MeshDev& m, int degree, const GradArgs<float>& a, hipStream_t s) {
-  return grad_impl<float>(m, degree, a, s);
+int launch_grad_cells32(const MeshDev& m, int degree, const GradArgs<float>& a, const int* list, int n, hipStream_t s) {
+  return grad_impl<float>(m, degree, a, list, n, s);
 }
-int launch_div32(const MeshDev& m, int degree, const DivArgs<float>& a, hipStream_t s) {
-  return div_impl<float>(m, degree, a, s);
+int launch_div_cells32(const MeshDev& m, int degree, const DivArgs<float>& a, const int* list, int n, hipStream_t s) {
+  return div_impl<float>(m, degree, a, list, n, s);
 }
 
 // ---------------------------------------------------------------- fast-diagonalisation kernel

@@ -600,6 +600,7 @@ struct dg_ctx {
   int4* d_cell = nullptr;
   int* d_fkind = nullptr;
   int4* d_fnbr = nullptr;
+  int* d_lists = nullptr;  // cells with conforming faces only, then cells with a 2:1 face
   double* d_tab = nullptr;
   float* d_tabf = nullptr;
   // geometry / background
@@ -702,6 +703,7 @@ void make_plan(dg_ctx* c, Plan& P) {
   TabLayout TL{c->degree + 1};
   P.add((void**)&c->d_cell, nc * sizeof(int4));
   P.add((void**)&c->d_fkind, nc * 2 * D * sizeof(int));
+  P.add((void**)&c->d_lists, nc * sizeof(int));
   P.add((void**)&c->d_fnbr, nc * 2 * D * sizeof(int4));
   P.add((void**)&c->d_tab, TL.size() * d8);
   P.add((void**)&c->d_tabf, TL.size() * f4);
@@ -1381,6 +1383,26 @@ dg_status dg_setup(const dg_case_desc* desc, int32_t degree, const dg_options* o
   } while (0)
   SETUP_CHK(hipMemcpyAsync(c->d_cell, cells.data(), cells.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   SETUP_CHK(hipMemcpyAsync(c->d_fkind, M.fkind.data(), M.fkind.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  std::vector<int> lists;
+  lists.reserve(M.ncell);
+  int nreg = 0;
+  {
+    const int NF = 2 * c->D;
+    std::vector<int> irr;
+    for (int i = 0; i < M.ncell; ++i) {
+      bool reg = true;
+      for (int f = 0; f < NF; ++f) {
+        const int k = M.fkind[(size_t)i * NF + f];
+        if (k == kFine || k == kCoarse) reg = false;
+      }
+      if (reg) lists.push_back(i);
+      else irr.push_back(i);
+    }
+    nreg = (int)lists.size();
+    lists.insert(lists.end(), irr.begin(), irr.end());
+  }
+  if (M.ncell > 0)
+    SETUP_CHK(hipMemcpyAsync(c->d_lists, lists.data(), lists.size() * sizeof(int), hipMemcpyHostToDevice, s));
   SETUP_CHK(hipMemcpyAsync(c->d_fnbr, nbr.data(), nbr.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   SETUP_CHK(hipMemcpyAsync(c->d_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s));
   SETUP_CHK(hipMemcpyAsync(c->d_tabf, tabf.data(), tabf.size() * sizeof(float), hipMemcpyHostToDevice, s));
@@ -1391,6 +1413,10 @@ dg_status dg_setup(const dg_case_desc* desc, int32_t degree, const dg_options* o
   md.cell = c->d_cell;
   md.fkind = c->d_fkind;
   md.fnbr = c->d_fnbr;
+  md.reg = c->d_lists;
+  md.nreg = nreg;
+  md.irr = c->d_lists + nreg;
+  md.nirr = M.ncell - nreg;
   md.tab = c->d_tab;
   md.tabf = c->d_tabf;
   for (int a = 0; a < 3; ++a) {
