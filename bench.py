@@ -71,8 +71,8 @@ KERNEL_NAMES = {
     "explicit_residual": "k_cell<OpExplicit> (explicit residual)",
     "weak_gradient": "k_cell<OpGrad> (Helmholtz pass 1: h M^-1 B p)",
     "weak_divergence": "k_cell<OpDiv> (Helmholtz pass 2: C w, penalty, mass)",
-    "gs_dots": "k_mdot_norm (Gram-Schmidt dot products)",
-    "gs_update": "k_axpy_norm (Gram-Schmidt update and norm)",
+    "gs_dots": "k_gs_dots (Gram-Schmidt reduction pass)",
+    "gs_update": "k_gs_update (Gram-Schmidt update pass)",
 }
 
 

@@ -75,8 +75,7 @@ __global__ void __launch_bounds__(256) k_col(const A a, const MeshDev m) {
   const int lc = lane ? tid / NC : CPB - 1;
   const int c = tid % NC;
   const int pos = xcd_block(blockIdx.x, gridDim.x) * CPB + lc;
-  const bool active = lane && pos < m.nreg;
-  const int cell = active ? m.reg[pos] : m.reg[0];
+  const int cell = lane && pos < m.ncell ? pos : 0;
   const unsigned N = (unsigned)m.N;
   const int i0 = c % NP;
   const int i1 = D == 3 ? c / NP : 0;
@@ -89,11 +88,16 @@ __global__ void __launch_bounds__(256) k_col(const A a, const MeshDev m) {
   // ---------------------------------------------------------------- loads
   const int4 ci = m.cell[cell];
   int kind[NF], nb[NF];
+  bool regular = true;
 #pragma unroll
   for (int f = 0; f < NF; ++f) {
     kind[f] = m.fkind[cell * NF + f];
     nb[f] = m.fnbr[cell * NF + f].x;
+    regular = regular && (kind[f] == kConf || kind[f] == kWall);
   }
+  // cells with a 2:1 face run through the same code (gathers only cross conforming faces) but
+  // store nothing; the general cell kernel owns them
+  const bool active = lane && pos < m.ncell && regular;
   const unsigned base = (unsigned)cell * NL + c;
   T pv[NP];            // grad: p; div: p (penalty / mass)
   T wv[D][NP];         // div: h qv
@@ -274,6 +278,8 @@ __global__ void __launch_bounds__(256) k_col(const A a, const MeshDev m) {
       }
       acc[D - 1][z] += -gzz * s2;
     }
+#pragma unroll
+    for (int o = 0; o < NO; ++o) pin(acc[o][z]);
   }
 
   // ---------------------------------------------------------------- vertical faces (registers)
@@ -326,6 +332,11 @@ __global__ void __launch_bounds__(256) k_col(const A a, const MeshDev m) {
       }
     }
   }
+
+#pragma unroll
+  for (int o = 0; o < NO; ++o)
+#pragma unroll
+    for (int z = 0; z < NP; ++z) pin(acc[o][z]);
 
   // ---------------------------------------------------------------- x / y faces: flux at point c
 #pragma unroll
@@ -416,8 +427,145 @@ template <int D, int NP, class T, bool DIV, class A>
 int run_col(const A& a, const MeshDev& m, hipStream_t s) {
   using C = Col<D, NP>;
   if (m.nreg <= 0) return 0;
-  const int grid = (m.nreg + C::CPB - 1) / C::CPB;
+  const int grid = (m.ncell + C::CPB - 1) / C::CPB;
   hipLaunchKernelGGL((k_col<D, NP, T, DIV, A>), dim3(grid), dim3(C::NT), 0, s, a, m);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// Cell-wise fast-diagonalisation preconditioner in the column layout:
+// z = (1/Jbar) (S x S x S) diag(1 / (1/(gamma-1) + sum_k alpha_k mu_{i_k})) (S x S x S)^T (scale v).
+// The vertical transforms stay in the thread's registers, the horizontal ones go through LDS.
+template <int D, int NP, class T>
+__global__ void __launch_bounds__(256) k_fdm_col(const FdmArgs<T> a, const MeshDev m) {
+  using C = Col<D, NP>;
+  constexpr int NC = C::NC, NL = C::NL, CPB = C::CPB;
+  constexpr TabLayout TL{NP};
+  __shared__ T sA[CPB][NL];
+  __shared__ T sB[CPB][NL];
+  __shared__ T sS[NP * NP];
+  __shared__ T sMu[NP];
+  const int tid = threadIdx.x;
+  const bool lane = tid < C::NTA;
+  const int lc = lane ? tid / NC : CPB - 1;
+  const int c = tid % NC;
+  const int cell0 = xcd_block(blockIdx.x, gridDim.x) * CPB;
+  const int cell = cell0 + lc;
+  const bool active = lane && cell < m.ncell;
+  const int cl = active ? cell : 0;
+  const int i0 = c % NP;
+  const int i1 = D == 3 ? c / NP : 0;
+  const T* gtab;
+  if constexpr (sizeof(T) == 8) gtab = (const T*)m.tab;
+  else gtab = (const T*)m.tabf;
+  for (int t = tid; t < NP * NP; t += C::NT) sS[t] = gtab[TL.fds() + t];
+  if (tid < NP) sMu[tid] = gtab[TL.fdmu() + tid];
+  const T* S = gtab + TL.fds();  // S[i][a]; compile-time indices below become scalar loads
+  const unsigned base = (unsigned)cl * NL + c;
+  T v[NP], w[NP];
+#pragma unroll
+  for (int z = 0; z < NP; ++z) v[z] = a.scale * a.v[base + NC * z];
+  const T cf0 = a.coef[cl * 4 + 0], cfx = a.coef[cl * 4 + 1], cfy = a.coef[cl * 4 + 2];
+  const T cfz = a.coef[cl * 4 + D];
+  // vertical forward: w_j = sum_q S[q][j] v_q
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    T t = 0;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) t += S[q * NP + j] * v[q];
+    w[j] = t;
+  }
+  if (lane) {
+#pragma unroll
+    for (int z = 0; z < NP; ++z) sA[lc][c + NC * z] = w[z];
+  }
+  __syncthreads();
+  // x forward
+#pragma unroll
+  for (int z = 0; z < NP; ++z) {
+    T t = 0;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) t += sS[q * NP + i0] * sA[lc][q + NP * i1 + NC * z];
+    w[z] = t;
+  }
+  if constexpr (D == 3) {
+    if (lane) {
+#pragma unroll
+      for (int z = 0; z < NP; ++z) sB[lc][c + NC * z] = w[z];
+    }
+    __syncthreads();
+    // y forward
+#pragma unroll
+    for (int z = 0; z < NP; ++z) {
+      T t = 0;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) t += sS[q * NP + i1] * sB[lc][i0 + NP * q + NC * z];
+      w[z] = t;
+    }
+  }
+  // divide by the separable eigenvalues
+  T lh = T(1) / T(kGamma - 1.0) + cfx * sMu[i0];
+  if constexpr (D == 3) lh += cfy * sMu[i1];
+#pragma unroll
+  for (int z = 0; z < NP; ++z) w[z] /= lh + cfz * sMu[z];
+  if constexpr (D == 3) {
+    // y backward (sA is free: its last readers passed the barrier before the y forward pass)
+    if (lane) {
+#pragma unroll
+      for (int z = 0; z < NP; ++z) sA[lc][c + NC * z] = w[z];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int z = 0; z < NP; ++z) {
+      T t = 0;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) t += sS[i1 * NP + q] * sA[lc][i0 + NP * q + NC * z];
+      w[z] = t;
+    }
+    // x backward through sB (its readers, the y forward pass, passed the barrier above)
+    if (lane) {
+#pragma unroll
+      for (int z = 0; z < NP; ++z) sB[lc][c + NC * z] = w[z];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int z = 0; z < NP; ++z) {
+      T t = 0;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) t += sS[i0 * NP + q] * sB[lc][q + NP * i1 + NC * z];
+      v[z] = t;
+    }
+  } else {
+    // x backward through sB
+    if (lane) {
+#pragma unroll
+      for (int z = 0; z < NP; ++z) sB[lc][c + NC * z] = w[z];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int z = 0; z < NP; ++z) {
+      T t = 0;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) t += sS[i0 * NP + q] * sB[lc][q + NC * z];
+      v[z] = t;
+    }
+  }
+  if (!active) return;
+  // vertical backward: out_j = sum_q S[j][q] v_q, times 1/Jbar
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    T t = 0;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) t += S[j * NP + q] * v[q];
+    a.z[base + NC * j] = t * cf0;
+  }
+}
+
+template <int D, int NP, class T>
+int run_fdm_col(const FdmArgs<T>& a, const MeshDev& m, hipStream_t s) {
+  using C = Col<D, NP>;
+  if (m.ncell <= 0) return 0;
+  const int grid = (m.ncell + C::CPB - 1) / C::CPB;
+  hipLaunchKernelGGL((k_fdm_col<D, NP, T>), dim3(grid), dim3(C::NT), 0, s, a, m);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -448,7 +596,23 @@ int div_col(const MeshDev& m, int degree, const DivArgs<T>& a, hipStream_t s) {
   }
 }
 
+template <class T>
+int fdm_col(const MeshDev& m, int degree, const FdmArgs<T>& a, hipStream_t s) {
+  if (m.dim == 2) {
+    DG_COL_DISPATCH(return (run_fdm_col<2, NP, T>(a, m, s)));
+  } else {
+    DG_COL_DISPATCH(return (run_fdm_col<3, NP, T>(a, m, s)));
+  }
+}
+
 }  // namespace
+
+int launch_fdm64(const MeshDev& m, int degree, const FdmArgs<double>& a, hipStream_t s) {
+  return fdm_col<double>(m, degree, a, s);
+}
+int launch_fdm32(const MeshDev& m, int degree, const FdmArgs<float>& a, hipStream_t s) {
+  return fdm_col<float>(m, degree, a, s);
+}
 
 // p given (no Jacobi scaling, no copy of p requested) and, for the divergence, h folded into the
 // vector field: column kernel on the conforming cells, cell kernel on the rest; otherwise the

@@ -762,83 +762,8 @@ int launch_div_cells32(const MeshDev& m, int degree, const DivArgs<float>& a, co
   return div_impl<float>(m, degree, a, list, n, s);
 }
 
-// ---------------------------------------------------------------- fast-diagonalisation kernel
-// z = P^{-1}(scale v) per cell: 1D transforms with S^T along every axis, division by the
-// separable eigenvalues, transforms back with S, times 1/Jbar.  One thread per node, LDS staging.
+// ------------------------------------------------------------------ per-cell coefficients
 namespace {
-template <int D, int NP, class T>
-__global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_fdm(const FdmArgs<T> a, const MeshDev m) {
-  using C = Cfg<D, NP>;
-  constexpr int NL = C::NL, TPC = C::TPC, CPB = C::CPB, NT = C::NT;
-  constexpr TabLayout TL{NP};
-  __shared__ T sS[NP * NP];
-  __shared__ T sMu[NP];
-  __shared__ T sA[CPB * NL];
-  __shared__ T sB[CPB * NL];
-  __shared__ T sCoef[CPB][4];
-  const int tid = threadIdx.x;
-  const int lc = tid / TPC, node = tid % TPC;
-  const int cell0 = blockIdx.x * CPB;
-  const int cell = cell0 + lc;
-  const bool active = node < NL && cell < m.ncell;
-  const T* gtab;
-  if constexpr (sizeof(T) == 8) gtab = (const T*)m.tab;
-  else gtab = (const T*)m.tabf;
-  for (int t = tid; t < NP * NP; t += NT) sS[t] = gtab[TL.fds() + t];
-  if (tid < NP) sMu[tid] = gtab[TL.fdmu() + tid];
-  if (tid < CPB * 4) {
-    const int c = tid / 4, k = tid % 4;
-    sCoef[c][k] = (cell0 + c) < m.ncell ? a.coef[(cell0 + c) * 4 + k] : T(0);
-  }
-  if (active) sA[lc * NL + node] = a.scale * a.v[(unsigned)cell * NL + node];
-  __syncthreads();
-  int ii[3] = {0, 0, 0};
-#pragma unroll
-  for (int k = 0; k < D; ++k) ii[k] = along<D, NP>(node, k);
-  T* src = sA;
-  T* dst = sB;
-  // forward: S^T along each axis
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    if (active) {
-      const int base = compose<D, NP>(k, 0, tang<D, NP>(node, k));
-      const int str = k == 0 ? 1 : (k == 1 ? NP : NP * NP);
-      T u = 0;
-#pragma unroll
-      for (int q = 0; q < NP; ++q) u += sS[q * NP + ii[k]] * src[lc * NL + base + q * str];
-      dst[lc * NL + node] = u;
-    }
-    __syncthreads();
-    T* t = src;
-    src = dst;
-    dst = t;
-  }
-  if (active) {
-    T lam = T(1) / T(kGamma - 1.0);
-#pragma unroll
-    for (int k = 0; k < D; ++k) lam += sCoef[lc][1 + k] * sMu[ii[k]];
-    src[lc * NL + node] /= lam;
-  }
-  __syncthreads();
-  // backward: S along each axis
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    if (active) {
-      const int base = compose<D, NP>(k, 0, tang<D, NP>(node, k));
-      const int str = k == 0 ? 1 : (k == 1 ? NP : NP * NP);
-      T u = 0;
-#pragma unroll
-      for (int q = 0; q < NP; ++q) u += sS[ii[k] * NP + q] * src[lc * NL + base + q * str];
-      dst[lc * NL + node] = u;
-    }
-    __syncthreads();
-    T* t = src;
-    src = dst;
-    dst = t;
-  }
-  if (active) a.z[(unsigned)cell * NL + node] = src[lc * NL + node] * sCoef[lc][0];
-}
-
 // One wavefront per cell: lam = sqrt((gamma-1) max h); hbar, Jbar (J = wJ / w); coefficients of
 // the fast-diagonalisation preconditioner alpha_k = (dt a)^2 hbar (2 / D_k)^2 with the vertical
 // size scaled by the cell's mean terrain stretching.
@@ -889,12 +814,6 @@ __global__ void k_cellcoef(const MeshDev m, const double* __restrict__ h, const 
 }  // namespace
 
 namespace {
-template <int D, int NP, class T>
-int run_fdm(const MeshDev& m, const FdmArgs<T>& a, hipStream_t s) {
-  using C = Cfg<D, NP>;
-  hipLaunchKernelGGL((k_fdm<D, NP, T>), dim3((m.ncell + C::CPB - 1) / C::CPB), dim3(C::NT), 0, s, a, m);
-  return hipGetLastError() == hipSuccess ? 0 : -3;
-}
 template <int D, int NP>
 int run_cellcoef(const MeshDev& m, const double* h, const double* wJ, double dta, double* lam,
                  float* lam32, double* coef, float* coef32, hipStream_t s) {
@@ -903,23 +822,6 @@ int run_cellcoef(const MeshDev& m, const double* h, const double* wJ, double dta
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 }  // namespace
-
-template <class T>
-static int fdm_impl(const MeshDev& m, int degree, const FdmArgs<T>& a, hipStream_t s) {
-  if (m.ncell == 0) return 0;
-  if (m.dim == 2) {
-    DG_DISPATCH(2, degree, return (run_fdm<2, NP, T>(m, a, s)));
-  } else {
-    DG_DISPATCH(3, degree, return (run_fdm<3, NP, T>(m, a, s)));
-  }
-}
-
-int launch_fdm64(const MeshDev& m, int degree, const FdmArgs<double>& a, hipStream_t s) {
-  return fdm_impl<double>(m, degree, a, s);
-}
-int launch_fdm32(const MeshDev& m, int degree, const FdmArgs<float>& a, hipStream_t s) {
-  return fdm_impl<float>(m, degree, a, s);
-}
 
 int launch_cellcoef(const MeshDev& m, int degree, const double* h, const double* wJ, double dta,
                     double* lam, float* lam32, double* coef, float* coef32, hipStream_t s) {

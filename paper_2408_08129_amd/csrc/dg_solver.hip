@@ -1295,7 +1295,7 @@ extern "C" {
 void dg_default_options(dg_options* o) {
   if (!o) return;
   o->fp_iters = 2;
-  o->gmres_restart = 30;
+  o->gmres_restart = 15;
   o->gmres_maxit = 2000;
   o->gmres_rtol = 1e-12;
   o->gmres_atol = 0.0;
