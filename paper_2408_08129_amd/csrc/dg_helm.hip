@@ -432,6 +432,333 @@ int run_col(const A& a, const MeshDev& m, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
+// Explicit advective residual (the explicit part of the IMEX split, Section 3.2) in the column
+// layout, for the cells whose faces are conforming or walls: volume fluxes (rho u, rho u (x) u,
+// rho k u) with k = |u|^2 / 2, Rusanov fluxes with the advective speed, the slip-wall flux, and
+// the gravity work -rho g w.  Fields and 1/rho go through LDS for the x / y passes; the same
+// buffer then carries the x / y face fluxes.
+template <int D, int NP>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_col_exp(const double* __restrict__ U, double* __restrict__ R,
+                                                 const MeshDev m) {
+  using C = Col<D, NP>;
+  using T = double;
+  constexpr int NC = C::NC, NL = C::NL, NF = C::NF, CPB = C::CPB, NHC = C::NHC;
+  constexpr TabLayout TL{NP};
+  constexpr int NH = D - 1;
+  constexpr int NV = D + 2;  // rho, m_0 .. m_{d-1}, rho E
+  constexpr int NXF = NV + 1;
+  // one buffer per cell: first the fields and 1/rho, then the x / y face fluxes
+  constexpr int NBUF = NXF * NL > 2 * NH * NV * NC ? NXF * NL : 2 * NH * NV * NC;
+
+  __shared__ T sTab[TL.size()];
+  __shared__ T sBuf[CPB][NBUF];
+  __shared__ T sFc[CPB][NC];
+  __shared__ T sHf[CPB][NH][2][NHC];
+  T(*sX)[NXF][NL] = reinterpret_cast<T(*)[NXF][NL]>(&sBuf[0][0]);
+  T(*sPhi)[2 * NH][NV][NC] = reinterpret_cast<T(*)[2 * NH][NV][NC]>(&sBuf[0][0]);
+
+  const int tid = threadIdx.x;
+  const bool lane = tid < C::NTA;
+  const int lc = lane ? tid / NC : CPB - 1;
+  const int c = tid % NC;
+  const int pos = xcd_block(blockIdx.x, gridDim.x) * CPB + lc;
+  const int cell = lane && pos < m.ncell ? pos : 0;
+  const unsigned N = (unsigned)m.N;
+  const int i0 = c % NP;
+  const int i1 = D == 3 ? c / NP : 0;
+  const T* gtab = m.tab;
+  for (int t = tid; t < TL.size(); t += C::NT) sTab[t] = gtab[t];
+
+  // ---------------------------------------------------------------- loads
+  const int4 ci = m.cell[cell];
+  int kind[NF], nb[NF];
+  bool regular = true;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    kind[f] = m.fkind[cell * NF + f];
+    nb[f] = m.fnbr[cell * NF + f].x;
+    regular = regular && (kind[f] == kConf || kind[f] == kWall);
+  }
+  const bool active = lane && pos < m.ncell && regular;
+  const unsigned base = (unsigned)cell * NL + c;
+  T u[NV][NP];
+#pragma unroll
+  for (int z = 0; z < NP; ++z)
+#pragma unroll
+    for (int g = 0; g < NV; ++g) u[g][z] = U[g * N + base + NC * z];
+  T tn[NF][NV];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    const int k = f >> 1, s = f & 1;
+#pragma unroll
+    for (int g = 0; g < NV; ++g) tn[f][g] = 0;
+    if (kind[f] != kConf) continue;
+    const unsigned nbase = (unsigned)nb[f] * NL;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const T lq = gtab[TL.lb() + (1 - s) * NP + q];
+      const unsigned idx = nbase + offs<D, NP>(k, q, c);
+#pragma unroll
+      for (int g = 0; g < NV; ++g) tn[f][g] += lq * U[g * N + idx];
+    }
+  }
+
+  // ---------------------------------------------------------------- geometry
+  const int lev = ci.x;
+  const int iz = D == 3 ? ci.w : ci.z;
+  const T dx0 = m.dxl[lev][0], dx1 = m.dxl[lev][1], dxz = m.dxl[lev][D - 1];
+  const T invH = m.invH;
+  const T ha = 0.5 * dx0, hb = 0.5 * dx1, he = 0.5 * dxz;
+  const T* xi = gtab + TL.xi();
+  T h, hx, hy;
+  {
+    const T x = dx0 * ((T)ci.y + 0.5 * (1.0 + xi[i0]));
+    const T y = D == 3 ? dx1 * ((T)ci.z + 0.5 * (1.0 + xi[i1])) : 0.0;
+    terrain<T>(m.ter, D, x, y, h, hx, hy);
+  }
+  const T fcol = he * (1.0 - h * invH);
+  for (int e = c; e < NH * 2 * NHC; e += NC) {
+    const int ax = e / (2 * NHC), sd = (e / NHC) & 1, j = e % NHC;
+    T x, y = 0;
+    if (ax == 0) {
+      int P = ci.y + sd;
+      if (m.per[0] && P >= m.nlev[lev][0]) P -= m.nlev[lev][0];
+      x = dx0 * (T)P;
+      if (D == 3) y = dx1 * ((T)ci.z + 0.5 * (1.0 + xi[j]));
+    } else {
+      int P = ci.z + sd;
+      if (m.per[1] && P >= m.nlev[lev][1]) P -= m.nlev[lev][1];
+      x = dx0 * ((T)ci.y + 0.5 * (1.0 + xi[j]));
+      y = dx1 * (T)P;
+    }
+    T hf, d1, d2;
+    terrain<T>(m.ter, D, x, y, hf, d1, d2);
+    if (lane) sHf[lc][ax][sd][j] = he * (1.0 - hf * invH);
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+#pragma unroll
+    for (int g = 0; g < NV; ++g) pin(tn[f][g]);
+  T ir[NP];
+#pragma unroll
+  for (int z = 0; z < NP; ++z) ir[z] = 1.0 / u[0][z];
+  if (lane) {
+    sFc[lc][c] = fcol;
+#pragma unroll
+    for (int z = 0; z < NP; ++z) {
+#pragma unroll
+      for (int g = 0; g < NV; ++g) sX[lc][g][c + NC * z] = u[g][z];
+      sX[lc][NV][c + NC * z] = ir[z];
+    }
+  }
+
+  const T* Dt = &sTab[TL.dt()];
+  const T* Lbw = &sTab[TL.lbw()];
+  const T* Dtu = gtab + TL.dt();
+  const T* Lbu = gtab + TL.lb();
+  const T* Lbwu = gtab + TL.lbw();
+  T acc[NV][NP];
+#pragma unroll
+  for (int o = 0; o < NV; ++o)
+#pragma unroll
+    for (int z = 0; z < NP; ++z) acc[o][z] = 0;
+
+  // the column's own work first (registers only), so that only the accumulators, the x / y
+  // neighbour traces and the vertical momentum stay live across the barrier
+  // ---------------------------------------------------------------- vertical contraction
+  const T gzz = D == 3 ? ha * hb : ha;
+  {
+    T gm[NP];  // Gam[d-1] . m at each node of the column
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const T zeta = dxz * ((T)iz + 0.5 * (1.0 + xi[q]));
+      const T om = 1.0 - zeta * invH;
+      T t = gzz * u[D][q] - gzz * (hx * om) * u[1][q];
+      if constexpr (D == 3) t -= gzz * (hy * om) * u[2][q];
+      gm[q] = t;
+    }
+#pragma unroll
+    for (int z = 0; z < NP; ++z) {
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        const T d = Dtu[z * NP + q] * gm[q];
+        const T dr = d * ir[q];
+        T m2 = 0;
+#pragma unroll
+        for (int l = 0; l < D; ++l) m2 += u[1 + l][q] * u[1 + l][q];
+        acc[0][z] += d;
+#pragma unroll
+        for (int l = 0; l < D; ++l) acc[1 + l][z] += dr * u[1 + l][q];
+        acc[NV - 1][z] += dr * (0.5 * m2 * ir[q]);
+      }
+#pragma unroll
+      for (int o = 0; o < NV; ++o) pin(acc[o][z]);
+    }
+  }
+  // ---------------------------------------------------------------- vertical faces (registers)
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int f = 2 * (D - 1) + s;
+    T tm[NV];
+#pragma unroll
+    for (int g = 0; g < NV; ++g) {
+      T t = 0;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) t += Lbu[s * NP + q] * u[g][q];
+      tm[g] = t;
+    }
+    const T zf = dxz * (T)(iz + s);
+    const T omf = 1.0 - zf * invH;
+    T Nv[D];
+    Nv[0] = -gzz * (hx * omf);
+    if constexpr (D == 3) Nv[1] = -gzz * (hy * omf);
+    Nv[D - 1] = gzz;
+    const T sign = s ? 1.0 : -1.0;
+    T F[NV], phi[NV];
+    if (kind[f] == kConf) {
+      if (s) rusanov<D>(tm, tn[f], Nv, F);
+      else rusanov<D>(tn[f], tm, Nv, F);
+#pragma unroll
+      for (int o = 0; o < NV; ++o) phi[o] = -sign * F[o];
+    } else {
+      T No[D];
+#pragma unroll
+      for (int l = 0; l < D; ++l) No[l] = sign * Nv[l];
+      wall_flux<D>(tm, No, F);
+#pragma unroll
+      for (int o = 0; o < NV; ++o) phi[o] = -F[o];
+    }
+#pragma unroll
+    for (int o = 0; o < NV; ++o)
+#pragma unroll
+      for (int z = 0; z < NP; ++z) acc[o][z] += Lbwu[s * NP + z] * phi[o];
+  }
+#pragma unroll
+  for (int o = 0; o < NV; ++o)
+#pragma unroll
+    for (int z = 0; z < NP; ++z) pin(acc[o][z]);
+
+  __syncthreads();
+
+  // ---------------------------------------------------------------- horizontal contractions
+  // along axis k < d-1 the flux through faces of constant xi_k is Gam[k][k] m_k (1, u, k)
+  const T g00 = D == 3 ? hb : 1.0;
+#pragma unroll
+  for (int z = 0; z < NP; ++z) {
+#pragma unroll
+    for (int k = 0; k < NH; ++k) {
+      const int ik = k == 0 ? i0 : i1;
+      const T gk = k == 0 ? g00 : ha;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        const int col = k == 0 ? q + NP * i1 : i0 + NP * q;
+        const int node = col + NC * z;
+        T mm[D];
+#pragma unroll
+        for (int l = 0; l < D; ++l) mm[l] = sX[lc][1 + l][node];
+        const T r1 = sX[lc][NV][node];
+        const T fl = Dt[ik * NP + q] * (gk * sFc[lc][col] * mm[k]);  // D~ Gam m_k
+        const T flr = fl * r1;
+        T m2 = 0;
+#pragma unroll
+        for (int l = 0; l < D; ++l) m2 += mm[l] * mm[l];
+        acc[0][z] += fl;
+#pragma unroll
+        for (int l = 0; l < D; ++l) acc[1 + l][z] += flr * mm[l];
+        acc[NV - 1][z] += flr * (0.5 * m2 * r1);
+      }
+#pragma unroll
+      for (int o = 0; o < NV; ++o) pin(acc[o][z]);
+    }
+  }
+  // ---------------------------------------------------------------- x / y faces: flux at point c
+  T phx[NH][2][NV];
+#pragma unroll
+  for (int k = 0; k < NH; ++k) {
+    const int jt = c % NP;
+    T line[NV][NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+      for (int g = 0; g < NV; ++g) line[g][q] = sX[lc][g][offs<D, NP>(k, q, c)];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int f = 2 * k + s;
+      T tm[NV];
+#pragma unroll
+      for (int g = 0; g < NV; ++g) {
+        T t = 0;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) t += Lbu[s * NP + q] * line[g][q];
+        tm[g] = t;
+      }
+      const T Nk = (D == 3 ? (k == 0 ? hb : ha) : 1.0) * sHf[lc][k][s][D == 3 ? jt : 0];
+      T Nv[D];
+#pragma unroll
+      for (int l = 0; l < D; ++l) Nv[l] = l == k ? Nk : 0.0;
+      const T sign = s ? 1.0 : -1.0;
+      T F[NV];
+      if (kind[f] == kConf) {
+        if (s) rusanov<D>(tm, tn[f], Nv, F);
+        else rusanov<D>(tn[f], tm, Nv, F);
+#pragma unroll
+        for (int o = 0; o < NV; ++o) phx[k][s][o] = -sign * F[o];
+      } else {
+        T No[D];
+#pragma unroll
+        for (int l = 0; l < D; ++l) No[l] = sign * Nv[l];
+        wall_flux<D>(tm, No, F);
+#pragma unroll
+        for (int o = 0; o < NV; ++o) phx[k][s][o] = -F[o];
+      }
+    }
+  }
+  __syncthreads();  // every read of the field buffer is done: it now takes the fluxes
+  if (lane) {
+#pragma unroll
+    for (int k = 0; k < NH; ++k)
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int o = 0; o < NV; ++o) sPhi[lc][2 * k + s][o][c] = phx[k][s][o];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NH; ++k) {
+    const int ik = k == 0 ? i0 : i1;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const T lw = Lbw[s * NP + ik];
+#pragma unroll
+      for (int z = 0; z < NP; ++z) {
+        const int ap = D == 3 ? (k == 0 ? i1 : i0) + NP * z : z;
+#pragma unroll
+        for (int o = 0; o < NV; ++o) acc[o][z] += lw * sPhi[lc][2 * k + s][o][ap];
+      }
+    }
+  }
+
+  // ---------------------------------------------------------------- finalize
+  if (!active) return;
+  const T iJ = 1.0 / ((D == 3 ? ha * hb : ha) * fcol);
+#pragma unroll
+  for (int z = 0; z < NP; ++z) {
+    const unsigned idx = base + NC * z;
+#pragma unroll
+    for (int o = 0; o < NV - 1; ++o) R[o * N + idx] = acc[o][z] * iJ;
+    R[(NV - 1) * N + idx] = acc[NV - 1][z] * iJ - kG * u[D][z];
+  }
+}
+
+template <int D, int NP>
+int run_col_exp(const double* U, double* R, const MeshDev& m, hipStream_t s) {
+  using C = Col<D, NP>;
+  if (m.nreg <= 0) return 0;
+  const int grid = (m.ncell + C::CPB - 1) / C::CPB;
+  hipLaunchKernelGGL((k_col_exp<D, NP>), dim3(grid), dim3(C::NT), 0, s, U, R, m);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
 // Cell-wise fast-diagonalisation preconditioner in the column layout:
 // z = (1/Jbar) (S x S x S) diag(1 / (1/(gamma-1) + sum_k alpha_k mu_{i_k})) (S x S x S)^T (scale v).
 // The vertical transforms stay in the thread's registers, the horizontal ones go through LDS.
@@ -605,7 +932,21 @@ int fdm_col(const MeshDev& m, int degree, const FdmArgs<T>& a, hipStream_t s) {
   }
 }
 
+int exp_col(const MeshDev& m, int degree, const double* U, double* R, hipStream_t s) {
+  if (m.dim == 2) {
+    DG_COL_DISPATCH(return (run_col_exp<2, NP>(U, R, m, s)));
+  } else {
+    DG_COL_DISPATCH(return (run_col_exp<3, NP>(U, R, m, s)));
+  }
+}
+
 }  // namespace
+
+int launch_explicit(const MeshDev& m, int degree, const double* U, double* R, hipStream_t s) {
+  int r = exp_col(m, degree, U, R, s);
+  if (r == 0) r = launch_explicit_cells(m, degree, U, R, m.irr, m.nirr, s);
+  return r;
+}
 
 int launch_fdm64(const MeshDev& m, int degree, const FdmArgs<double>& a, hipStream_t s) {
   return fdm_col<double>(m, degree, a, s);

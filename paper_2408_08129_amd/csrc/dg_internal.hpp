@@ -108,6 +108,8 @@ int launch_grad_cells64(const MeshDev& m, int degree, const GradArgs<double>& a,
 int launch_div_cells64(const MeshDev& m, int degree, const DivArgs<double>& a, const int* list, int n, hipStream_t s);
 int launch_grad_cells32(const MeshDev& m, int degree, const GradArgs<float>& a, const int* list, int n, hipStream_t s);
 int launch_div_cells32(const MeshDev& m, int degree, const DivArgs<float>& a, const int* list, int n, hipStream_t s);
+int launch_explicit_cells(const MeshDev& m, int degree, const double* U, double* R, const int* list, int n,
+                          hipStream_t s);
 int launch_explicit(const MeshDev& m, int degree, const double* U, double* R, hipStream_t s);
 int launch_grad64(const MeshDev& m, int degree, const GradArgs<double>& a, hipStream_t s);
 int launch_div64(const MeshDev& m, int degree, const DivArgs<double>& a, hipStream_t s);

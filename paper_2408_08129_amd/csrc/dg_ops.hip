@@ -19,47 +19,6 @@ namespace dg {
 namespace {
 using namespace dev;
 
-// ----------------------------------------------------------------------------------- fluxes
-template <int D>
-__device__ __forceinline__ void adv_flux_n(const double* U, const double* N, double* F) {
-  double mn = 0.0, m2 = 0.0;
-#pragma unroll
-  for (int l = 0; l < D; ++l) { mn += U[1 + l] * N[l]; m2 += U[1 + l] * U[1 + l]; }
-  const double un = mn / U[0];
-  F[0] = mn;
-#pragma unroll
-  for (int l = 0; l < D; ++l) F[1 + l] = U[1 + l] * un;
-  F[1 + D] = 0.5 * m2 / U[0] * un;
-}
-
-// Rusanov flux with the advective speed (acoustics are treated implicitly).
-template <int D>
-__device__ __forceinline__ void rusanov(const double* UL, const double* UR, const double* N, double* F) {
-  double FL[D + 2], FR[D + 2];
-  adv_flux_n<D>(UL, N, FL);
-  adv_flux_n<D>(UR, N, FR);
-  double vl = 0.0, vr = 0.0;
-#pragma unroll
-  for (int l = 0; l < D; ++l) { vl += UL[1 + l] * N[l]; vr += UR[1 + l] * N[l]; }
-  const double lam = fmax(fabs(vl / UL[0]), fabs(vr / UR[0]));
-#pragma unroll
-  for (int f = 0; f < D + 2; ++f) F[f] = 0.5 * (FL[f] + FR[f]) - 0.5 * lam * (UR[f] - UL[f]);
-}
-
-// Slip wall: Rusanov against the mirror state, simplified: no mass and energy flux, momentum
-// (m.N)(v + |v|) N / |N|^2 with v = (m.N)/rho, N the outward area-weighted normal.
-template <int D>
-__device__ __forceinline__ void wall_flux(const double* U, const double* N, double* F) {
-  double mn = 0.0, nn = 0.0;
-#pragma unroll
-  for (int l = 0; l < D; ++l) { mn += U[1 + l] * N[l]; nn += N[l] * N[l]; }
-  const double v = mn / U[0];
-  F[0] = 0.0;
-#pragma unroll
-  for (int l = 0; l < D; ++l) F[1 + l] = mn * (v + fabs(v)) * N[l] / nn;
-  F[1 + D] = 0.0;
-}
-
 // ------------------------------------------------------------------------------------- ops
 template <int D>
 struct OpExplicit {
@@ -715,9 +674,8 @@ int run(const Op& op, const MeshDev& m, const int* list, int n, hipStream_t s) {
     default: return -6;                        \
   }
 
-int launch_explicit(const MeshDev& m, int degree, const double* U, double* R, hipStream_t s) {
-  const int* list = nullptr;
-  const int n = m.ncell;
+int launch_explicit_cells(const MeshDev& m, int degree, const double* U, double* R, const int* list, int n,
+                          hipStream_t s) {
   if (m.dim == 2) {
     OpExplicit<2> op{U, R, (unsigned)m.N};
     DG_DISPATCH(2, degree, return (run<2, NP>(op, m, list, n, s)));
