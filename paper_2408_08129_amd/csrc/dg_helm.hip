@@ -1,6 +1,8 @@
-// Column kernels of the two Helmholtz passes (arXiv 2408.08129, Section 3.2: the weak gradient
-// M^{-1} B and the weak divergence C with the pressure-jump penalty) on the cells whose faces are
-// all conforming or walls.  Cells with a 2:1 face go through the general cell kernel.
+// Column kernels of the cell operators (arXiv 2408.08129, Section 3.2): the two Helmholtz passes
+// (the weak gradient M^{-1} B and the weak divergence C with the pressure-jump penalty), the
+// explicit advective residual and the cell-wise preconditioner.  They cover every cell; a 2:1
+// face contributes nothing here, and the general cell kernel adds the terms of those faces for
+// the cells that have one (its faces-only mode).
 //
 // Layout: one thread owns one vertical column of a cell (NP nodes, the last, vertical axis is the
 // slowest in the node order), so a cell is NP^(d-1) threads and a 256-thread workgroup holds
@@ -87,17 +89,14 @@ __global__ void __launch_bounds__(256) k_col(const A a, const MeshDev m) {
 
   // ---------------------------------------------------------------- loads
   const int4 ci = m.cell[cell];
+  // 2:1 faces contribute nothing here: the general kernel adds their terms afterwards
   int kind[NF], nb[NF];
-  bool regular = true;
 #pragma unroll
   for (int f = 0; f < NF; ++f) {
     kind[f] = m.fkind[cell * NF + f];
     nb[f] = m.fnbr[cell * NF + f].x;
-    regular = regular && (kind[f] == kConf || kind[f] == kWall);
   }
-  // cells with a 2:1 face run through the same code (gathers only cross conforming faces) but
-  // store nothing; the general cell kernel owns them
-  const bool active = lane && pos < m.ncell && regular;
+  const bool active = lane && pos < m.ncell;
   const unsigned base = (unsigned)cell * NL + c;
   T pv[NP];            // grad: p; div: p (penalty / mass)
   T wv[D][NP];         // div: h qv
@@ -322,7 +321,7 @@ __global__ void __launch_bounds__(256) k_col(const A a, const MeshDev m) {
 #pragma unroll
       for (int z = 0; z < NP; ++z) acc[0][z] += Lbwu[s * NP + z] * v;
     } else {
-      T ph = tm[D];
+      T ph = kind[f] == kWall ? tm[D] : T(0);
       if (conf) ph = s ? T(0.5) * (tm[D] + tn[f][D]) : T(0.5) * (tn[f][D] + tm[D]);
 #pragma unroll
       for (int l = 0; l < D; ++l) {
@@ -374,7 +373,7 @@ __global__ void __launch_bounds__(256) k_col(const A a, const MeshDev m) {
           }
         }
       } else {
-        T ph = tmp;
+        T ph = kind[f] == kWall ? tmp : T(0);
         if (conf) ph = s ? T(0.5) * (tmp + tn[f][D]) : T(0.5) * (tn[f][D] + tmp);
         phi = sign * ph * Nk;
       }
@@ -426,7 +425,7 @@ __global__ void __launch_bounds__(256) k_col(const A a, const MeshDev m) {
 template <int D, int NP, class T, bool DIV, class A>
 int run_col(const A& a, const MeshDev& m, hipStream_t s) {
   using C = Col<D, NP>;
-  if (m.nreg <= 0) return 0;
+  if (m.ncell <= 0) return 0;
   const int grid = (m.ncell + C::CPB - 1) / C::CPB;
   hipLaunchKernelGGL((k_col<D, NP, T, DIV, A>), dim3(grid), dim3(C::NT), 0, s, a, m);
   return hipGetLastError() == hipSuccess ? 0 : -3;
@@ -471,15 +470,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 
   // ---------------------------------------------------------------- loads
   const int4 ci = m.cell[cell];
+  // 2:1 faces contribute nothing here: the general kernel adds their terms afterwards
   int kind[NF], nb[NF];
-  bool regular = true;
 #pragma unroll
   for (int f = 0; f < NF; ++f) {
     kind[f] = m.fkind[cell * NF + f];
     nb[f] = m.fnbr[cell * NF + f].x;
-    regular = regular && (kind[f] == kConf || kind[f] == kWall);
   }
-  const bool active = lane && pos < m.ncell && regular;
+  const bool active = lane && pos < m.ncell;
   const unsigned base = (unsigned)cell * NL + c;
   T u[NV][NP];
 #pragma unroll
@@ -620,6 +618,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
       else rusanov<D>(tn[f], tm, Nv, F);
 #pragma unroll
       for (int o = 0; o < NV; ++o) phi[o] = -sign * F[o];
+    } else if (kind[f] != kWall) {
+#pragma unroll
+      for (int o = 0; o < NV; ++o) phi[o] = 0;
     } else {
       T No[D];
 #pragma unroll
@@ -703,6 +704,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         else rusanov<D>(tn[f], tm, Nv, F);
 #pragma unroll
         for (int o = 0; o < NV; ++o) phx[k][s][o] = -sign * F[o];
+      } else if (kind[f] != kWall) {
+#pragma unroll
+        for (int o = 0; o < NV; ++o) phx[k][s][o] = 0;
       } else {
         T No[D];
 #pragma unroll
@@ -753,7 +757,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 template <int D, int NP>
 int run_col_exp(const double* U, double* R, const MeshDev& m, hipStream_t s) {
   using C = Col<D, NP>;
-  if (m.nreg <= 0) return 0;
+  if (m.ncell <= 0) return 0;
   const int grid = (m.ncell + C::CPB - 1) / C::CPB;
   hipLaunchKernelGGL((k_col_exp<D, NP>), dim3(grid), dim3(C::NT), 0, s, U, R, m);
   return hipGetLastError() == hipSuccess ? 0 : -3;
@@ -944,7 +948,7 @@ int exp_col(const MeshDev& m, int degree, const double* U, double* R, hipStream_
 
 int launch_explicit(const MeshDev& m, int degree, const double* U, double* R, hipStream_t s) {
   int r = exp_col(m, degree, U, R, s);
-  if (r == 0) r = launch_explicit_cells(m, degree, U, R, m.irr, m.nirr, s);
+  if (r == 0) r = launch_explicit_hang(m, degree, U, R, s);
   return r;
 }
 
@@ -956,30 +960,30 @@ int launch_fdm32(const MeshDev& m, int degree, const FdmArgs<float>& a, hipStrea
 }
 
 // p given (no Jacobi scaling, no copy of p requested) and, for the divergence, h folded into the
-// vector field: column kernel on the conforming cells, cell kernel on the rest; otherwise the
+// vector field: the column kernel on every cell, then the 2:1 face terms; otherwise the general
 // cell kernel on every cell.
 int launch_grad64(const MeshDev& m, int degree, const GradArgs<double>& a, hipStream_t s) {
   if (a.dinv || a.z) return launch_grad_cells64(m, degree, a, nullptr, m.ncell, s);
   int r = grad_col<double>(m, degree, a, s);
-  if (r == 0) r = launch_grad_cells64(m, degree, a, m.irr, m.nirr, s);
+  if (r == 0) r = launch_grad_hang64(m, degree, a, s);
   return r;
 }
 int launch_div64(const MeshDev& m, int degree, const DivArgs<double>& a, hipStream_t s) {
   if (a.dinv || a.h || !a.p) return launch_div_cells64(m, degree, a, nullptr, m.ncell, s);
   int r = div_col<double>(m, degree, a, s);
-  if (r == 0) r = launch_div_cells64(m, degree, a, m.irr, m.nirr, s);
+  if (r == 0) r = launch_div_hang64(m, degree, a, s);
   return r;
 }
 int launch_grad32(const MeshDev& m, int degree, const GradArgs<float>& a, hipStream_t s) {
   if (a.dinv || a.z) return launch_grad_cells32(m, degree, a, nullptr, m.ncell, s);
   int r = grad_col<float>(m, degree, a, s);
-  if (r == 0) r = launch_grad_cells32(m, degree, a, m.irr, m.nirr, s);
+  if (r == 0) r = launch_grad_hang32(m, degree, a, s);
   return r;
 }
 int launch_div32(const MeshDev& m, int degree, const DivArgs<float>& a, hipStream_t s) {
   if (a.dinv || a.h || !a.p) return launch_div_cells32(m, degree, a, nullptr, m.ncell, s);
   int r = div_col<float>(m, degree, a, s);
-  if (r == 0) r = launch_div_cells32(m, degree, a, m.irr, m.nirr, s);
+  if (r == 0) r = launch_div_hang32(m, degree, a, s);
   return r;
 }
 

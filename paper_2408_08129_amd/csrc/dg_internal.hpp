@@ -102,14 +102,19 @@ struct FdmArgs {
 };
 
 // --------------------------------------------------------------------------------- launchers
-// Weak gradient / divergence: the column kernel on the cells with conforming faces, the general
-// cell kernel on the cells with 2:1 faces.
+// Weak gradient / divergence on a list of cells with the general cell kernel.
 int launch_grad_cells64(const MeshDev& m, int degree, const GradArgs<double>& a, const int* list, int n, hipStream_t s);
 int launch_div_cells64(const MeshDev& m, int degree, const DivArgs<double>& a, const int* list, int n, hipStream_t s);
 int launch_grad_cells32(const MeshDev& m, int degree, const GradArgs<float>& a, const int* list, int n, hipStream_t s);
 int launch_div_cells32(const MeshDev& m, int degree, const DivArgs<float>& a, const int* list, int n, hipStream_t s);
 int launch_explicit_cells(const MeshDev& m, int degree, const double* U, double* R, const int* list, int n,
                           hipStream_t s);
+// the 2:1 face terms of the cells with such faces, added to outputs the column kernels wrote
+int launch_grad_hang64(const MeshDev& m, int degree, const GradArgs<double>& a, hipStream_t s);
+int launch_div_hang64(const MeshDev& m, int degree, const DivArgs<double>& a, hipStream_t s);
+int launch_grad_hang32(const MeshDev& m, int degree, const GradArgs<float>& a, hipStream_t s);
+int launch_div_hang32(const MeshDev& m, int degree, const DivArgs<float>& a, hipStream_t s);
+int launch_explicit_hang(const MeshDev& m, int degree, const double* U, double* R, hipStream_t s);
 int launch_explicit(const MeshDev& m, int degree, const double* U, double* R, hipStream_t s);
 int launch_grad64(const MeshDev& m, int degree, const GradArgs<double>& a, hipStream_t s);
 int launch_div64(const MeshDev& m, int degree, const DivArgs<double>& a, hipStream_t s);

@@ -81,6 +81,12 @@ struct OpExplicit {
     for (int o = 0; o < NOUT; ++o) R[o * N + idx] = acc[o] * iJ;
     R[(1 + D) * N + idx] = acc[1 + D] * iJ - kG * tr[D];
   }
+  // adds the lifted 2:1 face terms to an output the column kernel has written
+  __device__ __forceinline__ void finalize_add(unsigned idx, const T* acc, T, T J) const {
+    const T iJ = T(1) / J;
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) R[o * N + idx] += acc[o] * iJ;
+  }
 };
 
 template <int D, class TT>
@@ -124,6 +130,12 @@ struct OpGrad {
 #pragma unroll
     for (int l = 0; l < D; ++l) a.q[l * N + idx] = acc[l] * iJ;
     if (a.z) a.z[idx] = tr[0];
+  }
+  __device__ __forceinline__ void finalize_add(unsigned idx, const T* acc, T, T J) const {
+    T iJ = T(1) / J;
+    if (a.h) iJ *= a.h[idx];
+#pragma unroll
+    for (int l = 0; l < D; ++l) a.q[l * N + idx] += acc[l] * iJ;
   }
 };
 
@@ -184,6 +196,10 @@ struct OpDiv {
   __device__ __forceinline__ void finalize(unsigned idx, const T* acc, T w, T J, const T* tr) const {
     if (a.weak) a.out[idx] = w * (acc[0] + a.amass * J * tr[D]);
     else a.out[idx] = acc[0] / J;
+  }
+  __device__ __forceinline__ void finalize_add(unsigned idx, const T* acc, T w, T J) const {
+    if (a.weak) a.out[idx] += w * acc[0];
+    else a.out[idx] += acc[0] / J;
   }
   __device__ __forceinline__ T lam(int cell) const { return a.lam ? a.lam[cell] : T(0); }
 };
@@ -275,7 +291,9 @@ struct TerTab {
 //   P3 only for faces with a 2:1 neighbour: neighbour traces, sub-face fluxes, restriction
 //      (coarse side) / interpolation (fine side);
 //   P4 lift of all faces along the normal lines, finalize.
-template <int D, int NP, class Op>
+// With HANG, only the 2:1 faces are evaluated and their lifted terms are added to the output
+// (the column kernels have written the rest for these cells).
+template <int D, int NP, class Op, bool HANG>
 __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const MeshDev m,
                                                              const int* __restrict__ list, int n) {
   using C = Cfg<D, NP>;
@@ -411,13 +429,15 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
       const T* te = &sTer[(lc * NH + col) * 3];
       T Gam[D][D];
       metric_h<D, T>(m, ci.x, te[0], te[1], te[2], zeta, Gam, Jn);
-      T G[NOUT][D];
-      op.vol(trn, Gam, G);
+      if constexpr (!HANG) {
+        T G[NOUT][D];
+        op.vol(trn, Gam, G);
 #pragma unroll
-      for (int o = 0; o < NOUT; ++o)
+        for (int o = 0; o < NOUT; ++o)
 #pragma unroll
-        for (int k = 0; k < D; ++k)
-          if (Op::vidx(o, k) >= 0) sScr[(lc * NVOL + Op::vidx(o, k)) * NL + node] = G[o][k];
+          for (int k = 0; k < D; ++k)
+            if (Op::vidx(o, k) >= 0) sScr[(lc * NVOL + Op::vidx(o, k)) * NL + node] = G[o][k];
+      }
     }
   }
   for (int t = tid; t < CPB * NF * NFP; t += NT) {
@@ -443,7 +463,7 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
   T acc[NOUT];
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) acc[o] = 0;
-  if (active) {
+  if (active && !HANG) {
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       const int ik = along<D, NP>(node, k);
@@ -463,6 +483,12 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
     if (sId[c] < 0) continue;
     const int kind = sKind[c][f];
     if (kind != kConf && kind != kWall) continue;
+    if constexpr (HANG) {
+      // conforming and wall faces belong to the column kernel
+#pragma unroll
+      for (int o = 0; o < NOUT; ++o) sFr[((c * NF + f) * NOUT + o) * NFP + j] = 0;
+      continue;
+    }
     const int k = f >> 1, s = f & 1;
     T tm[NTR], tn[NTR];
 #pragma unroll
@@ -649,16 +675,17 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
 #pragma unroll
       for (int o = 0; o < NOUT; ++o) acc[o] += lw * sFr[((lc * NF + f) * NOUT + o) * NFP + a];
     }
-    op.finalize((unsigned)cell * NL + node, acc, wn, Jn, trn);
+    if constexpr (HANG) op.finalize_add((unsigned)cell * NL + node, acc, wn, Jn);
+    else op.finalize((unsigned)cell * NL + node, acc, wn, Jn, trn);
   }
 }
 
-template <int D, int NP, class Op>
+template <int D, int NP, class Op, bool HANG = false>
 int run(const Op& op, const MeshDev& m, const int* list, int n, hipStream_t s) {
   using C = Cfg<D, NP>;
   if (n <= 0) return 0;
   const int grid = (n + C::CPB - 1) / C::CPB;
-  hipLaunchKernelGGL((k_cell<D, NP, Op>), dim3(grid), dim3(C::NT), 0, s, op, m, list, n);
+  hipLaunchKernelGGL((k_cell<D, NP, Op, HANG>), dim3(grid), dim3(C::NT), 0, s, op, m, list, n);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -684,26 +711,37 @@ int launch_explicit_cells(const MeshDev& m, int degree, const double* U, double*
     DG_DISPATCH(3, degree, return (run<3, NP>(op, m, list, n, s)));
   }
 }
-
-template <class T>
-static int grad_impl(const MeshDev& m, int degree, const GradArgs<T>& a, const int* list, int n, hipStream_t s) {
+int launch_explicit_hang(const MeshDev& m, int degree, const double* U, double* R, hipStream_t s) {
+  const int* list = m.irr;
+  const int n = m.nirr;
   if (m.dim == 2) {
-    OpGrad<2, T> op{a, (unsigned)m.N};
-    DG_DISPATCH(2, degree, return (run<2, NP>(op, m, list, n, s)));
+    OpExplicit<2> op{U, R, (unsigned)m.N};
+    DG_DISPATCH(2, degree, return (run<2, NP, OpExplicit<2>, true>(op, m, list, n, s)));
   } else {
-    OpGrad<3, T> op{a, (unsigned)m.N};
-    DG_DISPATCH(3, degree, return (run<3, NP>(op, m, list, n, s)));
+    OpExplicit<3> op{U, R, (unsigned)m.N};
+    DG_DISPATCH(3, degree, return (run<3, NP, OpExplicit<3>, true>(op, m, list, n, s)));
   }
 }
 
-template <class T>
+template <class T, bool HANG = false>
+static int grad_impl(const MeshDev& m, int degree, const GradArgs<T>& a, const int* list, int n, hipStream_t s) {
+  if (m.dim == 2) {
+    OpGrad<2, T> op{a, (unsigned)m.N};
+    DG_DISPATCH(2, degree, return (run<2, NP, OpGrad<2, T>, HANG>(op, m, list, n, s)));
+  } else {
+    OpGrad<3, T> op{a, (unsigned)m.N};
+    DG_DISPATCH(3, degree, return (run<3, NP, OpGrad<3, T>, HANG>(op, m, list, n, s)));
+  }
+}
+
+template <class T, bool HANG = false>
 static int div_impl(const MeshDev& m, int degree, const DivArgs<T>& a, const int* list, int n, hipStream_t s) {
   if (m.dim == 2) {
     OpDiv<2, T> op{a, (unsigned)m.N};
-    DG_DISPATCH(2, degree, return (run<2, NP>(op, m, list, n, s)));
+    DG_DISPATCH(2, degree, return (run<2, NP, OpDiv<2, T>, HANG>(op, m, list, n, s)));
   } else {
     OpDiv<3, T> op{a, (unsigned)m.N};
-    DG_DISPATCH(3, degree, return (run<3, NP>(op, m, list, n, s)));
+    DG_DISPATCH(3, degree, return (run<3, NP, OpDiv<3, T>, HANG>(op, m, list, n, s)));
   }
 }
 
@@ -718,6 +756,18 @@ int launch_grad_cells32(const MeshDev& m, int degree, const GradArgs<float>& a, 
 }
 int launch_div_cells32(const MeshDev& m, int degree, const DivArgs<float>& a, const int* list, int n, hipStream_t s) {
   return div_impl<float>(m, degree, a, list, n, s);
+}
+int launch_grad_hang64(const MeshDev& m, int degree, const GradArgs<double>& a, hipStream_t s) {
+  return grad_impl<double, true>(m, degree, a, m.irr, m.nirr, s);
+}
+int launch_div_hang64(const MeshDev& m, int degree, const DivArgs<double>& a, hipStream_t s) {
+  return div_impl<double, true>(m, degree, a, m.irr, m.nirr, s);
+}
+int launch_grad_hang32(const MeshDev& m, int degree, const GradArgs<float>& a, hipStream_t s) {
+  return grad_impl<float, true>(m, degree, a, m.irr, m.nirr, s);
+}
+int launch_div_hang32(const MeshDev& m, int degree, const DivArgs<float>& a, hipStream_t s) {
+  return div_impl<float, true>(m, degree, a, m.irr, m.nirr, s);
 }
 
 // ------------------------------------------------------------------ per-cell coefficients
