@@ -68,37 +68,32 @@ def run_gpu(w, precision, steps, warmup, timing=True):
 
 
 KERNEL_NAMES = {
-    "explicit_residual": "k_cell<OpExplicit> (explicit residual)",
-    "weak_gradient": "k_cell<OpGrad> (Helmholtz pass 1: h M^-1 B p)",
-    "weak_divergence": "k_cell<OpDiv> (Helmholtz pass 2: C w, penalty, mass)",
+    "explicit_residual": "k_col_exp + 2:1 faces pass of k_cell<OpExplicit> (explicit residual)",
+    "weak_gradient": "k_col<grad> + 2:1 faces pass of k_cell<OpGrad> (Helmholtz pass 1: h M^-1 B p)",
+    "weak_divergence": "k_col<div> + 2:1 faces pass of k_cell<OpDiv> (Helmholtz pass 2: C w, penalty, mass)",
     "gs_dots": "k_gs_dots (Gram-Schmidt reduction pass)",
     "gs_update": "k_gs_update (Gram-Schmidt update pass)",
 }
+SOURCES = ("dg_ops.hip", "dg_helm.hip", "dg_solver.hip", "dg_internal.hpp", "dg_device.hpp")
 
 
-PROFILE_KEYS = {
-    "explicit_residual": "k_cell<OpExplicit>",
-    "weak_gradient": "k_cell<OpGrad<double>>",
-    "weak_divergence": "k_cell<OpDiv<double>>",
-    "gs_dots": "k_mdot_norm<double>",
-    "gs_update": "k_axpy_norm<double>",
-}
+def source_sha256():
+    import hashlib
+    src = b"".join(open(os.path.join(ROOT, "paper_2408_08129_amd", "csrc", f), "rb").read() for f in SOURCES)
+    return hashlib.sha256(src).hexdigest()
 
 
 def measured_traffic(cls, workload):
     """HBM bytes per launch of a kernel class from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
     summary (calibrated against a plain copy), or None if absent or if the kernel sources changed
     since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = b"".join(open(os.path.join(ROOT, "paper_2408_08129_amd", "csrc", f), "rb").read()
-                   for f in ("dg_ops.hip", "dg_solver.hip", "dg_internal.hpp"))
-    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+    if source_sha256() != rec.get("source_sha256"):
         return None
-    k = rec["kernels"].get(PROFILE_KEYS.get(cls, ""))
+    k = rec.get("classes", {}).get(cls)
     return k["hbm_bytes_per_launch"] if k else None
 
 
