@@ -32,17 +32,20 @@ struct Col {
   static constexpr int NHC = D == 3 ? NP : 1;  // terrain samples per x / y face
 };
 
-// Input fields at node idx.  These kernels take p as given (no Jacobi scaling) and, for the
-// divergence, the vector field already multiplied by h; the general cell kernel covers the rest.
+// Input fields at node idx.  These kernels take p as given (no Jacobi scaling; the general cell
+// kernel covers that form).  Divergence: w = h qv with the multiplier h when HH (then p may be
+// absent), else the vector field already multiplied by h.
 template <class T>
 __device__ __forceinline__ T grad_in(const GradArgs<T>& a, unsigned idx) {
   return a.p[idx];
 }
-template <int D, class T>
+template <int D, class T, bool HH>
 __device__ __forceinline__ void div_in(const DivArgs<T>& a, unsigned N, unsigned idx, int mask, T* w, T& p) {
+  const T h = HH ? a.h[idx] : T(1);
 #pragma unroll
-  for (int l = 0; l < D; ++l) w[l] = ((mask >> l) & 1) ? a.qv[l * N + idx] : T(0);
-  p = a.p[idx];
+  for (int l = 0; l < D; ++l) w[l] = ((mask >> l) & 1) ? (HH ? h * a.qv[l * N + idx] : a.qv[l * N + idx]) : T(0);
+  if (HH) p = a.p ? a.p[idx] : T(0);
+  else p = a.p[idx];
 }
 
 // Materialise a value at this point of the program: keeps the compiler from sinking arithmetic
@@ -58,7 +61,7 @@ __device__ __forceinline__ int offs(int k, int q, int a) {
   return compose<D, NP>(k, q, a);
 }
 
-template <int D, int NP, class T, bool DIV, class A>
+template <int D, int NP, class T, bool DIV, class A, bool HH = false>
 __global__ void __launch_bounds__(256) k_col(const A a, const MeshDev m) {
   using C = Col<D, NP>;
   constexpr int NC = C::NC, NL = C::NL, NF = C::NF, CPB = C::CPB, NHC = C::NHC;
@@ -104,7 +107,7 @@ __global__ void __launch_bounds__(256) k_col(const A a, const MeshDev m) {
   for (int z = 0; z < NP; ++z) {
     if constexpr (DIV) {
       T w[D];
-      div_in<D, T>(a, N, base + NC * z, (1 << D) - 1, w, pv[z]);
+      div_in<D, T, HH>(a, N, base + NC * z, (1 << D) - 1, w, pv[z]);
 #pragma unroll
       for (int l = 0; l < D; ++l) wv[l][z] = w[l];
     } else {
@@ -127,7 +130,7 @@ __global__ void __launch_bounds__(256) k_col(const A a, const MeshDev m) {
       const unsigned idx = nbase + offs<D, NP>(k, q, c);
       if constexpr (DIV) {
         T w[D], p;
-        div_in<D, T>(a, N, idx, mask, w, p);
+        div_in<D, T, HH>(a, N, idx, mask, w, p);
 #pragma unroll
         for (int l = 0; l < D; ++l) tn[f][l] += lq * w[l];
         tn[f][D] += lq * p;
@@ -422,12 +425,12 @@ __global__ void __launch_bounds__(256) k_col(const A a, const MeshDev m) {
   }
 }
 
-template <int D, int NP, class T, bool DIV, class A>
+template <int D, int NP, class T, bool DIV, class A, bool HH = false>
 int run_col(const A& a, const MeshDev& m, hipStream_t s) {
   using C = Col<D, NP>;
   if (m.ncell <= 0) return 0;
   const int grid = (m.ncell + C::CPB - 1) / C::CPB;
-  hipLaunchKernelGGL((k_col<D, NP, T, DIV, A>), dim3(grid), dim3(C::NT), 0, s, a, m);
+  hipLaunchKernelGGL((k_col<D, NP, T, DIV, A, HH>), dim3(grid), dim3(C::NT), 0, s, a, m);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -918,12 +921,12 @@ int grad_col(const MeshDev& m, int degree, const GradArgs<T>& a, hipStream_t s) 
     DG_COL_DISPATCH(return (run_col<3, NP, T, false>(a, m, s)));
   }
 }
-template <class T>
+template <class T, bool HH = false>
 int div_col(const MeshDev& m, int degree, const DivArgs<T>& a, hipStream_t s) {
   if (m.dim == 2) {
-    DG_COL_DISPATCH(return (run_col<2, NP, T, true>(a, m, s)));
+    DG_COL_DISPATCH(return (run_col<2, NP, T, true, DivArgs<T>, HH>(a, m, s)));
   } else {
-    DG_COL_DISPATCH(return (run_col<3, NP, T, true>(a, m, s)));
+    DG_COL_DISPATCH(return (run_col<3, NP, T, true, DivArgs<T>, HH>(a, m, s)));
   }
 }
 
@@ -969,8 +972,8 @@ int launch_grad64(const MeshDev& m, int degree, const GradArgs<double>& a, hipSt
   return r;
 }
 int launch_div64(const MeshDev& m, int degree, const DivArgs<double>& a, hipStream_t s) {
-  if (a.dinv || a.h || !a.p) return launch_div_cells64(m, degree, a, nullptr, m.ncell, s);
-  int r = div_col<double>(m, degree, a, s);
+  if (a.dinv || (!a.h && !a.p)) return launch_div_cells64(m, degree, a, nullptr, m.ncell, s);
+  int r = a.h ? div_col<double, true>(m, degree, a, s) : div_col<double>(m, degree, a, s);
   if (r == 0) r = launch_div_hang64(m, degree, a, s);
   return r;
 }
