@@ -15,7 +15,12 @@ paper (Orlando, Benacchio, Bonaventura, arXiv 2408.08129):
 * Section 3.2: each implicit stage runs a fixed-point loop for the pressure whose linear system is
   non-symmetric and solved with GMRES, applying the operators matrix-free;
 * Section 3.1, Eq. (4)-(5): the stratified initial state (with the factor g^2 / N^2 that makes it
-  hydrostatic), or an isothermal atmosphere.
+  hydrostatic), or an isothermal atmosphere;
+* Section 3.1: the test runs with non-reflecting top and lateral boundaries whose form the paper
+  defers to cited work.  Reading used here: absorbing layers of Rayleigh friction on the momentum,
+  d m / dt = -tau (m - rho u_ref e_x), explicit, with the sin^2 rate profile of Klemp and Lilly
+  (1978) below the lid and along walled lateral boundaries (mass and total energy untouched: the
+  layer turns the damped kinetic energy into heat).
 
 The pressure unknown of the implicit stage is the perturbation p' = p - pbar from the analytic
 hydrostatic background evaluated at every node, so that an atmosphere at rest has exactly zero
@@ -146,6 +151,8 @@ class Case:
     oro: tuple = (0.0, 1.0, 0.0, 0.0)
     atm_kind: int = ISOTHERMAL
     atm: tuple = (1.0e5, 250.0, 0.0)
+    # absorbing layers: (top depth, top rate, lateral width, lateral rate, reference wind u_ref)
+    sponge: tuple = (0.0, 0.0, 0.0, 0.0, 0.0)
 
     def to_struct(self) -> _Case:
         c = _Case()
@@ -214,6 +221,7 @@ class Oracle:
         sz = np.zeros((self.ncell, 3))
         L.oc_cell_sizes(h, _p(sz))
         self.cell_sizes = sz
+        self.tau = self.sponge_rate()
         g, a, dd = self.ARK_G, self.ARK_A, self.ARK_D
         self.A = np.array([[0, 0, 0], [2 * g, 0, 0], [1 - a, a, 0]], dtype=np.float64)
         self.At = np.array([[0, 0, 0], [g, g, 0], [dd, dd, g]], dtype=np.float64)
@@ -226,11 +234,41 @@ class Oracle:
         except Exception:
             pass
 
+    # ---------------------------------------------------------------------------- absorbing layers
+    def sponge_rate(self) -> np.ndarray:
+        """Rayleigh friction rate tau at every node (physical coordinates): below the lid,
+        tau_t sin^2(pi/2 (z - z_s) / (H - z_s)) for z > z_s = H - depth; along a walled lateral
+        boundary, tau_l sin^2(pi/2 (1 - dist / width)) for dist < width; the rates add."""
+        depth, rate_t, width, rate_l, _ = (float(v) for v in self.case.sponge)
+        c = self.case
+        H = float(c.length[2])
+        tau = np.zeros(self.N)
+        if depth > 0.0 and rate_t > 0.0:
+            zs = H - depth
+            t = np.clip((self.z - zs) / depth, 0.0, None)
+            tau += np.where(self.z > zs, rate_t * np.sin(0.5 * math.pi * t) ** 2, 0.0)
+        if width > 0.0 and rate_l > 0.0:
+            walls = [(0, self.x, float(c.length[0]))]
+            if self.d == 3:
+                walls.append((1, self.y, float(c.length[1])))
+            for ax, coord, L in walls:
+                if c.periodic[ax]:
+                    continue
+                dist = np.minimum(coord, L - coord)
+                t = np.clip(1.0 - dist / width, 0.0, None)
+                tau += np.where(dist < width, rate_l * np.sin(0.5 * math.pi * t) ** 2, 0.0)
+        return tau
+
     # -------------------------------------------------------------------------------- operators
     def explicit_residual(self, U: np.ndarray) -> np.ndarray:
+        """M^{-1} times the explicit weak form, plus the absorbing-layer friction on the momentum."""
         U = np.ascontiguousarray(U, dtype=np.float64)
         R = np.zeros_like(U)
         lib().oc_explicit_residual(self._m, _p(U), _p(R))
+        if np.any(self.tau > 0.0):
+            uref = float(self.case.sponge[4])
+            R[1:1 + self.d] -= self.tau[None, :] * U[1:1 + self.d]
+            R[1] += self.tau * U[0] * uref
         return R
 
     def grad(self, p: np.ndarray) -> np.ndarray:

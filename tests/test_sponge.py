@@ -1,0 +1,82 @@
+"""Absorbing layers (next row N1; Section 3.1 defers the non-reflecting boundaries to cited work).
+
+Reading: Rayleigh friction on the momentum, d m/dt = -tau (m - rho u_ref e_x), in the explicit
+part of the IMEX split, with the sin^2 rate profile of Klemp and Lilly (1978) below the lid and
+along walled lateral boundaries.
+
+Oracle pins (CPU): a uniform wind over flat ground is a steady state of the undamped equations, so
+inside a layer every node's momentum must decay by exactly the explicit ARK2 amplification factor
+of d m/dt = -tau m per step (computed here from the Butcher tableau, independently of the DG
+code), stay unchanged outside the layers, and stay unchanged everywhere when u_ref equals the
+wind.  GPU parity: explicit residual and whole steps with layers against the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+
+def ark2_explicit_factor(o, z):
+    """Amplification of y' = lam y over one step of the explicit tableau, z = lam dt."""
+    A, b = o.A, o.b
+    Y = []
+    for i in range(3):
+        Y.append(1.0 + z * sum(A[i, j] * Y[j] for j in range(i)))
+    return 1.0 + z * sum(b[j] * Y[j] for j in range(3))
+
+
+def layered_case(dim, sponge, periodic):
+    if dim == 2:
+        return O.Case(dim=2, degree=3, nbase=(4, 1, 4), length=(4000.0, 1.0, 4000.0), periodic=periodic,
+                      atm_kind=O.ISOTHERMAL, atm=(1e5, 250.0), sponge=sponge)
+    return O.Case(dim=3, degree=2, nbase=(2, 4, 2), length=(2000.0, 4000.0, 2000.0), periodic=periodic,
+                  atm_kind=O.ISOTHERMAL, atm=(1e5, 250.0), sponge=sponge)
+
+
+@pytest.mark.parametrize("dim,sponge,periodic", [
+    (2, (2000.0, 0.02, 0.0, 0.0, 0.0), (1, 1)),      # top layer
+    (3, (0.0, 0.0, 1500.0, 0.02, 0.0), (1, 0)),      # lateral layers along the y walls
+    (3, (800.0, 0.03, 1000.0, 0.01, 0.0), (1, 0)),   # both, rates add
+])
+def test_layer_damps_uniform_wind_at_the_explicit_rk_rate(dim, sponge, periodic):
+    o = O.Oracle(layered_case(dim, sponge, periodic))
+    u0, dt, K = 1.0, 2.0, 10
+    U = o.initial_state(u0)
+    m0 = U[1].copy()
+    for _ in range(K):
+        U = o.step(U, dt)
+    tau = o.tau
+    assert np.any(tau > 0.0) and np.any(tau == 0.0)
+    expect = m0 * np.array([ark2_explicit_factor(o, -t * dt) for t in tau]) ** K
+    inside = tau > 0.0
+    assert np.max(np.abs(U[1] - expect) / np.abs(m0)) < 2e-5
+    assert np.max(np.abs(U[1][~inside] - m0[~inside]) / np.abs(m0[~inside])) < 2e-5
+    # the strongest node has really decayed (the test would pass trivially otherwise)
+    assert np.min(U[1] / m0) < 0.75
+
+
+def test_layer_leaves_the_reference_wind_alone():
+    sponge = (2000.0, 0.02, 0.0, 0.0, 3.0)
+    o = O.Oracle(layered_case(2, sponge, (1, 1)))
+    U = o.initial_state(3.0)
+    U0 = U.copy()
+    for _ in range(3):
+        U = o.step(U, 2.0)
+    assert np.max(np.abs(U[1] - U0[1])) < 1e-10 * np.max(np.abs(U0[1]))
+
+
+@pytest.mark.parametrize("dim,sponge,periodic,expect", [
+    # integral of the rate over the domain: each layer contributes rate * (its depth or width) / 2
+    # times the area of its boundary (the mean of sin^2 over a quarter period is 1/2)
+    (2, (2000.0, 0.05, 0.0, 0.0, 0.0), (1, 1), 0.05 * 2000.0 / 2 * 4000.0),
+    (3, (0.0, 0.0, 1000.0, 0.02, 0.0), (1, 0), 2 * 0.02 * 1000.0 / 2 * 2000.0 * 2000.0),
+])
+def test_layer_rate_integrates_to_half_rate_times_thickness(dim, sponge, periodic, expect):
+    c = layered_case(dim, sponge, periodic)
+    c.degree = 5  # Gauss quadrature of the smooth profile on cells aligned with the layer
+    o = O.Oracle(c)
+    total = float(np.sum(o.wJ * o.tau))
+    assert abs(total - expect) < 1e-6 * expect
+    # zero outside the layers, the full rate only at the boundary itself
+    assert np.all(o.tau >= 0.0) and np.max(o.tau) < max(sponge[1], sponge[3])
