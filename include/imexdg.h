@@ -63,6 +63,12 @@ typedef struct {
 } dg_refine_rule;
 
 /* Problem description, plain data copied at setup.
+ *   sponge = (top depth, top rate, lateral width, lateral rate, u_ref): absorbing layers for the
+ *     non-reflecting boundaries of Section 3.1 (whose form the paper leaves to cited work):
+ *     Rayleigh friction d m/dt = -tau (m - rho u_ref e_x) in the explicit part, tau = top rate
+ *     sin^2(pi/2 (z - z_s)/depth) above z_s = H - depth (physical height z) plus lateral rate
+ *     sin^2(pi/2 (1 - dist/width)) within width of a walled lateral boundary; rates <= 0 switch a
+ *     layer off.
  *   dim: 2 (x-z slice) or 3; nbase: base cells along x, y, z (y ignored in 2D);
  *   length: Lx, Ly, H in metres (H = rigid-lid height); periodic_x / periodic_y: 1 periodic,
  *   0 slip walls; bottom and top are slip walls;
@@ -82,6 +88,7 @@ typedef struct {
   double oro[4];
   int32_t atmosphere;
   double atm[3];
+  double sponge[5];
 } dg_case_desc;
 
 /* Solver options (Section 3.2: fixed-point loop + GMRES).

@@ -43,7 +43,7 @@ class dg_case_desc(ctypes.Structure):
                 ("periodic_y", ctypes.c_int32), ("n_rules", ctypes.c_int32),
                 ("rules", dg_refine_rule * MAX_RULES), ("orography", ctypes.c_int32),
                 ("oro", ctypes.c_double * 4), ("atmosphere", ctypes.c_int32),
-                ("atm", ctypes.c_double * 3)]
+                ("atm", ctypes.c_double * 3), ("sponge", ctypes.c_double * 5)]
 
 
 class dg_options(ctypes.Structure):
@@ -167,6 +167,8 @@ class Case:
     oro: tuple = (0.0, 1.0, 0.0, 0.0)
     atmosphere: int = ATM_ISOTHERMAL
     atm: tuple = (1.0e5, 250.0, 0.0)
+    # absorbing layers: (top depth, top rate, lateral width, lateral rate, u_ref); rates 0 = off
+    sponge: tuple = (0.0, 0.0, 0.0, 0.0, 0.0)
 
     def to_c(self) -> dg_case_desc:
         c = dg_case_desc()
@@ -187,6 +189,9 @@ class Case:
         atm = list(self.atm) + [0.0] * (3 - len(self.atm))
         for i in range(3):
             c.atm[i] = float(atm[i])
+        sp = list(self.sponge) + [0.0] * (5 - len(self.sponge))
+        for i in range(5):
+            c.sponge[i] = float(sp[i])
         return c
 
 

@@ -11,6 +11,7 @@ namespace dg {
 constexpr double kG = 9.81;
 constexpr double kR = 287.0;
 constexpr double kGamma = 1.4;
+constexpr double kPi = 3.14159265358979323846;
 
 // Orography and atmosphere parameters (Section 3.1).
 struct Terrain {
@@ -37,6 +38,7 @@ struct MeshDev {
   int per[3];
   Terrain ter;
   double invH;                 // 1 / lid height
+  double sponge[5];            // absorbing layers: top depth, top rate, lateral width, lateral rate, u_ref
   double dxl[kMaxLev][3];      // cell size per level and axis
   int nlev[kMaxLev][3];        // cells per axis at each level
   // cells whose faces are all conforming or walls (reg) and cells with a 2:1 face (irr), each
@@ -107,8 +109,6 @@ int launch_grad_cells64(const MeshDev& m, int degree, const GradArgs<double>& a,
 int launch_div_cells64(const MeshDev& m, int degree, const DivArgs<double>& a, const int* list, int n, hipStream_t s);
 int launch_grad_cells32(const MeshDev& m, int degree, const GradArgs<float>& a, const int* list, int n, hipStream_t s);
 int launch_div_cells32(const MeshDev& m, int degree, const DivArgs<float>& a, const int* list, int n, hipStream_t s);
-int launch_explicit_cells(const MeshDev& m, int degree, const double* U, double* R, const int* list, int n,
-                          hipStream_t s);
 // the 2:1 face terms of the cells with such faces, added to outputs the column kernels wrote
 int launch_grad_hang64(const MeshDev& m, int degree, const GradArgs<double>& a, hipStream_t s);
 int launch_div_hang64(const MeshDev& m, int degree, const DivArgs<double>& a, hipStream_t s);

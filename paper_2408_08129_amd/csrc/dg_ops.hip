@@ -701,16 +701,6 @@ int run(const Op& op, const MeshDev& m, const int* list, int n, hipStream_t s) {
     default: return -6;                        \
   }
 
-int launch_explicit_cells(const MeshDev& m, int degree, const double* U, double* R, const int* list, int n,
-                          hipStream_t s) {
-  if (m.dim == 2) {
-    OpExplicit<2> op{U, R, (unsigned)m.N};
-    DG_DISPATCH(2, degree, return (run<2, NP>(op, m, list, n, s)));
-  } else {
-    OpExplicit<3> op{U, R, (unsigned)m.N};
-    DG_DISPATCH(3, degree, return (run<3, NP>(op, m, list, n, s)));
-  }
-}
 int launch_explicit_hang(const MeshDev& m, int degree, const double* U, double* R, hipStream_t s) {
   const int* list = m.irr;
   const int n = m.nirr;

@@ -766,6 +766,11 @@ dg_status prepare(dg_ctx* c, const dg_case_desc* desc, int degree, const dg_opti
   if (o.preconditioner != DG_PREC_DIAGONAL && o.preconditioner != DG_PREC_CELL_FDM)
     return fail(c, DG_EINVAL, "bad preconditioner");
   if (desc->orography < 0 || desc->orography > 4) return fail(c, DG_EINVAL, "bad orography kind");
+  for (int i = 0; i < 4; ++i)
+    if (!(desc->sponge[i] >= 0.0)) return fail(c, DG_EINVAL, "absorbing-layer sizes and rates must be >= 0");
+  if (desc->sponge[1] > 0.0 && !(desc->sponge[0] > 0.0 && desc->sponge[0] <= desc->length[2]))
+    return fail(c, DG_EINVAL, "top absorbing layer needs 0 < depth <= H");
+  if (!std::isfinite(desc->sponge[4])) return fail(c, DG_EINVAL, "absorbing-layer reference wind must be finite");
   if (desc->atmosphere < 0 || desc->atmosphere > 1) return fail(c, DG_EINVAL, "bad atmosphere kind");
   if (desc->oro[0] >= desc->length[2]) return fail(c, DG_EINVAL, "orography higher than the lid");
   std::string err;
@@ -1427,6 +1432,7 @@ dg_status dg_setup(const dg_case_desc* desc, int32_t degree, const dg_options* o
   md.ter = Terrain{c->desc.orography, c->desc.oro[0], c->desc.oro[1], c->desc.oro[2], c->desc.oro[3],
                    1.0 / (c->desc.oro[1] * c->desc.oro[1])};
   md.invH = 1.0 / M.L[c->D - 1];
+  for (int i = 0; i < 5; ++i) md.sponge[i] = c->desc.sponge[i];
   for (int l = 0; l < kMaxLev; ++l)
     for (int a = 0; a < 3; ++a) {
       md.nlev[l][a] = M.nb[a] << l;

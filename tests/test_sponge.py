@@ -80,3 +80,59 @@ def test_layer_rate_integrates_to_half_rate_times_thickness(dim, sponge, periodi
     assert abs(total - expect) < 1e-6 * expect
     # zero outside the layers, the full rate only at the boundary itself
     assert np.all(o.tau >= 0.0) and np.max(o.tau) < max(sponge[1], sponge[3])
+
+
+# ------------------------------------------------------------------------------- GPU parity
+def _sponged(w, sponge, periodic=None):
+    w = dict(w)
+    w["sponge"] = sponge
+    if periodic is not None:
+        w["periodic"] = periodic
+    return w
+
+
+def _layer_cases():
+    from tests import _common as C
+    return [
+        _sponged(C.walls2d(3), (1500.0, 0.03, 2000.0, 0.02, 4.0)),
+        _sponged(C.twolevel3d(2), (800.0, 0.05, 1200.0, 0.02, -3.0), periodic=(1, 0)),
+        _sponged(C.tiny3d(4), (400.0, 0.1, 0.0, 0.0, 2.0)),
+    ]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("i", [0, 1, 2])
+def test_gpu_explicit_residual_with_layers(i):
+    from paper_2408_08129_amd import inputs
+    from tests import _common as C
+    from tests.test_gpu_parity import TOL64, dev, host, pair
+    w = _layer_cases()[i]
+    o, s, perm = pair(w)
+    assert np.any(o.tau > 0.0)
+    Uo = inputs.random_state(o.nf, o.N, seed=71 + i)
+    Ro = o.explicit_residual(Uo)
+    R = C.to_oracle_order(host(s.explicit_residual(dev(C.to_product_order(Uo, perm, o.nloc)))), perm, o.nloc)
+    for f in range(o.nf):
+        assert C.rel_err(R[f], Ro[f]) < TOL64, (f, C.rel_err(R[f], Ro[f]))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("i", [0, 1])
+def test_gpu_steps_with_layers(i):
+    from tests.test_gpu_parity import _run_pair
+    _run_pair(_layer_cases()[i], 3, 6.0, 0.5)
+
+
+def test_invalid_layer_parameters_rejected():
+    import paper_2408_08129_amd as P
+    from tests import _common as C
+    for sp in [(-1.0, 0.01, 0.0, 0.0, 0.0), (0.0, 0.01, 0.0, 0.0, 0.0), (5000.0, 0.01, 0.0, 0.0, 0.0),
+               (100.0, 0.01, 0.0, -0.5, 0.0), (100.0, 0.01, 0.0, 0.0, float("nan"))]:
+        w = dict(C.walls2d(2))
+        w["sponge"] = sp
+        with pytest.raises(P.DGError) as e:
+            P.dg_footprint(C.product_case(w), 2)
+        assert e.value.status == P.DG_EINVAL, sp
+    w = dict(C.walls2d(2))
+    w["sponge"] = (1000.0, 0.01, 500.0, 0.02, 3.0)
+    assert P.dg_footprint(C.product_case(w), 2) > 0
