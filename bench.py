@@ -193,10 +193,16 @@ def main():
         r32 = run_gpu(w, P.DG_FP32_INNER, args.steps, args.warmup)
         v32 = r32["dofs"] * args.steps / r32["total"]
         # same number of steps from the same initial state: per-field difference to FP64
-        diff = []
-        for f in range(r32["nf"]):
+        # momentum components are measured against the largest momentum component: a component
+        # that is zero up to rounding (flow along a ridge) has no scale of its own
+        nf = r32["nf"]
+        mscale = max(float(ref[f].abs().max()) for f in range(1, nf - 1))
+        diff, adiff = [], []
+        for f in range(nf):
             a, b = r32["U"][f], ref[f]
-            diff.append(float((a - b).abs().max() / b.abs().max()))
+            scale = mscale if 1 <= f < nf - 1 else float(b.abs().max())
+            adiff.append(float((a - b).abs().max()))
+            diff.append(adiff[-1] / scale)
         line["fp32_inner"] = {
             "value": round(v32, 1), "unit": "DoF-updates/s",
             "ms_per_step": round(r32["total"] / args.steps * 1e3, 3),
@@ -204,6 +210,7 @@ def main():
             "p99_step_ms": round(percentile(r32["lat"], 99), 3),
             "gain_vs_fp64": round(v32 / value, 3),
             "max_rel_diff_vs_fp64_per_field": diff,
+            "max_abs_diff_vs_fp64_per_field": adiff,
             "inner_iters": [s["gmres_iters"] for s in r32["stats"]],
             "outer_iters": [s["outer_iters"] for s in r32["stats"]],
         }
