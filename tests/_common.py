@@ -11,7 +11,7 @@ def oracle_case(w: dict) -> O.Case:
     return O.Case(dim=w["dim"], degree=w["degree"], nbase=tuple(w["nbase"]), length=tuple(w["length"]),
                   periodic=tuple(w.get("periodic", (1, 1))), rules=list(w.get("rules", [])),
                   oro_kind=w["orography"], oro=tuple(w["oro"]), atm_kind=w["atmosphere"],
-                  atm=tuple(w["atm"]))
+                  atm=tuple(w["atm"]), sponge=tuple(w.get("sponge", (0.0,) * 5)))
 
 
 def product_case(w: dict):
@@ -19,7 +19,7 @@ def product_case(w: dict):
     return P.Case(dim=w["dim"], nbase=tuple(w["nbase"]), length=tuple(w["length"]),
                   periodic=tuple(w.get("periodic", (1, 1))), rules=list(w.get("rules", [])),
                   orography=w["orography"], oro=tuple(w["oro"]), atmosphere=w["atmosphere"],
-                  atm=tuple(w["atm"]))
+                  atm=tuple(w["atm"]), sponge=tuple(w.get("sponge", (0.0,) * 5)))
 
 
 def cell_perm(prod_cells: np.ndarray, oracle_cells: np.ndarray) -> np.ndarray:
