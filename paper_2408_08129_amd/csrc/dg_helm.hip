@@ -748,53 +748,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   // ---------------------------------------------------------------- finalize
   if (!active) return;
   const T iJ = 1.0 / ((D == 3 ? ha * hb : ha) * fcol);
-  // absorbing layers: Rayleigh friction -tau (m - rho u_ref e_x), tau from the node's position
-  T tau[NP];
-#pragma unroll
-  for (int z = 0; z < NP; ++z) tau[z] = 0.0;
-  if (m.sponge[1] > 0.0 || m.sponge[3] > 0.0) {  // uniform
-    const T depth = m.sponge[0], rt = m.sponge[1], width = m.sponge[2], rl = m.sponge[3];
-    T lat = 0.0;
-    if (rl > 0.0 && width > 0.0) {
-      const T xc = dx0 * ((T)ci.y + 0.5 * (1.0 + xi[i0]));
-      const T yc = D == 3 ? dx1 * ((T)ci.z + 0.5 * (1.0 + xi[i1])) : 0.0;
-#pragma unroll
-      for (int ax = 0; ax < D - 1; ++ax) {
-        if (m.per[ax]) continue;
-        const T c0 = ax == 0 ? xc : yc;
-        const T d = fmin(c0, m.L[ax] - c0);
-        if (d < width) {
-          const T sn = sin(0.5 * kPi * (1.0 - d / width));
-          lat += rl * sn * sn;
-        }
-      }
-    }
-    const T H = 1.0 / invH, zs = H - depth;
-#pragma unroll
-    for (int z = 0; z < NP; ++z) {
-      T t = lat;
-      if (rt > 0.0) {
-        const T zeta = dxz * ((T)iz + 0.5 * (1.0 + xi[z]));
-        const T zp = zeta + h * (1.0 - zeta * invH);
-        if (zp > zs) {
-          const T sn = sin(0.5 * kPi * ((zp - zs) / depth));
-          t += rt * sn * sn;
-        }
-      }
-      tau[z] = t;
-    }
-  }
-  const T uref = m.sponge[4];
 #pragma unroll
   for (int z = 0; z < NP; ++z) {
     const unsigned idx = base + NC * z;
-    R[idx] = acc[0][z] * iJ;
 #pragma unroll
-    for (int l = 0; l < D; ++l) {
-      T r = acc[1 + l][z] * iJ - tau[z] * u[1 + l][z];
-      if (l == 0) r += tau[z] * u[0][z] * uref;
-      R[(1 + l) * N + idx] = r;
-    }
+    for (int o = 0; o < NV - 1; ++o) R[o * N + idx] = acc[o][z] * iJ;
     R[(NV - 1) * N + idx] = acc[NV - 1][z] * iJ - kG * u[D][z];
   }
 }

@@ -126,8 +126,10 @@ int launch_fdm32(const MeshDev& m, int degree, const FdmArgs<float>& a, hipStrea
 int launch_cellcoef(const MeshDev& m, int degree, const double* h, const double* wJ, double dta,
                     double* lam, float* lam32, double* coef, float* coef32, hipStream_t s);
 
-// node geometry: physical coordinates, w J, background p and rho per node
+// node geometry: physical coordinates, w J, background p and rho, absorbing-layer rate per node
+// (each output optional)
 int launch_geometry(const MeshDev& m, int degree, double* x, double* y, double* z, double* wJ,
-                    double* pbar, double* rbar, int atm_kind, const double* atm, hipStream_t s);
+                    double* pbar, double* rbar, double* tau, int atm_kind, const double* atm,
+                    hipStream_t s);
 
 }  // namespace dg

@@ -1,9 +1,12 @@
-// Matrix-free DG cell operators for gfx950.
+// Matrix-free DG cell operators for gfx950: the general cell kernel.
 //
 // One kernel template serves the three operators of the IMEX-DG step (arXiv 2408.08129,
 // Section 2 and Section 3.2): the explicit advective residual, the weak gradient B and the weak
-// divergence C with the pressure-jump penalty P.  A workgroup owns CPB cells; one thread owns one
-// node of one cell.  The cell's data is staged in LDS, the volume term is a sum-factorised 1D
+// divergence C with the pressure-jump penalty P.  The column kernels (dg_helm.hip) do the bulk
+// of the work; this kernel adds the terms of the 2:1 faces for the cells that have one (its
+// faces-only mode) and serves the operator variants the column kernels leave out (Jacobi-scaled
+// p).  A workgroup owns CPB cells, taken from a cell list; one thread owns one node of one cell.
+// The cell's data is staged in LDS, the volume term is a sum-factorised 1D
 // contraction along each axis, and the face terms are evaluated face by face:
 //   (a) traces of the own cell (from LDS) and of the neighbour (gathered along its normal lines
 //       from HBM / L2; no trace buffer, no atomics: every cell writes only its own outputs),
@@ -443,6 +446,7 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
   for (int t = tid; t < CPB * NF * NFP; t += NT) {
     const int c = t / (NF * NFP), f = (t / NFP) % NF, j = t % NFP;
     if (sId[c] < 0) continue;
+    if (HANG && sKind[c][f] != kFine && sKind[c][f] != kCoarse) continue;  // only 2:1 faces needed
     const int k = f >> 1, s = f & 1;
     const int base = compose<D, NP>(k, 0, j);
     const int str = compose<D, NP>(k, 1, 0);
@@ -853,7 +857,7 @@ __device__ void background(const Atm& at, double z, double& p, double& rho) {
 
 template <int D, int NP>
 __global__ void k_geometry(const MeshDev m, const Atm at, double* x, double* y, double* z,
-                           double* wJ, double* pbar, double* rbar) {
+                           double* wJ, double* pbar, double* rbar, double* tau) {
   constexpr int NL = ipow(NP, D);
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= m.N) return;
@@ -884,19 +888,41 @@ __global__ void k_geometry(const MeshDev m, const Atm at, double* x, double* y, 
     if (pbar) pbar[gid] = p;
     if (rbar) rbar[gid] = r;
   }
+  if (tau) {
+    // absorbing-layer rate: sin^2 ramps below the lid (physical height) and towards walled
+    // lateral boundaries, each scaled by its rate
+    const double depth = m.sponge[0], rt = m.sponge[1], width = m.sponge[2], rl = m.sponge[3];
+    double t = 0.0;
+    if (rl > 0.0 && width > 0.0)
+      for (int a = 0; a < D - 1; ++a) {
+        if (m.per[a]) continue;
+        const double d = fmin(X[a], m.L[a] - X[a]);
+        if (d < width) {
+          const double sn = sin(0.5 * kPi * (1.0 - d / width));
+          t += rl * sn * sn;
+        }
+      }
+    const double zs = m.L[D - 1] - depth;
+    if (rt > 0.0 && zz > zs) {
+      const double sn = sin(0.5 * kPi * ((zz - zs) / depth));
+      t += rt * sn * sn;
+    }
+    tau[gid] = t;
+  }
 }
 
 }  // namespace
 
 int launch_geometry(const MeshDev& m, int degree, double* x, double* y, double* z, double* wJ,
-                    double* pbar, double* rbar, int atm_kind, const double* atm, hipStream_t s) {
+                    double* pbar, double* rbar, double* tau, int atm_kind, const double* atm,
+                    hipStream_t s) {
   Atm at{atm_kind, atm[0], atm[1], atm[2]};
   const int grid = (int)((m.N + 255) / 256);
   if (m.N == 0) return 0;
 #define DG_GEO(D_)                                                                               \
   DG_DISPATCH(D_, degree,                                                                        \
               hipLaunchKernelGGL((k_geometry<D_, NP>), dim3(grid), dim3(256), 0, s, m, at, x, y, \
-                                 z, wJ, pbar, rbar);                                             \
+                                 z, wJ, pbar, rbar, tau);                                        \
               return hipGetLastError() == hipSuccess ? 0 : -3)
   if (m.dim == 2) {
     DG_GEO(2);

@@ -257,6 +257,19 @@ __global__ void k_lam(const double* __restrict__ h, int nloc, int ncell, double*
   }
 }
 
+// absorbing layers: R_m -= tau (m - rho u_ref e_x) (Rayleigh friction in the explicit part)
+template <int D>
+__global__ void k_friction(const double* __restrict__ U, const double* __restrict__ tau, double uref,
+                           long N, long ld, double* __restrict__ R) {
+  GRID_LOOP(e, N) {
+    const double t = tau[e];
+    if (t == 0.0) continue;
+    R[ld + e] -= t * (U[ld + e] - U[e] * uref);
+#pragma unroll
+    for (int l = 1; l < D; ++l) R[(1 + l) * ld + e] -= t * U[(1 + l) * ld + e];
+  }
+}
+
 template <int D>
 __global__ void k_fi_momentum(const double* __restrict__ q, const double* __restrict__ U,
                               const double* __restrict__ rbar, long N, long ld, double* __restrict__ F) {
@@ -605,6 +618,7 @@ struct dg_ctx {
   float* d_tabf = nullptr;
   // geometry / background
   double *pbar = nullptr, *rbar = nullptr, *wJ = nullptr;
+  double* tau = nullptr;  // absorbing-layer rate per node (only with an absorbing layer)
   // step workspace
   double* FE[3] = {nullptr, nullptr, nullptr};
   double* FI[3] = {nullptr, nullptr, nullptr};
@@ -710,6 +724,7 @@ void make_plan(dg_ctx* c, Plan& P) {
   P.add((void**)&c->pbar, ld * d8);
   P.add((void**)&c->rbar, ld * d8);
   P.add((void**)&c->wJ, ld * d8);
+  if (c->desc.sponge[1] > 0.0 || c->desc.sponge[3] > 0.0) P.add((void**)&c->tau, ld * d8);
   for (int j = 0; j < 3; ++j) {
     P.add((void**)&c->FE[j], F * ld * d8);
     P.add((void**)&c->FI[j], F * ld * d8);
@@ -1153,6 +1168,14 @@ dg_status explicit_residual(dg_ctx* c, const double* U, double* R) {
   int re;
   TIMEDB(0, 16.0 * c->F * c->N, re = launch_explicit(c->md, c->degree, U, R, c->stream));
   LCHK(re);
+  if (c->tau) {
+    if (c->D == 2)
+      TIMED(4, hipLaunchKernelGGL((k_friction<2>), pw_grid(c->N), dim3(256), 0, c->stream, U, c->tau,
+                                  c->desc.sponge[4], c->N, c->ld, R));
+    else
+      TIMED(4, hipLaunchKernelGGL((k_friction<3>), pw_grid(c->N), dim3(256), 0, c->stream, U, c->tau,
+                                  c->desc.sponge[4], c->N, c->ld, R));
+  }
   return DG_OK;
 }
 
@@ -1441,7 +1464,7 @@ dg_status dg_setup(const dg_case_desc* desc, int32_t degree, const dg_options* o
   {
     MeshDev g = md;
     g.N = c->N;  // geometry kernel iterates over N nodes
-    if (launch_geometry(g, c->degree, nullptr, nullptr, nullptr, c->wJ, c->pbar, c->rbar,
+    if (launch_geometry(g, c->degree, nullptr, nullptr, nullptr, c->wJ, c->pbar, c->rbar, c->tau,
                         c->desc.atmosphere, c->desc.atm, s)) {
       dg_destroy(c);
       return fail(nullptr, DG_EDEVICE, "geometry kernel launch failed");
@@ -1510,7 +1533,8 @@ dg_status dg_node_geometry(dg_ctx* c, double* x, double* y, double* z, double* w
   if (!c) return fail(nullptr, DG_EINVAL, "null context");
   MeshDev g = c->md;
   g.N = c->N;
-  if (launch_geometry(g, c->degree, x, y, z, wJ, nullptr, nullptr, c->desc.atmosphere, c->desc.atm, c->stream))
+  if (launch_geometry(g, c->degree, x, y, z, wJ, nullptr, nullptr, nullptr, c->desc.atmosphere, c->desc.atm,
+                      c->stream))
     return fail(c, DG_EDEVICE, "geometry kernel launch failed");
   return DG_OK;
 }
