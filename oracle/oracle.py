@@ -19,8 +19,8 @@ paper (Orlando, Benacchio, Bonaventura, arXiv 2408.08129):
 * Section 3.1: the test runs with non-reflecting top and lateral boundaries whose form the paper
   defers to cited work.  Reading used here: absorbing layers of Rayleigh friction on the momentum,
   d m / dt = -tau (m - rho u_ref e_x), explicit, with the sin^2 rate profile of Klemp and Lilly
-  (1978) below the lid and along walled lateral boundaries (mass and total energy untouched: the
-  layer turns the damped kinetic energy into heat).
+  (1978) below the lid and along the lateral sides, walled or periodic (mass and total energy
+  untouched: the layer turns the damped kinetic energy into heat).
 
 The pressure unknown of the implicit stage is the perturbation p' = p - pbar from the analytic
 hydrostatic background evaluated at every node, so that an atmosphere at rest has exactly zero
@@ -237,8 +237,10 @@ class Oracle:
     # ---------------------------------------------------------------------------- absorbing layers
     def sponge_rate(self) -> np.ndarray:
         """Rayleigh friction rate tau at every node (physical coordinates): below the lid,
-        tau_t sin^2(pi/2 (z - z_s) / (H - z_s)) for z > z_s = H - depth; along a walled lateral
-        boundary, tau_l sin^2(pi/2 (1 - dist / width)) for dist < width; the rates add."""
+        tau_t sin^2(pi/2 (z - z_s) / (H - z_s)) for z > z_s = H - depth; along each lateral side
+        (x = 0, x = Lx and, in 3D, y = 0, y = Ly; walled or periodic: at a periodic seam the
+        layer absorbs what leaves on one side before it comes back on the other),
+        tau_l sin^2(pi/2 (1 - dist / width)) for dist < width; the rates add."""
         depth, rate_t, width, rate_l, _ = (float(v) for v in self.case.sponge)
         c = self.case
         H = float(c.length[2])
@@ -252,8 +254,6 @@ class Oracle:
             if self.d == 3:
                 walls.append((1, self.y, float(c.length[1])))
             for ax, coord, L in walls:
-                if c.periodic[ax]:
-                    continue
                 dist = np.minimum(coord, L - coord)
                 t = np.clip(1.0 - dist / width, 0.0, None)
                 tau += np.where(dist < width, rate_l * np.sin(0.5 * math.pi * t) ** 2, 0.0)
