@@ -67,8 +67,9 @@ typedef struct {
  *     non-reflecting boundaries of Section 3.1 (whose form the paper leaves to cited work):
  *     Rayleigh friction d m/dt = -tau (m - rho u_ref e_x) in the explicit part, tau = top rate
  *     sin^2(pi/2 (z - z_s)/depth) above z_s = H - depth (physical height z) plus lateral rate
- *     sin^2(pi/2 (1 - dist/width)) within width of a walled lateral boundary; rates <= 0 switch a
- *     layer off.
+ *     sin^2(pi/2 (1 - dist/width)) within width of each lateral side (x = 0, x = Lx, and in 3D
+ *     y = 0, y = Ly), walled or periodic (at a periodic seam the layer absorbs what leaves one side
+ *     before it re-enters on the other); rates <= 0 switch a layer off.
  *   dim: 2 (x-z slice) or 3; nbase: base cells along x, y, z (y ignored in 2D);
  *   length: Lx, Ly, H in metres (H = rigid-lid height); periodic_x / periodic_y: 1 periodic,
  *   0 slip walls; bottom and top are slip walls;

@@ -11,6 +11,8 @@ ORO_FLAT, ORO_AGNESI, ORO_BELL, ORO_GAUSS_HILL, ORO_GAUSS_RIDGE = range(5)
 ATM_ISOTHERMAL, ATM_STRATIFIED = range(2)
 
 STRAT = (1.0e5, 293.15, 0.01)
+# absorbing layers of the bell-hill case: (top depth, top rate, side width, side rate, u_ref)
+BELL_LAYERS = (6000.0, 0.05, 10000.0, 0.05, 10.0)
 
 WORKLOADS = {
     # 2D slice, degree 2, conforming 32 x 16 quads on 20 km x 10 km, isothermal 250 K,
@@ -41,6 +43,24 @@ WORKLOADS = {
         rules=[(2000.0, 64000.0, 2500.0, 0.0, -1.0), (1000.0, 64000.0, 1250.0, 0.0, -1.0)],
         orography=ORO_GAUSS_RIDGE, oro=(1000.0, 5000.0, 64000.0, 0.0),
         atmosphere=ATM_STRATIFIED, atm=STRAT, ubar=10.0, dt=0.4, steps=20),
+    # The 3D bell-hill test of Section 3.1: 60 x 40 x 16 km, bell of Eq. (3) with h_c = 400 m,
+    # a_c = 1 km at (30, 20) km, stratified N = 0.01, u = 10 m/s, degree 4, dt = 2 s, one hour.
+    # Non-reflecting top and sides as absorbing layers (6 km below the lid, 10 km along each
+    # periodic side, rates 0.05 1/s, towards the background wind).  Uniform: 60 x 40 x 16 cells
+    # of 1 km (250 m between nodes), 38,400 cells.
+    "bell3d_r4_uniform": dict(
+        dim=3, degree=4, nbase=(60, 40, 16), length=(60000.0, 40000.0, 16000.0), periodic=(1, 1),
+        rules=[], orography=ORO_BELL, oro=(400.0, 1000.0, 30000.0, 20000.0),
+        atmosphere=ATM_STRATIFIED, atm=STRAT, ubar=10.0, dt=2.0, steps=1800,
+        sponge=BELL_LAYERS),
+    # Non-conforming: 15 x 10 x 4 base cells of 4 km, 2 km cells over the lowest 4 km, 1 km cells
+    # (the uniform mesh's size) over the lowest 2 km within 10 km (x) and 4 km (y) of the hill:
+    # 450 + 1160 + 320 = 1930 cells (the paper's mesh of 1958 cells is shown only as a figure).
+    "bell3d_r4_nonconforming": dict(
+        dim=3, degree=4, nbase=(15, 10, 4), length=(60000.0, 40000.0, 16000.0), periodic=(1, 1),
+        rules=[(4000.0, 0.0, -1.0, 0.0, -1.0), (2000.0, 30000.0, 10000.0, 20000.0, 4000.0)],
+        orography=ORO_BELL, oro=(400.0, 1000.0, 30000.0, 20000.0), atmosphere=ATM_STRATIFIED,
+        atm=STRAT, ubar=10.0, dt=2.0, steps=1800, sponge=BELL_LAYERS),
 }
 
 

@@ -889,13 +889,12 @@ __global__ void k_geometry(const MeshDev m, const Atm at, double* x, double* y, 
     if (rbar) rbar[gid] = r;
   }
   if (tau) {
-    // absorbing-layer rate: sin^2 ramps below the lid (physical height) and towards walled
-    // lateral boundaries, each scaled by its rate
+    // absorbing-layer rate: sin^2 ramps below the lid (physical height) and towards each lateral
+    // side, walled or periodic, each scaled by its rate
     const double depth = m.sponge[0], rt = m.sponge[1], width = m.sponge[2], rl = m.sponge[3];
     double t = 0.0;
     if (rl > 0.0 && width > 0.0)
       for (int a = 0; a < D - 1; ++a) {
-        if (m.per[a]) continue;
         const double d = fmin(X[a], m.L[a] - X[a]);
         if (d < width) {
           const double sn = sin(0.5 * kPi * (1.0 - d / width));
