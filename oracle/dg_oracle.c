@@ -39,6 +39,7 @@
 #define OC_GAMMA 1.4
 
 #define OC_MAXNP 8 /* degree <= 7 */
+#define OC_MAXNQ 12 /* explicit-flux quadrature points per direction */
 #define OC_MAXRULES 8
 
 enum { OC_FLAT = 0, OC_AGNESI = 1, OC_BELL = 2, OC_GAUSS_HILL = 3, OC_GAUSS_RIDGE = 4 };
@@ -77,6 +78,15 @@ typedef struct {
   double *subL;   /* [face][sub][fp][i] = L_i at the fine sub-face point, in coarse coordinates */
   double *wq;     /* volume weights [q] */
   double *wf;     /* face weights [fp] */
+  /* over-integration of the explicit flux: nq Gauss points per direction (0: not set) */
+  int nq, nvq, nfq;
+  double xq[OC_MAXNQ], wq1[OC_MAXNQ];
+  double *phiQ;   /* [qv][i] = L_i at volume quadrature point qv */
+  double *gradQ;  /* [qv][i][k] = d/dxi_k L_i at qv */
+  double *wvq;    /* [qv] volume weights */
+  double *faceQ;  /* [face][j][i] = L_i at face quadrature point j of face (k,s) */
+  double *subQ;   /* [face][sub][j][i] = L_i at the fine sub-face quadrature point, coarse coords */
+  double *wfq;    /* [j] face weights */
 } oc_mesh;
 
 /* ------------------------------------------------------------------------------------------ */
@@ -485,7 +495,80 @@ void oc_mesh_free(oc_mesh* m) {
   if (!m) return;
   free(m->lev); free(m->idx); free(m->fkind); free(m->fnbr);
   free(m->gradL); free(m->faceL); free(m->subL); free(m->wq); free(m->wf);
+  free(m->phiQ); free(m->gradQ); free(m->wvq); free(m->faceQ); free(m->subQ); free(m->wfq);
   free(m);
+}
+
+/* Over-integration (quadrature of the explicit flux integrals with nq >= r + 1 Gauss points per
+ * direction): the basis and its gradient at the volume points, the basis at the points of every
+ * face and of every fine sub-face (in the coarse cell's coordinates), and the weights.  Returns 0,
+ * or -1 for an nq out of range. */
+int oc_set_quadrature(oc_mesh* m, int nq) {
+  int d = m->d, np1 = m->np1, nloc = m->nloc, nf = 2 * d, nsub = 1 << (d - 1);
+  if (nq < np1 || nq > OC_MAXNQ) return -1;
+  free(m->phiQ); free(m->gradQ); free(m->wvq); free(m->faceQ); free(m->subQ); free(m->wfq);
+  m->nq = nq;
+  oc_gauss(nq, m->xq, m->wq1);
+  int nvq = 1, nfq = 1;
+  for (int a = 0; a < d; ++a) nvq *= nq;
+  for (int a = 0; a < d - 1; ++a) nfq *= nq;
+  m->nvq = nvq;
+  m->nfq = nfq;
+  m->phiQ = (double*)malloc(sizeof(double) * nvq * nloc);
+  m->gradQ = (double*)malloc(sizeof(double) * nvq * nloc * d);
+  m->wvq = (double*)malloc(sizeof(double) * nvq);
+  m->faceQ = (double*)malloc(sizeof(double) * nf * nfq * nloc);
+  m->subQ = (double*)malloc(sizeof(double) * nf * nsub * nfq * nloc);
+  m->wfq = (double*)malloc(sizeof(double) * nfq);
+  for (int q = 0; q < nvq; ++q) {
+    double xqv[3], wv = 1.0;
+    int t = q;
+    for (int a = 0; a < d; ++a) { xqv[a] = m->xq[t % nq]; wv *= m->wq1[t % nq]; t /= nq; }
+    m->wvq[q] = wv;
+    for (int i = 0; i < nloc; ++i) {
+      int ia[3], u = i;
+      for (int a = 0; a < d; ++a) { ia[a] = u % np1; u /= np1; }
+      double v = 1.0;
+      for (int a = 0; a < d; ++a) v *= lag(np1, m->xi, ia[a], xqv[a]);
+      m->phiQ[q * nloc + i] = v;
+      for (int k = 0; k < d; ++k) {
+        double g = 1.0;
+        for (int a = 0; a < d; ++a)
+          g *= (a == k) ? dlag(np1, m->xi, ia[a], xqv[a]) : lag(np1, m->xi, ia[a], xqv[a]);
+        m->gradQ[(q * nloc + i) * d + k] = g;
+      }
+    }
+  }
+  for (int j = 0; j < nfq; ++j) {
+    int t = j;
+    double wv = 1.0;
+    for (int a = 0; a < d - 1; ++a) { wv *= m->wq1[t % nq]; t /= nq; }
+    m->wfq[j] = wv;
+  }
+  for (int k = 0; k < d; ++k)
+    for (int s = 0; s < 2; ++s) {
+      int f = 2 * k + s;
+      for (int sub = 0; sub <= nsub; ++sub)
+        for (int j = 0; j < nfq; ++j) {
+          double pt[3];
+          pt[k] = s ? 1.0 : -1.0;
+          int t = j;
+          for (int tt = 0; tt < d - 1; ++tt) {
+            int ta = tang(d, k, tt);
+            double xj = m->xq[t % nq];
+            t /= nq;
+            pt[ta] = sub == 0 ? xj : 0.5 * (xj + 2.0 * (((sub - 1) >> tt) & 1) - 1.0);
+          }
+          for (int i = 0; i < nloc; ++i) {
+            int u = i;
+            double v = 1.0;
+            for (int a = 0; a < d; ++a) { v *= lag(np1, m->xi, u % np1, pt[a]); u /= np1; }
+            if (sub == 0) m->faceQ[(f * nfq + j) * nloc + i] = v;
+            else m->subQ[((f * nsub + (sub - 1)) * nfq + j) * nloc + i] = v;
+          }
+        }
+    }
+  return 0;
 }
 
 int oc_ncell(const oc_mesh* m) { return m->ncell; }
@@ -731,6 +814,127 @@ void oc_explicit_residual(const oc_mesh* m, const double* U, double* R) {
       R[(1 + d) * N + (long)c * nloc + q] -= OC_G * U[d * N + (long)c * nloc + q];
     }
   }
+}
+
+/* The over-integrated explicit residual: the same weak form as oc_explicit_residual, with the
+ * volume and face integrals of the flux taken with nq Gauss points per direction (the state
+ * interpolated there from the nodes); on a 2:1 face the points are those of the fine sub-face, as
+ * for the nodal rule.  The mass matrix stays the nodal one and the gravity work stays pointwise. */
+static void face_points_q(const oc_mesh* m, int c, int f, int sub, oc_facepts* fp) {
+  face_points(m, c, f, sub, fp);
+  int d = m->d, k = f / 2, s = f % 2, nf = 2 * d, nfq = m->nfq, nloc = m->nloc, nsub = 1 << (d - 1);
+  int kind = m->fkind[c * nf + f];
+  int fo = 2 * k + (1 - s);
+  if (kind == OC_COARSE) {
+    fp->myL = &m->subQ[((f * nsub + sub) * nfq) * nloc];
+    fp->nbL = &m->faceQ[(fo * nfq) * nloc];
+  } else {
+    fp->myL = &m->faceQ[(f * nfq) * nloc];
+    if (kind == OC_FINE) {
+      int csub = 0;
+      for (int t = 0; t < d - 1; ++t) csub |= (m->idx[3 * c + tang(d, k, t)] & 1) << t;
+      fp->nbL = &m->subQ[((fo * nsub + csub) * nfq) * nloc];
+    } else {
+      fp->nbL = &m->faceQ[(fo * nfq) * nloc];
+    }
+  }
+}
+
+static void face_normal_q(const oc_mesh* m, int k, const oc_facepts* fp, int j, double* N) {
+  int d = m->d;
+  double X[3];
+  X[k] = m->L[k] / (m->n[k] * (double)(1 << fp->lev)) * (double)fp->P;
+  int t = j;
+  for (int tt = 0; tt < d - 1; ++tt) {
+    int ta = tang(d, k, tt);
+    double dx = m->L[ta] / (m->n[ta] * (double)(1 << fp->lev));
+    X[ta] = dx * (fp->T[ta] + 0.5 * (1.0 + m->xq[t % m->nq]));
+    t /= m->nq;
+  }
+  double Gam[3][3], J, zp;
+  metric(m, fp->lev, X, Gam, &J, &zp);
+  for (int a = 0; a < d; ++a) N[a] = Gam[k][a];
+}
+
+int oc_explicit_residual_oi(const oc_mesh* m, const double* U, double* R) {
+  if (m->nq == 0) return -1;
+  int d = m->d, nloc = m->nloc, nf = 2 * d, NF = d + 2, nq = m->nq, nvq = m->nvq, nfq = m->nfq;
+  long N = (long)m->ncell * nloc;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int c = 0; c < m->ncell; ++c) {
+    double W[5][OC_MAXNP * OC_MAXNP * OC_MAXNP];
+    int l = m->lev[c];
+    for (int f = 0; f < NF; ++f)
+      for (int i = 0; i < nloc; ++i) W[f][i] = 0.0;
+    /* volume, at the nq^d quadrature points */
+    for (int q = 0; q < nvq; ++q) {
+      double Uq[5], X[3], Gam[3][3], J, zp;
+      for (int f = 0; f < NF; ++f) Uq[f] = dense_trace(&m->phiQ[q * nloc], &U[f * N + (long)c * nloc], nloc);
+      int t = q;
+      for (int a = 0; a < d; ++a) {
+        double dx = m->L[a] / (m->n[a] * (double)(1 << l));
+        X[a] = dx * (m->idx[3 * c + a] + 0.5 * (1.0 + m->xq[t % nq]));
+        t /= nq;
+      }
+      metric(m, l, X, Gam, &J, &zp);
+      double rho = Uq[0], m2 = 0.0, u[3];
+      for (int a = 0; a < d; ++a) { u[a] = Uq[1 + a] / rho; m2 += Uq[1 + a] * Uq[1 + a]; }
+      double rk = 0.5 * m2 / rho;
+      for (int k = 0; k < d; ++k) {
+        double Gu = 0.0;
+        for (int a = 0; a < d; ++a) Gu += Gam[k][a] * u[a];
+        double Gk[5];
+        Gk[0] = rho * Gu;
+        for (int a = 0; a < d; ++a) Gk[1 + a] = Uq[1 + a] * Gu;
+        Gk[1 + d] = rk * Gu;
+        for (int i = 0; i < nloc; ++i) {
+          double gl = m->gradQ[(q * nloc + i) * d + k] * m->wvq[q];
+          for (int f = 0; f < NF; ++f) W[f][i] += gl * Gk[f];
+        }
+      }
+    }
+    /* faces, at the nq^(d-1) points of every (sub-)face */
+    for (int f = 0; f < nf; ++f) {
+      int kind = m->fkind[c * nf + f];
+      int k = f / 2;
+      int nsub = (kind == OC_COARSE) ? (1 << (d - 1)) : 1;
+      for (int sub = 0; sub < nsub; ++sub) {
+        oc_facepts fp;
+        face_points_q(m, c, f, sub, &fp);
+        for (int j = 0; j < nfq; ++j) {
+          double Nv[3], Um[5], Un[5], Fh[5];
+          face_normal_q(m, k, &fp, j, Nv);
+          for (int g = 0; g < NF; ++g) Um[g] = dense_trace(&fp.myL[j * nloc], &U[g * N + (long)c * nloc], nloc);
+          double sign = fp.left ? 1.0 : -1.0;
+          if (kind == OC_WALL) {
+            double No[3];
+            for (int a = 0; a < d; ++a) No[a] = sign * Nv[a];
+            wall_flux(d, Um, No, Fh);
+            sign = 1.0;
+          } else {
+            for (int g = 0; g < NF; ++g)
+              Un[g] = dense_trace(&fp.nbL[j * nloc], &U[g * N + (long)fp.nb * nloc], nloc);
+            if (fp.left) rusanov(d, Um, Un, Nv, Fh);
+            else rusanov(d, Un, Um, Nv, Fh);
+          }
+          double wj = m->wfq[j];
+          for (int i = 0; i < nloc; ++i) {
+            double li = fp.myL[j * nloc + i] * wj * sign;
+            for (int g = 0; g < NF; ++g) W[g][i] -= li * Fh[g];
+          }
+        }
+      }
+    }
+    for (int q = 0; q < nloc; ++q) {
+      double X[3], Gam[3][3], J, zp;
+      node_X(m, c, q, X);
+      metric(m, l, X, Gam, &J, &zp);
+      double mJ = m->wq[q] * J;
+      for (int f = 0; f < NF; ++f) R[f * N + (long)c * nloc + q] = W[f][q] / mJ;
+      R[(1 + d) * N + (long)c * nloc + q] -= OC_G * U[d * N + (long)c * nloc + q];
+    }
+  }
+  return 0;
 }
 
 /* q = M^{-1} B p: weak gradient, B p . phi = -int p div(phi) + int p^ phi.n, with the central

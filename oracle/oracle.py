@@ -97,6 +97,10 @@ def lib():
         L.oc_node_geometry.argtypes = [P, dp, dp, dp, dp]
         L.oc_background_nodes.argtypes = [P, dp, dp]
         L.oc_explicit_residual.argtypes = [P, dp, dp]
+        L.oc_explicit_residual_oi.argtypes = [P, dp, dp]
+        L.oc_explicit_residual_oi.restype = ctypes.c_int
+        L.oc_set_quadrature.argtypes = [P, ctypes.c_int]
+        L.oc_set_quadrature.restype = ctypes.c_int
         L.oc_grad.argtypes = [P, dp, dp]
         L.oc_div.argtypes = [P, dp, dp]
         L.oc_penalty.argtypes = [P, dp, dp, dp]
@@ -189,9 +193,10 @@ class Oracle:
     ARK_D = 1.0 / (2.0 * math.sqrt(2.0))
     ARK_A = (3.0 + 2.0 * math.sqrt(2.0)) / 6.0
 
-    def __init__(self, case: Case, beta: float = 1.0):
+    def __init__(self, case: Case, beta: float = 1.0, quad_extra: int = 0):
         self.case = case
         self.beta = beta
+        self.quad_extra = quad_extra
         self._cs = case.to_struct()
         h = ctypes.c_void_p()
         rc = lib().oc_mesh_build(ctypes.byref(self._cs), ctypes.byref(h))
@@ -222,6 +227,10 @@ class Oracle:
         L.oc_cell_sizes(h, _p(sz))
         self.cell_sizes = sz
         self.tau = self.sponge_rate()
+        if quad_extra > 0:
+            # over-integration of the explicit flux: r + 1 + quad_extra Gauss points per direction
+            if L.oc_set_quadrature(h, self.r + 1 + quad_extra) != 0:
+                raise ValueError("quad_extra out of range")
         g, a, dd = self.ARK_G, self.ARK_A, self.ARK_D
         self.A = np.array([[0, 0, 0], [2 * g, 0, 0], [1 - a, a, 0]], dtype=np.float64)
         self.At = np.array([[0, 0, 0], [g, g, 0], [dd, dd, g]], dtype=np.float64)
@@ -264,7 +273,10 @@ class Oracle:
         """M^{-1} times the explicit weak form, plus the absorbing-layer friction on the momentum."""
         U = np.ascontiguousarray(U, dtype=np.float64)
         R = np.zeros_like(U)
-        lib().oc_explicit_residual(self._m, _p(U), _p(R))
+        if self.quad_extra > 0:
+            lib().oc_explicit_residual_oi(self._m, _p(U), _p(R))
+        else:
+            lib().oc_explicit_residual(self._m, _p(U), _p(R))
         if np.any(self.tau > 0.0):
             uref = float(self.case.sponge[4])
             R[1:1 + self.d] -= self.tau[None, :] * U[1:1 + self.d]
