@@ -74,7 +74,7 @@ KERNEL_NAMES = {
     "gs_dots": "k_gs_dots (Gram-Schmidt reduction pass)",
     "gs_update": "k_gs_update (Gram-Schmidt update pass)",
 }
-SOURCES = ("dg_ops.hip", "dg_helm.hip", "dg_solver.hip", "dg_internal.hpp", "dg_device.hpp")
+SOURCES = ("dg_ops.hip", "dg_helm.hip", "dg_solver.hip", "dg_internal.hpp", "dg_device.hpp")  # the kernels profiled
 
 
 def source_sha256():

@@ -101,7 +101,12 @@ typedef struct {
  *   penalty_beta: weight of the pressure-jump penalty in the implicit energy flux;
  *   preconditioner: DG_PREC_DIAGONAL (a diagonal scaling) or DG_PREC_CELL_FDM (cell-wise fast
  *     diagonalisation of a separable approximation of the cell block); changes iteration counts
- *     only, not the converged solution. */
+ *     only, not the converged solution;
+ *   quad_extra: over-integration of the explicit advective flux (de-aliasing of the nonlinear
+ *     terms): its volume and face integrals use degree + 1 + quad_extra Gauss points per direction
+ *     (on a 2:1 face the fine sub-face's points), the mass matrix stays the nodal one and the
+ *     gravity work pointwise; 0 (default) keeps the nodal rule.  quad_extra <= 3 and
+ *     degree + 1 + quad_extra <= 8, else DG_EUNSUPPORTED; negative: DG_EINVAL. */
 typedef struct {
   int32_t fp_iters;
   int32_t gmres_restart;
@@ -114,6 +119,7 @@ typedef struct {
   int32_t inner_maxit;
   double penalty_beta;
   int32_t preconditioner;
+  int32_t quad_extra;
 } dg_options;
 
 /* Per-step statistics ([implicit stage][fixed-point iteration]). */

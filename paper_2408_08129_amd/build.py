@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libimexdg.so")
-SOURCES = ["dg_ops.hip", "dg_helm.hip", "dg_solver.hip", "dg_mesh.cpp"]
+SOURCES = ["dg_ops.hip", "dg_helm.hip", "dg_oi.hip", "dg_solver.hip", "dg_mesh.cpp"]
 ARCH = os.environ.get("PYTORCH_ROCM_ARCH", "gfx950")
 
 HIPCC_FLAGS = ["-std=c++17", "-O3", "-fPIC", "--offload-arch=" + ARCH,

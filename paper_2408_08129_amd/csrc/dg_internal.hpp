@@ -47,6 +47,10 @@ struct MeshDev {
   int nreg;
   const int* irr;
   int nirr;
+  // over-integration of the explicit flux: NQ Gauss points per direction and their tables
+  // (OiLayout), or nq = 0
+  const double* oitab;
+  int nq;
 };
 
 // Offsets into the 1D table for NP = r + 1 points.
@@ -63,6 +67,18 @@ struct TabLayout {
   __host__ __device__ constexpr int fdmu() const { return 6 * np + 6 * np * np; }  // mu[a]
   __host__ __device__ constexpr int size() const { return 7 * np + 6 * np * np; }
 };
+
+// Offsets into the over-integration table for NP nodes and NQ quadrature points per direction.
+struct OiLayout {
+  int np, nq;
+  __host__ __device__ constexpr int xq() const { return 0; }                         // points
+  __host__ __device__ constexpr int wq() const { return nq; }                        // weights
+  __host__ __device__ constexpr int bq() const { return 2 * nq; }                    // Bq[q][j] = l_j(xq_q)
+  __host__ __device__ constexpr int dq() const { return 2 * nq + nq * np; }          // Dq[q][j] = l_j'(xq_q)
+  __host__ __device__ constexpr int bs() const { return 2 * nq + 2 * nq * np; }      // Bs[h][q][j] = l_j((xq_q + 2h - 1) / 2)
+  __host__ __device__ constexpr int size() const { return 2 * nq + 4 * nq * np; }
+};
+constexpr int kMaxNq = 8;  // over-integration points per direction
 
 // ----------------------------------------------------------------------- operator parameters
 // Inputs of the weak gradient M^{-1} B p (output q, d fields).
@@ -121,6 +137,9 @@ int launch_div64(const MeshDev& m, int degree, const DivArgs<double>& a, hipStre
 int launch_grad32(const MeshDev& m, int degree, const GradArgs<float>& a, hipStream_t s);
 int launch_div32(const MeshDev& m, int degree, const DivArgs<float>& a, hipStream_t s);
 int launch_fdm64(const MeshDev& m, int degree, const FdmArgs<double>& a, hipStream_t s);
+// explicit residual with its flux integrals over-integrated at m.nq points per direction (all
+// cells, general faces); returns -6 for an unsupported (degree, nq)
+int launch_explicit_oi(const MeshDev& m, int degree, const double* U, double* R, hipStream_t s);
 int launch_fdm32(const MeshDev& m, int degree, const FdmArgs<float>& a, hipStream_t s);
 // per-cell sound speed (lam) and preconditioner coefficients from h and w J
 int launch_cellcoef(const MeshDev& m, int degree, const double* h, const double* wJ, double dta,

@@ -560,6 +560,27 @@ void fdm_eigen(int np, const std::vector<long double>& x, const std::vector<long
   }
 }
 
+// Over-integration table (OiLayout): NQ Gauss points and weights, the nodal basis and its
+// derivative at the points, and the basis at the points mapped into either half of [-1, 1].
+std::vector<double> make_oi_tables(int np, int nq) {
+  OiLayout L{np, nq};
+  std::vector<double> t(L.size(), 0.0);
+  std::vector<long double> x, w, xq, wq;
+  gauss_legendre(np, x, w);
+  gauss_legendre(nq, xq, wq);
+  for (int q = 0; q < nq; ++q) {
+    t[L.xq() + q] = (double)xq[q];
+    t[L.wq() + q] = (double)wq[q];
+    for (int j = 0; j < np; ++j) {
+      t[L.bq() + q * np + j] = (double)lagrange(x, j, xq[q]);
+      t[L.dq() + q * np + j] = (double)lagrange_d(x, j, xq[q]);
+      for (int h = 0; h < 2; ++h)
+        t[L.bs() + (h * nq + q) * np + j] = (double)lagrange(x, j, (xq[q] + 2 * h - 1) / 2);
+    }
+  }
+  return t;
+}
+
 std::vector<double> make_tables(int np) {
   TabLayout TL{np};
   std::vector<double> t(TL.size(), 0.0);
@@ -616,6 +637,7 @@ struct dg_ctx {
   int* d_lists = nullptr;  // cells with conforming faces only, then cells with a 2:1 face
   double* d_tab = nullptr;
   float* d_tabf = nullptr;
+  double* d_oitab = nullptr;  // over-integration table (quad_extra > 0)
   // geometry / background
   double *pbar = nullptr, *rbar = nullptr, *wJ = nullptr;
   double* tau = nullptr;  // absorbing-layer rate per node (only with an absorbing layer)
@@ -721,6 +743,7 @@ void make_plan(dg_ctx* c, Plan& P) {
   P.add((void**)&c->d_fnbr, nc * 2 * D * sizeof(int4));
   P.add((void**)&c->d_tab, TL.size() * d8);
   P.add((void**)&c->d_tabf, TL.size() * f4);
+  if (c->opt.quad_extra > 0) P.add((void**)&c->d_oitab, OiLayout{c->degree + 1, c->degree + 1 + c->opt.quad_extra}.size() * d8);
   P.add((void**)&c->pbar, ld * d8);
   P.add((void**)&c->rbar, ld * d8);
   P.add((void**)&c->wJ, ld * d8);
@@ -778,6 +801,9 @@ dg_status prepare(dg_ctx* c, const dg_case_desc* desc, int degree, const dg_opti
   if (o.gmres_restart < 1 || o.gmres_restart > kMaxV - 1) return fail(c, DG_EINVAL, "gmres_restart must be in [1, 31]");
   if (o.inner_restart < 1 || o.inner_restart > kMaxV - 1) return fail(c, DG_EINVAL, "inner_restart must be in [1, 31]");
   if (o.precision != DG_FP64 && o.precision != DG_FP32_INNER) return fail(c, DG_EINVAL, "bad precision");
+  if (o.quad_extra < 0) return fail(c, DG_EINVAL, "quad_extra must be >= 0");
+  if (o.quad_extra > 3 || degree + 1 + o.quad_extra > kMaxNq)
+    return fail(c, DG_EUNSUPPORTED, "over-integration needs quad_extra <= 3 and degree + 1 + quad_extra <= 8");
   if (o.preconditioner != DG_PREC_DIAGONAL && o.preconditioner != DG_PREC_CELL_FDM)
     return fail(c, DG_EINVAL, "bad preconditioner");
   if (desc->orography < 0 || desc->orography > 4) return fail(c, DG_EINVAL, "bad orography kind");
@@ -1166,7 +1192,10 @@ dg_status solve_mixed(dg_ctx* c, double dta, int& its, int& outer, double& relre
 // ----------------------------------------------------------------------------------- operators
 dg_status explicit_residual(dg_ctx* c, const double* U, double* R) {
   int re;
-  TIMEDB(0, 16.0 * c->F * c->N, re = launch_explicit(c->md, c->degree, U, R, c->stream));
+  if (c->md.nq > 0)
+    TIMEDB(0, 16.0 * c->F * c->N, re = launch_explicit_oi(c->md, c->degree, U, R, c->stream));
+  else
+    TIMEDB(0, 16.0 * c->F * c->N, re = launch_explicit(c->md, c->degree, U, R, c->stream));
   LCHK(re);
   if (c->tau) {
     if (c->D == 2)
@@ -1333,6 +1362,7 @@ void dg_default_options(dg_options* o) {
   o->inner_maxit = 500;
   o->penalty_beta = 1.0;
   o->preconditioner = DG_PREC_CELL_FDM;
+  o->quad_extra = 0;
 }
 
 const char* dg_last_error(void) { return g_last_error.c_str(); }
@@ -1398,6 +1428,8 @@ dg_status dg_setup(const dg_case_desc* desc, int32_t degree, const dg_options* o
   for (int i = 0; i < M.ncell; ++i) cells[i] = make_int4(M.cell[4 * i], M.cell[4 * i + 1], M.cell[4 * i + 2], M.cell[4 * i + 3]);
   for (size_t i = 0; i < nbr.size(); ++i) nbr[i] = make_int4(M.fnbr[4 * i], M.fnbr[4 * i + 1], M.fnbr[4 * i + 2], M.fnbr[4 * i + 3]);
   std::vector<double> tab = make_tables(c->degree + 1);
+  std::vector<double> oitab;
+  if (c->opt.quad_extra > 0) oitab = make_oi_tables(c->degree + 1, c->degree + 1 + c->opt.quad_extra);
   std::vector<float> tabf(tab.begin(), tab.end());
   hipStream_t s = c->stream;
 #define SETUP_CHK(call)                                                             \
@@ -1434,6 +1466,8 @@ dg_status dg_setup(const dg_case_desc* desc, int32_t degree, const dg_options* o
   SETUP_CHK(hipMemcpyAsync(c->d_fnbr, nbr.data(), nbr.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   SETUP_CHK(hipMemcpyAsync(c->d_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s));
   SETUP_CHK(hipMemcpyAsync(c->d_tabf, tabf.data(), tabf.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  if (!oitab.empty())
+    SETUP_CHK(hipMemcpyAsync(c->d_oitab, oitab.data(), oitab.size() * sizeof(double), hipMemcpyHostToDevice, s));
   MeshDev& md = c->md;
   md.dim = c->D;
   md.ncell = M.ncell;
@@ -1447,6 +1481,8 @@ dg_status dg_setup(const dg_case_desc* desc, int32_t degree, const dg_options* o
   md.nirr = M.ncell - nreg;
   md.tab = c->d_tab;
   md.tabf = c->d_tabf;
+  md.oitab = c->d_oitab;
+  md.nq = c->opt.quad_extra > 0 ? c->degree + 1 + c->opt.quad_extra : 0;
   for (int a = 0; a < 3; ++a) {
     md.L[a] = M.L[a];
     md.nb[a] = M.nb[a];

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_function():
 def test_default_options():
     o = P.options()
     assert (o.fp_iters, o.gmres_restart, o.gmres_maxit, o.inner_restart) == (2, 15, 2000, 30)
-    assert o.gmres_rtol == 1e-12 and o.precision == P.DG_FP64
+    assert o.gmres_rtol == 1e-12 and o.precision == P.DG_FP64 and o.quad_extra == 0
 
 
 @pytest.mark.parametrize("mk", [C.tiny2d, C.tiny3d, C.twolevel2d, C.twolevel3d, C.walls2d])
