@@ -38,10 +38,12 @@ struct Oi {
   // face arrays: own node traces, neighbour node traces (per sub-face), point values, node sums
   static constexpr int FO = NF * NV * NPF;
   static constexpr int FN = NF * MS * NV * NPF;
-  static constexpr int FL = MS * NV * NFQ;
+  static constexpr int FL = NF * MS * NV * NFQ;
   static constexpr int FG = NF * NV * NPF;
-  static constexpr int R1 = cmax(cmax(NV * (IA + IB + NVQ), D * NV * (CA + CB)), FO + FN + FL + FG);
-  static constexpr int LDS = 8 * (2 * NV * NL + D * NV * NVQ + R1 + OiLayout{NP, NQ}.size());
+  static constexpr int SF = D * NV * NVQ;
+  // after the volume terms the face arrays reuse the flux and scratch buffers together
+  static constexpr int R1 = cmax(cmax(NV * (IA + IB + NVQ), D * NV * (CA + CB)), FO + FN + FL + FG - SF);
+  static constexpr int LDS = 8 * (2 * NV * NL + SF + R1 + OiLayout{NP, NQ}.size());
 };
 
 // y = M x along one axis of a tensor array: x has extent nin along the axis, y extent nout;
@@ -183,9 +185,9 @@ __global__ void __launch_bounds__(256) k_exp_oi(const double* __restrict__ U, do
   }
 
   // ------------------------------------------------------------------ faces
-  double* sTO = sR;                  // [NF][NV][NPF]
+  double* sTO = sF;                  // [NF][NV][NPF]
   double* sTN = sTO + C::FO;         // [NF][MS][NV][NPF]
-  double* sL = sTN + C::FN;          // [MS][NV][NFQ]
+  double* sL = sTN + C::FN;          // [NF][MS][NV][NFQ]
   double* sG = sL + C::FL;           // [NF][NV][NPF]
   // node traces: own (LDS) and neighbours (HBM / L2, along their normal lines)
   for (int t = tid; t < NF * NV * NPF; t += NT) {
@@ -209,10 +211,13 @@ __global__ void __launch_bounds__(256) k_exp_oi(const double* __restrict__ U, do
   }
   __syncthreads();
 
-  for (int f = 0; f < NF; ++f) {
+  // flux at every point of every (sub-)face, times the face weight
+  for (int t = tid; t < NF * MS * NFQ; t += NT) {
+    const int f = t / (MS * NFQ), sub = (t / NFQ) % MS, j = t % NFQ;
     const int k = f >> 1, s = f & 1;
     const int kd = m.fkind[cell * NF + f];
-    const int nsub = kd == kCoarse ? MS : 1;
+    if (kd != kCoarse && sub > 0) continue;
+    const int j0 = j % NQ, j1 = D == 3 ? j / NQ : 0;
     // this cell's position on its coarse neighbour's face (fine side)
     int cs[2] = {0, 0};
     {
@@ -221,107 +226,104 @@ __global__ void __launch_bounds__(256) k_exp_oi(const double* __restrict__ U, do
       for (int ax = 0; ax < D; ++ax)
         if (ax != k) cs[tt++] = cid[ax] & 1;
     }
-    // flux at every (sub-)face point, times the face weight
-    for (int t = tid; t < nsub * NFQ; t += NT) {
-      const int sub = t / NFQ, j = t % NFQ;
-      const int j0 = j % NQ, j1 = D == 3 ? j / NQ : 0;
-      // own-side and neighbour-side interpolation matrices per tangential direction
+    // own-side and neighbour-side interpolation matrices per tangential direction
+    const int c0 = sub & 1, c1 = sub >> 1;
+    const double* Mo0 = kd == kCoarse ? Bs + c0 * NQ * NP : Bq;
+    const double* Mo1 = kd == kCoarse ? Bs + c1 * NQ * NP : Bq;
+    const double* Mn0 = kd == kFine ? Bs + cs[0] * NQ * NP : Bq;
+    const double* Mn1 = kd == kFine ? Bs + cs[1] * NQ * NP : Bq;
+    double tm[NV], tn[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double* To = sTO + (f * NV + v) * NPF;
+      const double* Tn = sTN + ((f * MS + sub) * NV + v) * NPF;
+      double a = 0.0, b = 0.0;
+      if constexpr (D == 3) {
+#pragma unroll 1
+        for (int a1 = 0; a1 < NP; ++a1) {
+          double ra = 0.0, rb = 0.0;
+#pragma unroll 1
+          for (int a0 = 0; a0 < NP; ++a0) {
+            ra += Mo0[j0 * NP + a0] * To[a0 + NP * a1];
+            rb += Mn0[j0 * NP + a0] * Tn[a0 + NP * a1];
+          }
+          a += Mo1[j1 * NP + a1] * ra;
+          b += Mn1[j1 * NP + a1] * rb;
+        }
+      } else {
+#pragma unroll 1
+        for (int a0 = 0; a0 < NP; ++a0) {
+          a += Mo0[j0 * NP + a0] * To[a0];
+          b += Mn0[j0 * NP + a0] * Tn[a0];
+        }
+      }
+      tm[v] = a;
+      tn[v] = b;
+    }
+    // area-weighted normal at the point, from the integer description of the (sub)face
+    const int lf = kd == kCoarse ? lev + 1 : lev;
+    int P = kd == kCoarse ? (s ? 2 * (cid[k] + 1) : 2 * cid[k]) : (s ? cid[k] + 1 : cid[k]);
+    if (m.per[k] && P >= m.nlev[lf][k]) P -= m.nlev[lf][k];
+    double X[D];
+    {
+      int tt = 0;
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) {
+        const double dx = m.dxl[lf][ax];
+        if (ax == k) {
+          X[ax] = dx * (double)P;
+        } else {
+          const int Tt = kd == kCoarse ? 2 * cid[ax] + ((sub >> tt) & 1) : cid[ax];
+          X[ax] = dx * ((double)Tt + 0.5 * (1.0 + xq[tt == 0 ? j0 : j1]));
+          ++tt;
+        }
+      }
+    }
+    double Gam[D][D], Jf, Nv[D];
+    metric<D, double>(m, lf, X, Gam, Jf);
+#pragma unroll
+    for (int a = 0; a < D; ++a) Nv[a] = Gam[k][a];
+    const double wj = D == 3 ? wq[j0] * wq[j1] : wq[j0];
+    double F[NV];
+    double sgn = s ? 1.0 : -1.0;
+    if (kd == kWall) {
+      double No[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) No[a] = sgn * Nv[a];
+      wall_flux<D>(tm, No, F);
+      sgn = 1.0;
+    } else if (s) {
+      rusanov<D>(tm, tn, Nv, F);
+    } else {
+      rusanov<D>(tn, tm, Nv, F);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sL[((f * MS + sub) * NV + v) * NFQ + j] = -sgn * wj * F[v];
+  }
+  __syncthreads();
+  // back onto the face nodes (transposed own-side interpolation), every face at once
+  for (int t = tid; t < NF * NV * NPF; t += NT) {
+    const int f = t / (NV * NPF), v = (t / NPF) % NV, a = t % NPF;
+    const int kd = m.fkind[cell * NF + f];
+    const int nsub = kd == kCoarse ? MS : 1;
+    const int a0 = a % NP, a1 = D == 3 ? a / NP : 0;
+    double g = 0.0;
+#pragma unroll 1
+    for (int sub = 0; sub < nsub; ++sub) {
       const int c0 = sub & 1, c1 = sub >> 1;
       const double* Mo0 = kd == kCoarse ? Bs + c0 * NQ * NP : Bq;
       const double* Mo1 = kd == kCoarse ? Bs + c1 * NQ * NP : Bq;
-      const double* Mn0 = kd == kFine ? Bs + cs[0] * NQ * NP : Bq;
-      const double* Mn1 = kd == kFine ? Bs + cs[1] * NQ * NP : Bq;
-      double tm[NV], tn[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const double* To = sTO + (f * NV + v) * NPF;
-        const double* Tn = sTN + ((f * MS + sub) * NV + v) * NPF;
-        double a = 0.0, b = 0.0;
-        if constexpr (D == 3) {
+      const double* Lp = sL + ((f * MS + sub) * NV + v) * NFQ;
 #pragma unroll 1
-          for (int a1 = 0; a1 < NP; ++a1) {
-            double ra = 0.0, rb = 0.0;
-#pragma unroll 1
-            for (int a0 = 0; a0 < NP; ++a0) {
-              ra += Mo0[j0 * NP + a0] * To[a0 + NP * a1];
-              rb += Mn0[j0 * NP + a0] * Tn[a0 + NP * a1];
-            }
-            a += Mo1[j1 * NP + a1] * ra;
-            b += Mn1[j1 * NP + a1] * rb;
-          }
-        } else {
-#pragma unroll 1
-          for (int a0 = 0; a0 < NP; ++a0) {
-            a += Mo0[j0 * NP + a0] * To[a0];
-            b += Mn0[j0 * NP + a0] * Tn[a0];
-          }
-        }
-        tm[v] = a;
-        tn[v] = b;
+      for (int j = 0; j < NFQ; ++j) {
+        const int j0 = j % NQ, j1 = D == 3 ? j / NQ : 0;
+        const double b = D == 3 ? Mo0[j0 * NP + a0] * Mo1[j1 * NP + a1] : Mo0[j0 * NP + a0];
+        g += b * Lp[j];
       }
-      // area-weighted normal at the point, from the integer description of the (sub)face
-      const int lf = kd == kCoarse ? lev + 1 : lev;
-      int P = kd == kCoarse ? (s ? 2 * (cid[k] + 1) : 2 * cid[k]) : (s ? cid[k] + 1 : cid[k]);
-      if (m.per[k] && P >= m.nlev[lf][k]) P -= m.nlev[lf][k];
-      double X[D];
-      {
-        int tt = 0;
-#pragma unroll
-        for (int ax = 0; ax < D; ++ax) {
-          const double dx = m.dxl[lf][ax];
-          if (ax == k) {
-            X[ax] = dx * (double)P;
-          } else {
-            const int Tt = kd == kCoarse ? 2 * cid[ax] + ((sub >> tt) & 1) : cid[ax];
-            X[ax] = dx * ((double)Tt + 0.5 * (1.0 + xq[tt == 0 ? j0 : j1]));
-            ++tt;
-          }
-        }
-      }
-      double Gam[D][D], Jf, Nv[D];
-      metric<D, double>(m, lf, X, Gam, Jf);
-#pragma unroll
-      for (int a = 0; a < D; ++a) Nv[a] = Gam[k][a];
-      const double wj = D == 3 ? wq[j0] * wq[j1] : wq[j0];
-      double F[NV];
-      double sgn = s ? 1.0 : -1.0;
-      if (kd == kWall) {
-        double No[D];
-#pragma unroll
-        for (int a = 0; a < D; ++a) No[a] = sgn * Nv[a];
-        wall_flux<D>(tm, No, F);
-        sgn = 1.0;
-      } else if (s) {
-        rusanov<D>(tm, tn, Nv, F);
-      } else {
-        rusanov<D>(tn, tm, Nv, F);
-      }
-#pragma unroll
-      for (int v = 0; v < NV; ++v) sL[(sub * NV + v) * NFQ + j] = -sgn * wj * F[v];
     }
-    __syncthreads();
-    // back onto the face nodes (transposed own-side interpolation)
-    for (int t = tid; t < NV * NPF; t += NT) {
-      const int v = t / NPF, a = t % NPF;
-      const int a0 = a % NP, a1 = D == 3 ? a / NP : 0;
-      double g = 0.0;
-#pragma unroll 1
-      for (int sub = 0; sub < nsub; ++sub) {
-        const int c0 = sub & 1, c1 = sub >> 1;
-        const double* Mo0 = kd == kCoarse ? Bs + c0 * NQ * NP : Bq;
-        const double* Mo1 = kd == kCoarse ? Bs + c1 * NQ * NP : Bq;
-        const double* Lp = sL + (sub * NV + v) * NFQ;
-#pragma unroll 1
-        for (int j = 0; j < NFQ; ++j) {
-          const int j0 = j % NQ, j1 = D == 3 ? j / NQ : 0;
-          const double b = D == 3 ? Mo0[j0 * NP + a0] * Mo1[j1 * NP + a1] : Mo0[j0 * NP + a0];
-          g += b * Lp[j];
-        }
-      }
-      sG[(f * NV + v) * NPF + a] = g;
-    }
-    __syncthreads();
+    sG[t] = g;
   }
+  __syncthreads();
 
   // ------------------------------------------------------------------ lift and finalize
   for (int t = tid; t < NL; t += NT) {
