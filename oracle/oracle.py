@@ -21,6 +21,10 @@ paper (Orlando, Benacchio, Bonaventura, arXiv 2408.08129):
   d m / dt = -tau (m - rho u_ref e_x), explicit, with the sin^2 rate profile of Klemp and Lilly
   (1978) below the lid and along the lateral sides, walled or periodic (mass and total energy
   untouched: the layer turns the damped kinetic energy into heat).
+* Optional enthalpy split of the implicit energy flux (enthalpy_split=True): the background part
+  of div(h m) is taken as hbar div(m) + m . grad(hbar), with the continuity equation's discrete
+  divergence and the exact height derivative of the background enthalpy, so that the discrete
+  buoyancy balance of grid-scale modes keeps the sign of N^2.
 
 The pressure unknown of the implicit stage is the perturbation p' = p - pbar from the analytic
 hydrostatic background evaluated at every node, so that an atmosphere at rest has exactly zero
@@ -193,10 +197,11 @@ class Oracle:
     ARK_D = 1.0 / (2.0 * math.sqrt(2.0))
     ARK_A = (3.0 + 2.0 * math.sqrt(2.0)) / 6.0
 
-    def __init__(self, case: Case, beta: float = 1.0, quad_extra: int = 0):
+    def __init__(self, case: Case, beta: float = 1.0, quad_extra: int = 0, enthalpy_split: bool = False):
         self.case = case
         self.beta = beta
         self.quad_extra = quad_extra
+        self.enthalpy_split = enthalpy_split
         self._cs = case.to_struct()
         h = ctypes.c_void_p()
         rc = lib().oc_mesh_build(ctypes.byref(self._cs), ctypes.byref(h))
@@ -227,6 +232,7 @@ class Oracle:
         L.oc_cell_sizes(h, _p(sz))
         self.cell_sizes = sz
         self.tau = self.sponge_rate()
+        self.hbar, self.dhbar = self.background_enthalpy()
         if quad_extra > 0:
             # over-integration of the explicit flux: r + 1 + quad_extra Gauss points per direction
             if L.oc_set_quadrature(h, self.r + 1 + quad_extra) != 0:
@@ -283,6 +289,29 @@ class Oracle:
             R[1] += self.tau * U[0] * uref
         return R
 
+    def background_enthalpy(self):
+        """Enthalpy of the hydrostatic background at the nodes, hbar = gamma pbar / ((gamma-1) rhobar),
+        and its vertical derivative from the closed form of the background (dp/dz = -rho g):
+        d hbar / dz = -g + c_p T N^2 / g in the stratified atmosphere, 0 in the isothermal one."""
+        hbar = GAMMA * self.pbar / ((GAMMA - 1.0) * self.rbar)
+        if self.case.atm_kind == STRATIFIED:
+            Nb = float(self.case.atm[2])
+            T = self.pbar / (RGAS * self.rbar)
+            dhbar = -G + GAMMA * RGAS / (GAMMA - 1.0) * T * Nb * Nb / G
+        else:
+            dhbar = np.zeros(self.N)
+        return hbar, dhbar
+
+    def enthalpy_flux_div(self, h: np.ndarray, m: np.ndarray) -> np.ndarray:
+        """Weak divergence of the implicit energy flux h m.  Plain: C(h m).  With the enthalpy
+        split the background part is written as hbar div(m) + m . grad(hbar) with the same discrete
+        divergence C as the continuity equation and the exact gradient of hbar (which depends on
+        the height only): C((h - hbar) m) + hbar C(m) + M (d hbar/dz) m_z."""
+        if not self.enthalpy_split:
+            return self.div(h[None, :] * m)
+        return (self.div((h - self.hbar)[None, :] * m) + self.hbar * self.div(m)
+                + self.wJ * self.dhbar * m[self.d - 1])
+
     def grad(self, p: np.ndarray) -> np.ndarray:
         """M^{-1} B p, shape (d, N)."""
         p = np.ascontiguousarray(p, dtype=np.float64)
@@ -331,7 +360,7 @@ class Oracle:
         out = self.wJ * p / (GAMMA - 1.0)
         if self.beta != 0.0:
             out = out + dta * self.beta / (2.0 * (GAMMA - 1.0)) * self.penalty(lam, p)
-        out = out - dta * dta * self.div(h[None, :] * q)
+        out = out - dta * dta * self.enthalpy_flux_div(h, q)
         return out
 
     def jacobi_diag(self, dta: float, h: np.ndarray) -> np.ndarray:
@@ -432,7 +461,7 @@ class Oracle:
         q = self.grad(pp)
         F[1:1 + d] = -q
         F[d] -= (rho - self.rbar) * G
-        e = self.div(h[None, :] * U[1:1 + d])
+        e = self.enthalpy_flux_div(h, U[1:1 + d])
         if self.beta != 0.0:
             e = e + self.beta / (2.0 * (GAMMA - 1.0)) * self.penalty(lam, pp)
         F[1 + d] = -e / self.wJ
@@ -464,7 +493,7 @@ class Oracle:
                 h = self.enthalpy(self.pbar + pp, rho_i)
                 rk = 0.5 * np.sum(m * m, axis=0) / rho_i
                 lam = self.cell_sound_speed(h)
-                rhs = self.wJ * (et - rk - self.pbar / (GAMMA - 1.0)) - dta * self.div(h[None, :] * mprime)
+                rhs = self.wJ * (et - rk - self.pbar / (GAMMA - 1.0)) - dta * self.enthalpy_flux_div(h, mprime)
                 op = lambda v, h=h, lam=lam: self.helmholtz(dta, h, lam, v)
                 r0 = rhs - op(pp)
                 dinv = 1.0 / self.jacobi_diag(dta, h)
