@@ -106,7 +106,13 @@ typedef struct {
  *     terms): its volume and face integrals use degree + 1 + quad_extra Gauss points per direction
  *     (on a 2:1 face the fine sub-face's points), the mass matrix stays the nodal one and the
  *     gravity work pointwise; 0 (default) keeps the nodal rule.  quad_extra <= 3 and
- *     degree + 1 + quad_extra <= 8, else DG_EUNSUPPORTED; negative: DG_EINVAL. */
+ *     degree + 1 + quad_extra <= 8, else DG_EUNSUPPORTED; negative: DG_EINVAL;
+ *   enthalpy_split: 1 splits the implicit energy flux div(h m) into the perturbation part
+ *     div((h - hbar) m) and the background part hbar div(m) + m . grad(hbar), the latter with the
+ *     continuity equation's discrete divergence and the exact height derivative of the background
+ *     enthalpy hbar = gamma pbar / ((gamma - 1) rhobar); this keeps the discrete buoyancy balance
+ *     of grid-scale modes stable in a stratified atmosphere (with the plain flux they grow, with
+ *     e-folding times of 20-60 s; long runs also need penalty_beta = 0).  0 (default): plain. */
 typedef struct {
   int32_t fp_iters;
   int32_t gmres_restart;
@@ -120,6 +126,7 @@ typedef struct {
   double penalty_beta;
   int32_t preconditioner;
   int32_t quad_extra;
+  int32_t enthalpy_split;
 } dg_options;
 
 /* Per-step statistics ([implicit stage][fixed-point iteration]). */

@@ -52,7 +52,8 @@ class dg_options(ctypes.Structure):
                 ("gmres_atol", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("inner_rtol", ctypes.c_double), ("inner_restart", ctypes.c_int32),
                 ("inner_maxit", ctypes.c_int32), ("penalty_beta", ctypes.c_double),
-                ("preconditioner", ctypes.c_int32), ("quad_extra", ctypes.c_int32)]
+                ("preconditioner", ctypes.c_int32), ("quad_extra", ctypes.c_int32),
+                ("enthalpy_split", ctypes.c_int32)]
 
 
 class dg_step_stats(ctypes.Structure):

@@ -984,8 +984,8 @@ int launch_grad32(const MeshDev& m, int degree, const GradArgs<float>& a, hipStr
   return r;
 }
 int launch_div32(const MeshDev& m, int degree, const DivArgs<float>& a, hipStream_t s) {
-  if (a.dinv || a.h || !a.p) return launch_div_cells32(m, degree, a, nullptr, m.ncell, s);
-  int r = div_col<float>(m, degree, a, s);
+  if (a.dinv || !a.p) return launch_div_cells32(m, degree, a, nullptr, m.ncell, s);
+  int r = a.h ? div_col<float, true>(m, degree, a, s) : div_col<float>(m, degree, a, s);
   if (r == 0) r = launch_div_hang32(m, degree, a, s);
   return r;
 }

@@ -376,6 +376,36 @@ __global__ void k_scale_cast(const double* __restrict__ a, double s, long N, flo
   GRID_LOOP(e, N) out[e] = (float)(s * a[e]);
 }
 
+// Background enthalpy hbar = gamma pbar / ((gamma - 1) rhobar) and its height derivative from the
+// closed form of the hydrostatic background: -g + c_p T N^2 / g (stratified), 0 (isothermal).
+__global__ void k_hbar(const double* __restrict__ pbar, const double* __restrict__ rbar, int strat, double Nbv,
+                       long N, double* __restrict__ hb, double* __restrict__ dhb, float* __restrict__ hb32,
+                       float* __restrict__ dhb32) {
+  GRID_LOOP(e, N) {
+    const double h = kGamma * pbar[e] / ((kGamma - 1.0) * rbar[e]);
+    const double T = pbar[e] / (kR * rbar[e]);
+    const double d = strat ? -kG + kGamma * kR / (kGamma - 1.0) * T * Nbv * Nbv / kG : 0.0;
+    hb[e] = h;
+    dhb[e] = d;
+    if (hb32) {
+      hb32[e] = (float)h;
+      dhb32[e] = (float)d;
+    }
+  }
+}
+
+// Enthalpy split: out += hbar * s2 + adiv (w J if weak) (d hbar/dz) q_z, s2 = adiv C(q) (weak form,
+// or with M^-1 applied when not weak).
+template <class T>
+__global__ void k_split_add(T* __restrict__ out, const T* __restrict__ s2, const T* __restrict__ hb,
+                            const T* __restrict__ dhb, const T* __restrict__ qz, double adiv, int weak,
+                            const double* __restrict__ wJ, long N) {
+  GRID_LOOP(e, N) {
+    const double m = weak ? wJ[e] : 1.0;
+    out[e] = (T)((double)out[e] + (double)hb[e] * (double)s2[e] + adiv * m * (double)dhb[e] * (double)qz[e]);
+  }
+}
+
 template <int D>
 __global__ void k_backsub(const double* __restrict__ mp, const double* __restrict__ q, double dta,
                           long N, long ld, double* __restrict__ Us) {
@@ -641,6 +671,9 @@ struct dg_ctx {
   // geometry / background
   double *pbar = nullptr, *rbar = nullptr, *wJ = nullptr;
   double* tau = nullptr;  // absorbing-layer rate per node (only with an absorbing layer)
+  // enthalpy split: background enthalpy, its height derivative, h - hbar (FP64 / FP32 copies)
+  double *hb = nullptr, *dhb = nullptr, *hp = nullptr;
+  float *hb32 = nullptr, *dhb32 = nullptr, *hp32 = nullptr;
   // step workspace
   double* FE[3] = {nullptr, nullptr, nullptr};
   double* FI[3] = {nullptr, nullptr, nullptr};
@@ -748,6 +781,16 @@ void make_plan(dg_ctx* c, Plan& P) {
   P.add((void**)&c->rbar, ld * d8);
   P.add((void**)&c->wJ, ld * d8);
   if (c->desc.sponge[1] > 0.0 || c->desc.sponge[3] > 0.0) P.add((void**)&c->tau, ld * d8);
+  if (c->opt.enthalpy_split) {
+    P.add((void**)&c->hb, ld * d8);
+    P.add((void**)&c->dhb, ld * d8);
+    P.add((void**)&c->hp, ld * d8);
+    if (c->opt.precision == DG_FP32_INNER) {
+      P.add((void**)&c->hb32, ld * f4);
+      P.add((void**)&c->dhb32, ld * f4);
+      P.add((void**)&c->hp32, ld * f4);
+    }
+  }
   for (int j = 0; j < 3; ++j) {
     P.add((void**)&c->FE[j], F * ld * d8);
     P.add((void**)&c->FI[j], F * ld * d8);
@@ -802,6 +845,7 @@ dg_status prepare(dg_ctx* c, const dg_case_desc* desc, int degree, const dg_opti
   if (o.inner_restart < 1 || o.inner_restart > kMaxV - 1) return fail(c, DG_EINVAL, "inner_restart must be in [1, 31]");
   if (o.precision != DG_FP64 && o.precision != DG_FP32_INNER) return fail(c, DG_EINVAL, "bad precision");
   if (o.quad_extra < 0) return fail(c, DG_EINVAL, "quad_extra must be >= 0");
+  if (o.enthalpy_split != 0 && o.enthalpy_split != 1) return fail(c, DG_EINVAL, "enthalpy_split must be 0 or 1");
   if (o.quad_extra > 3 || degree + 1 + o.quad_extra > kMaxNq)
     return fail(c, DG_EUNSUPPORTED, "over-integration needs quad_extra <= 3 and degree + 1 + quad_extra <= 8");
   if (o.preconditioner != DG_PREC_DIAGONAL && o.preconditioner != DG_PREC_CELL_FDM)
@@ -842,6 +886,10 @@ template <> struct PrecBuf<double> {
   static double* z(dg_ctx* c) { return c->z; }
   static double* lam(dg_ctx* c) { return c->lam; }
   static double* coef(dg_ctx* c) { return c->coef; }
+  static double* hp(dg_ctx* c) { return c->hp; }
+  static double* hb(dg_ctx* c) { return c->hb; }
+  static double* dhb(dg_ctx* c) { return c->dhb; }
+  static double* s2(dg_ctx* c) { return c->u; }
   static int grad(const MeshDev& m, int deg, const GradArgs<double>& a, hipStream_t s) { return launch_grad64(m, deg, a, s); }
   static int div(const MeshDev& m, int deg, const DivArgs<double>& a, hipStream_t s) { return launch_div64(m, deg, a, s); }
   static int fdm(const MeshDev& m, int deg, const FdmArgs<double>& a, hipStream_t s) { return launch_fdm64(m, deg, a, s); }
@@ -852,10 +900,42 @@ template <> struct PrecBuf<float> {
   static float* z(dg_ctx* c) { return c->z32; }
   static float* lam(dg_ctx* c) { return c->lam32; }
   static float* coef(dg_ctx* c) { return c->coef32; }
+  static float* hp(dg_ctx* c) { return c->hp32; }
+  static float* hb(dg_ctx* c) { return c->hb32; }
+  static float* dhb(dg_ctx* c) { return c->dhb32; }
+  static float* s2(dg_ctx* c) { return c->u32; }
   static int grad(const MeshDev& m, int deg, const GradArgs<float>& a, hipStream_t s) { return launch_grad32(m, deg, a, s); }
   static int div(const MeshDev& m, int deg, const DivArgs<float>& a, hipStream_t s) { return launch_div32(m, deg, a, s); }
   static int fdm(const MeshDev& m, int deg, const FdmArgs<float>& a, hipStream_t s) { return launch_fdm32(m, deg, a, s); }
 };
+
+// Weak divergence of the implicit energy flux h qv with the penalty / mass terms of a (a.h = h):
+// plain C(h qv), or with the enthalpy split C((h - hbar) qv) + hbar C(qv) + M (d hbar/dz) qv_z.
+template <class T>
+int energy_div(dg_ctx* c, const DivArgs<T>& a) {
+  using PB = PrecBuf<T>;
+  if (!c->opt.enthalpy_split) return PB::div(c->md, c->degree, a, c->stream);
+  DivArgs<T> a1 = a;
+  a1.h = PB::hp(c);
+  int r = PB::div(c->md, c->degree, a1, c->stream);
+  if (r) return r;
+  // qv stands in for the (unused: no penalty, no mass) scalar so that the column kernel runs
+  DivArgs<T> a2{a.qv, nullptr, a.qv, nullptr, T(1), a.lam, a.adiv, T(0), T(0), a.weak, PB::s2(c)};
+  r = PB::div(c->md, c->degree, a2, c->stream);
+  if (r) return r;
+  hipLaunchKernelGGL((k_split_add<T>), pw_grid(c->N), dim3(256), 0, c->stream, a.out, (const T*)PB::s2(c),
+                     (const T*)PB::hb(c), (const T*)PB::dhb(c), a.qv + (size_t)(c->D - 1) * c->ld,
+                     (double)a.adiv, a.weak, (const double*)c->wJ, c->N);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// h - hbar for the enthalpy split, after h (and h32) changed
+void split_update(dg_ctx* c) {
+  if (!c->opt.enthalpy_split) return;
+  hipLaunchKernelGGL(k_sub, pw_grid(c->N), dim3(256), 0, c->stream, c->h, c->hb, c->N, c->hp);
+  if (c->opt.precision == DG_FP32_INNER)
+    hipLaunchKernelGGL(k_scale_cast, pw_grid(c->N), dim3(256), 0, c->stream, c->hp, 1.0, c->N, c->hp32);
+}
 
 // w = A(h) p in precision T.  With dinv == null and scale == 1, p = v is taken as given; else
 // p = scale * dinv * v is formed on the fly and written to the z buffer by pass 1.
@@ -866,18 +946,20 @@ int apply_A(dg_ctx* c, double dta, const T* v, const T* dinv, T scale, T* w) {
   const bool given = (dinv == nullptr && scale == T(1));
   T* zout = given ? nullptr : PB::z(c);
   const T* p = given ? v : PB::z(c);
-  GradArgs<T> g{v, dinv, scale, PB::q(c), PB::h(c), zout};
+  // with the enthalpy split pass 1 leaves q = M^-1 B p and pass 2 applies the split flux of h q
+  const bool split = c->opt.enthalpy_split != 0;
+  GradArgs<T> g{v, dinv, scale, PB::q(c), split ? nullptr : PB::h(c), zout};
   const double nb = (double)sizeof(T) * c->N;
   int rg;
   // pass 1: v (and dinv), h in; h M^-1 B p (d fields) and, if formed here, p out
   TIMEDB(1, nb * ((dinv ? 2 : 1) + 1 + c->D + (given ? 0 : 1)), rg = PB::grad(c->md, c->degree, g, c->stream));
   if (rg) return -1;
   const double beta = c->opt.penalty_beta;
-  DivArgs<T> a{PB::q(c), nullptr, p, nullptr, T(1), PB::lam(c), (T)(-dta * dta),
+  DivArgs<T> a{PB::q(c), split ? PB::h(c) : nullptr, p, nullptr, T(1), PB::lam(c), (T)(-dta * dta),
                (T)(dta * beta / (2.0 * (kGamma - 1.0))), (T)(1.0 / (kGamma - 1.0)), 1, w};
   int rd;
   // pass 2: d fields and p in; A p out
-  TIMEDB(2, nb * (c->D + 2), rd = PB::div(c->md, c->degree, a, c->stream));
+  TIMEDB(2, nb * (c->D + 2), rd = energy_div<T>(c, a));
   return rd;
 }
 
@@ -1218,6 +1300,7 @@ dg_status implicit_term(dg_ctx* c, const double* U, double* F) {
     TIMED(4, hipLaunchKernelGGL((k_pressure_h<3>), pw_grid(N), dim3(256), 0, c->stream, U, c->pbar, N, ld, c->pp, c->h));
   TIMED(4, hipLaunchKernelGGL(k_lam, dim3((c->hm.ncell + 3) / 4), dim3(256), 0, c->stream, c->h, c->NL,
                      c->hm.ncell, c->lam, (float*)nullptr));
+  TIMED(4, split_update(c));
   GradArgs<double> g{c->pp, nullptr, 1.0, c->q, nullptr, nullptr};
   int rg;
   TIMED(1, rg = launch_grad64(c->md, c->degree, g, c->stream));
@@ -1230,7 +1313,7 @@ dg_status implicit_term(dg_ctx* c, const double* U, double* F) {
   DivArgs<double> a{U + ld, c->h, c->pp, nullptr, 1.0, c->lam, -1.0,
                     -beta / (2.0 * (kGamma - 1.0)), 0.0, 0, F + (size_t)(1 + D) * ld};
   int rd;
-  TIMED(2, rd = launch_div64(c->md, c->degree, a, c->stream));
+  TIMED(2, rd = energy_div<double>(c, a));
   LCHK(rd);
   return DG_OK;
 }
@@ -1275,10 +1358,11 @@ dg_status step_impl(dg_ctx* c, double* U, double dt, dg_step_stats* stats) {
                                        c->coef, mixed ? c->coef32 : nullptr, s));
         LCHK(rcc);
       }
+      TIMED(4, split_update(c));
       // b = -dta C(h m') + M (e~ - rho k - pbar/(gamma-1))
       DivArgs<double> a{c->mp, c->h, nullptr, nullptr, 1.0, c->lam, -dta, 0.0, 0.0, 1, c->b};
       int rd;
-      TIMED(2, rd = launch_div64(c->md, c->degree, a, s));
+      TIMED(2, rd = energy_div<double>(c, a));
       LCHK(rd);
       TIMED(4, hipLaunchKernelGGL((k_rhs_add<D>), pg, bs, 0, s, c->b, c->wJ, c->et, c->Us, c->pbar, N, ld));
       // r0 = b - A p'
@@ -1363,6 +1447,7 @@ void dg_default_options(dg_options* o) {
   o->penalty_beta = 1.0;
   o->preconditioner = DG_PREC_CELL_FDM;
   o->quad_extra = 0;
+  o->enthalpy_split = 0;
 }
 
 const char* dg_last_error(void) { return g_last_error.c_str(); }
@@ -1505,6 +1590,10 @@ dg_status dg_setup(const dg_case_desc* desc, int32_t degree, const dg_options* o
       dg_destroy(c);
       return fail(nullptr, DG_EDEVICE, "geometry kernel launch failed");
     }
+    if (c->opt.enthalpy_split)
+      hipLaunchKernelGGL(k_hbar, pw_grid(c->N), dim3(256), 0, s, (const double*)c->pbar, (const double*)c->rbar,
+                         c->desc.atmosphere == DG_ATM_STRATIFIED ? 1 : 0, c->desc.atm[2], c->N, c->hb, c->dhb,
+                         c->hb32, c->dhb32);
   }
   SETUP_CHK(hipStreamSynchronize(s));
 #undef SETUP_CHK
@@ -1602,6 +1691,7 @@ dg_status dg_apply_helmholtz(dg_ctx* c, double dta, const void* h, const void* p
     HIPCHK(hipMemcpyAsync(c->h, h, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     hipLaunchKernelGGL(k_lam, dim3((c->hm.ncell + 3) / 4), dim3(256), 0, c->stream, c->h, c->NL,
                        c->hm.ncell, c->lam, (float*)nullptr);
+    split_update(c);
     if (apply_A<double>(c, dta, (const double*)p, nullptr, 1.0, (double*)Ap)) return fail(c, DG_EDEVICE, "launch failed");
     return DG_OK;
   }
@@ -1613,6 +1703,7 @@ dg_status dg_apply_helmholtz(dg_ctx* c, double dta, const void* h, const void* p
     hipLaunchKernelGGL(k_widen, pw_grid(N), dim3(256), 0, c->stream, (const float*)c->h32, N, c->h);
     hipLaunchKernelGGL(k_lam, dim3((c->hm.ncell + 3) / 4), dim3(256), 0, c->stream, c->h, c->NL,
                        c->hm.ncell, c->lam, c->lam32);
+    split_update(c);
     if (apply_A<float>(c, dta, (const float*)p, nullptr, 1.0f, (float*)Ap)) return fail(c, DG_EDEVICE, "launch failed");
     return DG_OK;
   }

@@ -77,3 +77,76 @@ def test_stratified_column_stability(split, bound):
         assert w < bound, w
     else:
         assert w > 0.1, w  # the plain flux: grid-scale buoyancy modes have grown from 1e-3 K noise
+
+
+# ------------------------------------------------------------------------------- library / GPU
+def test_split_option_validated():
+    import paper_2408_08129_amd as P
+    assert P.options().enthalpy_split == 0
+    with pytest.raises(P.DGError) as e:
+        P.dg_footprint(C.product_case(C.tiny2d(2)), 2, P.options(enthalpy_split=2))
+    assert e.value.status == P.DG_EINVAL
+    assert P.dg_footprint(C.product_case(C.tiny2d(2)), 2, P.options(enthalpy_split=1)) > \
+        P.dg_footprint(C.product_case(C.tiny2d(2)), 2)
+
+
+def _gpu_pair(w, beta=1.0, **opt):
+    import paper_2408_08129_amd as P
+    print("[case] %s split beta %g %s" % ({k: w[k] for k in ("dim", "degree", "nbase")}, beta, opt), flush=True)
+    o = O.Oracle(C.oracle_case(w), beta=beta, enthalpy_split=True)
+    s = P.Solver(C.product_case(w), w["degree"], P.options(enthalpy_split=1, penalty_beta=beta, **opt))
+    perm = C.cell_perm(s.cell_table(), o.cells)
+    return o, s, perm
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("mk,r", [(C.tiny3d, 3), (C.twolevel2d, 4), (C.twolevel3d, 2), (C.walls2d, 3)])
+def test_gpu_split_operators(mk, r):
+    import paper_2408_08129_amd as P
+    from paper_2408_08129_amd import inputs
+    from tests.test_gpu_parity import TOL64, dev, host
+    o, s, perm = _gpu_pair(mk(r))
+    U = inputs.random_state(o.nf, o.N, seed=91 + r)
+    Fo = o.implicit_term(U)
+    F = C.to_oracle_order(host(s.implicit_term(dev(C.to_product_order(U, perm, o.nloc)))), perm, o.nloc)
+    for f in range(1, o.nf):
+        assert C.rel_err(F[f], Fo[f]) < TOL64, (f, C.rel_err(F[f], Fo[f]))
+    h = inputs.random_positive(o.N, 92 + r, 2.5e5, 3.5e5)
+    p = inputs.random_normal(o.N, 93 + r, 100.0)
+    dta = 0.37
+    ref = o.helmholtz(dta, h, o.cell_sound_speed(h), p)
+    Ap = host(s.apply_helmholtz(dta, dev(C.to_product_order(h, perm, o.nloc)),
+                                dev(C.to_product_order(p, perm, o.nloc)), P.DG_FP64))
+    assert C.rel_err(C.to_oracle_order(Ap, perm, o.nloc), ref) < TOL64
+    # the split differs from the plain flux here (stratified background)
+    o0 = O.Oracle(C.oracle_case(mk(r)))
+    assert C.rel_err(o0.helmholtz(dta, h, o0.cell_sound_speed(h), p), ref) > 1e-8
+    # FP32 operator with the oracle fed the FP32-rounded inputs
+    o32, s32, perm = _gpu_pair(mk(r), precision=P.DG_FP32_INNER)
+    h32, p32 = h.astype(np.float32), p.astype(np.float32)
+    ref = o32.helmholtz(dta, h32.astype(np.float64), o32.cell_sound_speed(h32.astype(np.float64)),
+                        p32.astype(np.float64))
+    Ap = s32.apply_helmholtz(dta, dev(C.to_product_order(h32, perm, o.nloc)),
+                             dev(C.to_product_order(p32, perm, o.nloc)), P.DG_FP32_INNER)
+    assert C.rel_err(C.to_oracle_order(host(Ap).astype(np.float64), perm, o.nloc), ref) < 2e-5
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("mk,r,beta,steps,dt,prec", [(C.twolevel3d, 2, 1.0, 3, 1.0, 0), (C.twolevel2d, 4, 0.0, 4, 0.5, 0),
+                                                     (C.twolevel3d, 2, 0.0, 3, 1.0, 1)])
+def test_gpu_split_steps(mk, r, beta, steps, dt, prec):
+    import math
+    from tests.test_gpu_parity import TOL_MIXED, TOL_STEP, dev, host
+    o, s, perm = _gpu_pair(mk(r), beta=beta, precision=prec)
+    Uo = o.initial_state(10.0)
+    U = dev(C.to_product_order(Uo, perm, o.nloc))
+    for _ in range(steps):
+        Uo = o.step(Uo, dt)
+        s.step(U, dt)
+    Ug = C.to_oracle_order(host(U), perm, o.nloc)
+    tol = TOL_MIXED if prec else TOL_STEP
+    for f in range(o.nf):
+        err = C.rel_err(Ug[f], Uo[f])
+        l2 = math.sqrt(np.sum(o.wJ * (Ug[f] - Uo[f]) ** 2) / np.sum(o.wJ * Uo[f] ** 2))
+        print("field %d max rel %.2e L2 rel %.2e" % (f, err, l2), flush=True)
+        assert err < tol and l2 < tol, (f, err, l2)
