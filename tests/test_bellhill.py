@@ -94,9 +94,23 @@ def test_slices_and_layers():
 
 @pytest.mark.gpu
 def test_gpu_bell_nonconforming_two_steps():
-    from tests.test_gpu_parity import _run_pair
+    """In the benchmark's configuration: enthalpy split, no pressure-jump penalty."""
+    import math
+    from tests.test_gpu_parity import TOL_STEP, dev, host
+    from tests.test_split import _gpu_pair
     w = _bell("bell3d_r4_nonconforming", 2)
-    _run_pair(w, 2, w["ubar"], w["dt"])
+    assert w["enthalpy_split"] == 1 and w["penalty_beta"] == 0.0
+    o, s, perm = _gpu_pair(w, beta=0.0)
+    Uo = o.initial_state(w["ubar"])
+    U = dev(C.to_product_order(Uo, perm, o.nloc))
+    for _ in range(2):
+        Uo = o.step(Uo, w["dt"])
+        s.step(U, w["dt"])
+    Ug = C.to_oracle_order(host(U), perm, o.nloc)
+    for f in range(o.nf):
+        err = C.rel_err(Ug[f], Uo[f])
+        l2 = math.sqrt(np.sum(o.wJ * (Ug[f] - Uo[f]) ** 2) / np.sum(o.wJ * Uo[f] ** 2))
+        assert err < TOL_STEP and l2 < TOL_STEP, (f, err, l2)
 
 
 @pytest.mark.gpu
