@@ -43,6 +43,24 @@ __device__ __forceinline__ int tang(int node, int k) {
   if (k == 1) return (node % NP) + NP * (node / (NP * NP));
   return node % (NP * NP);
 }
+// The NP values of a contiguous line (the x-normal line of a cell: nodes x fastest) in 16-byte
+// vector loads plus a scalar tail: gfx950 global loads need only the element alignment, and
+// across a wavefront one such line per lane reads ~20 cache lines per instruction, so fewer,
+// wider instructions cut the address-processing work.
+template <int NP, class T>
+__device__ __forceinline__ void load_line(const T* p, T (&v)[NP]) {
+  constexpr int W = 16 / (int)sizeof(T);
+  typedef T V __attribute__((ext_vector_type(W), aligned(sizeof(T))));
+#pragma unroll
+  for (int j = 0; j < NP / W; ++j) {
+    const V x = *(const V*)(p + j * W);
+#pragma unroll
+    for (int i = 0; i < W; ++i) v[j * W + i] = x[i];
+  }
+#pragma unroll
+  for (int q = NP / W * W; q < NP; ++q) v[q] = p[q];
+}
+
 template <int D, int NP>
 __device__ __forceinline__ int compose(int k, int q, int a) {
   if (D == 2) return k == 0 ? q + NP * a : a + NP * q;

@@ -124,6 +124,33 @@ __global__ void __launch_bounds__(256) k_col(const A a, const MeshDev m) {
     if (kind[f] != kConf) continue;
     const unsigned nbase = (unsigned)nb[f] * NL;
     const int mask = k == D - 1 ? (1 << D) - 1 : (1 << k);
+    if (k == 0) {
+      // x faces: the normal line is contiguous in memory (w_0 and p are exchanged)
+      const unsigned idx = nbase + offs<D, NP>(0, 0, c);
+      T wl[NP], pl[NP];
+      if constexpr (DIV) {
+        load_line<NP>(a.qv + idx, wl);
+        if constexpr (HH) {
+          T hl[NP];
+          load_line<NP>(a.h + idx, hl);
+#pragma unroll
+          for (int q = 0; q < NP; ++q) wl[q] *= hl[q];
+        }
+      }
+      if (!HH || a.p) {
+        load_line<NP>(a.p + idx, pl);
+      } else {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) pl[q] = 0;
+      }
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        const T lq = gtab[TL.lb() + (1 - s) * NP + q];
+        if constexpr (DIV) tn[f][0] += lq * wl[q];
+        tn[f][D] += lq * pl[q];
+      }
+      continue;
+    }
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
       const T lq = gtab[TL.lb() + (1 - s) * NP + q];
@@ -495,6 +522,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     for (int g = 0; g < NV; ++g) tn[f][g] = 0;
     if (kind[f] != kConf) continue;
     const unsigned nbase = (unsigned)nb[f] * NL;
+    if (k == 0) {
+      // x faces: the normal line is contiguous in memory
+      const unsigned idx = nbase + offs<D, NP>(0, 0, c);
+#pragma unroll
+      for (int g = 0; g < NV; ++g) {
+        T l[NP];
+        load_line<NP>(U + g * N + idx, l);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) tn[f][g] += gtab[TL.lb() + (1 - s) * NP + q] * l[q];
+      }
+      continue;
+    }
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
       const T lq = gtab[TL.lb() + (1 - s) * NP + q];

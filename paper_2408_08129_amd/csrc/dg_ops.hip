@@ -294,8 +294,8 @@ struct TerTab {
 //   P3 only for faces with a 2:1 neighbour: neighbour traces, sub-face fluxes, restriction
 //      (coarse side) / interpolation (fine side);
 //   P4 lift of all faces along the normal lines, finalize.
-// With HANG, only the 2:1 faces are evaluated and their lifted terms are added to the output
-// (the column kernels have written the rest for these cells).
+// With HANG, only the 2:1 faces are evaluated and lifted, and their terms are added to the
+// output (the column kernels have written the rest for these cells).
 template <int D, int NP, class Op, bool HANG>
 __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const MeshDev m,
                                                              const int* __restrict__ list, int n) {
@@ -311,7 +311,8 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
   constexpr int O_NB = 0;
   constexpr int O_FL = O_NB + CPB * MS * NTR * NFP;
   constexpr int SLOWSZ = O_FL + CPB * MS * NOUT * NFP;
-  constexpr int SCR = VOLSZ > SLOWSZ ? VOLSZ : SLOWSZ;
+  // the faces-only mode forms no volume fluxes: the scratch holds the 2:1 face buffers only
+  constexpr int SCR = (!HANG && VOLSZ > SLOWSZ) ? VOLSZ : SLOWSZ;
   constexpr int NH = TT::NH;
 
   __shared__ T sTab[TL.size()];
@@ -467,18 +468,20 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
   T acc[NOUT];
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) acc[o] = 0;
-  if (active && !HANG) {
+  if constexpr (!HANG) {  // the faces-only mode has no volume terms (and no volume scratch)
+    if (active) {
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-      const int ik = along<D, NP>(node, k);
-      const int base = compose<D, NP>(k, 0, tang<D, NP>(node, k));
-      const int str = k == 0 ? 1 : (k == 1 ? NP : NP * NP);
+      for (int k = 0; k < D; ++k) {
+        const int ik = along<D, NP>(node, k);
+        const int base = compose<D, NP>(k, 0, tang<D, NP>(node, k));
+        const int str = k == 0 ? 1 : (k == 1 ? NP : NP * NP);
 #pragma unroll
-      for (int q = 0; q < NP; ++q) {
-        const T dq = Dt[ik * NP + q];
+        for (int q = 0; q < NP; ++q) {
+          const T dq = Dt[ik * NP + q];
 #pragma unroll
-        for (int o = 0; o < NOUT; ++o)
-          if (Op::vidx(o, k) >= 0) acc[o] += dq * sScr[(lc * NVOL + Op::vidx(o, k)) * NL + base + q * str];
+          for (int o = 0; o < NOUT; ++o)
+            if (Op::vidx(o, k) >= 0) acc[o] += dq * sScr[(lc * NVOL + Op::vidx(o, k)) * NL + base + q * str];
+        }
       }
     }
   }
@@ -487,12 +490,7 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
     if (sId[c] < 0) continue;
     const int kind = sKind[c][f];
     if (kind != kConf && kind != kWall) continue;
-    if constexpr (HANG) {
-      // conforming and wall faces belong to the column kernel
-#pragma unroll
-      for (int o = 0; o < NOUT; ++o) sFr[((c * NF + f) * NOUT + o) * NFP + j] = 0;
-      continue;
-    }
+    if constexpr (HANG) continue;  // conforming and wall faces belong to the column kernel
     const int k = f >> 1, s = f & 1;
     T tm[NTR], tn[NTR];
 #pragma unroll
@@ -672,6 +670,7 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const Me
   if (active) {
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
+      if (HANG && sKind[lc][f] != kFine && sKind[lc][f] != kCoarse) continue;  // lift 2:1 faces only
       const int k = f >> 1, s = f & 1;
       const int ik = along<D, NP>(node, k);
       const int a = tang<D, NP>(node, k);

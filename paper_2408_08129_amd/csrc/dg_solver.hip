@@ -66,14 +66,20 @@ __device__ __forceinline__ void block_store(const double (&acc)[NV], double* par
   }
 }
 
-// Second stage: one wavefront per reduced value, fixed order.
-__global__ void k_reduce(const double* part, int nv, int G, double* out) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int i = wv; i < nv; i += kRedThreads / 64) {
-    double t = 0.0;
-    for (int b = lane; b < G; b += 64) t += part[(long)i * G + b];
-    t = wave_sum(t);
-    if (lane == 0) out[i] = t;
+// Second stage: one workgroup per reduced value (grid = nv), fixed order.
+__global__ void __launch_bounds__(kRedThreads) k_reduce(const double* part, int G, double* out) {
+  __shared__ double s[kRedThreads / 64];
+  const int i = blockIdx.x;
+  double t = 0.0;
+  for (int b = threadIdx.x; b < G; b += kRedThreads) t += part[(long)i * G + b];
+  t = wave_sum(t);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double u = 0.0;
+#pragma unroll
+    for (int k = 0; k < kRedThreads / 64; ++k) u += s[k];
+    out[i] = u;
   }
 }
 
@@ -979,7 +985,8 @@ int apply_AP(dg_ctx* c, double dta, const T* v, const T* dinv, T scale, T* w) {
 
 // reduce nv partial sums to host
 dg_status reduce_to_host(dg_ctx* c, int nv, int G, double* out) {
-  TIMED(6, hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, c->stream, c->part, nv, G, c->red));
+  if (nv < 1 || nv > 2 * kMaxV + 3) return fail(c, DG_EINVAL, "reduction of " + std::to_string(nv) + " values");
+  TIMED(6, hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(kRedThreads), 0, c->stream, c->part, G, c->red));
   HIPCHK(hipMemcpyAsync(c->hred, c->red, nv * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   memcpy(out, c->hred, nv * sizeof(double));
