@@ -61,8 +61,10 @@ __device__ __forceinline__ int offs(int k, int q, int a) {
   return compose<D, NP>(k, q, a);
 }
 
+// FP32 up to degree 4: the divergence fits 5 waves per SIMD (<= 96 VGPRs) and the gradient 6
+// (<= 80) without spills; the FP64 forms are limited by LDS (divergence) or would spill.
 template <int D, int NP, class T, bool DIV, class A, bool HH = false>
-__global__ void __launch_bounds__(256) k_col(const A a, const MeshDev m) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NP <= 5 ? (DIV ? (HH ? 1 : 5) : 6) : 1))) k_col(const A a, const MeshDev m) {
   using C = Col<D, NP>;
   constexpr int NC = C::NC, NL = C::NL, NF = C::NF, CPB = C::CPB, NHC = C::NHC;
   constexpr TabLayout TL{NP};
