@@ -296,8 +296,10 @@ struct TerTab {
 //   P4 lift of all faces along the normal lines, finalize.
 // With HANG, only the 2:1 faces are evaluated and lifted, and their terms are added to the
 // output (the column kernels have written the rest for these cells).
+// The faces-only mode asks for 4 waves per SIMD up to degree 4: its 2:1-face phases are latency
+// bound, and the register budget that buys (a few dwords of spill in the FP64 divergence) pays.
 template <int D, int NP, class Op, bool HANG>
-__global__ void __launch_bounds__((Cfg<D, NP>::NT)) k_cell(const Op op, const MeshDev m,
+__global__ void __launch_bounds__((Cfg<D, NP>::NT)) __attribute__((amdgpu_waves_per_eu(HANG && NP <= 5 ? 4 : 1))) k_cell(const Op op, const MeshDev m,
                                                              const int* __restrict__ list, int n) {
   using C = Cfg<D, NP>;
   using T = typename Op::T;
