@@ -83,35 +83,65 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce(const double* part, int 
   }
 }
 
+// The basis kernels stream 16 bytes per lane per access (two doubles or four floats; gfx950
+// global accesses need only the element alignment), with a scalar tail for n % W.
+template <class T>
+struct Vec16 {
+  static constexpr int W = 16 / (int)sizeof(T);
+  typedef T type __attribute__((ext_vector_type(W), aligned(sizeof(T))));
+};
+
 // Reduction pass of the Gram-Schmidt step: for i < NV the products V_i.x and (HASY) V_i.y,
 // then x.x and (HASY) x.y, y.y, accumulated in FP64.  Value order in part:
 // [V_i.x]_i, [V_i.y]_i, x.x, x.y, y.y (without y: [V_i.x]_i, x.x).
+template <int NV, bool HASY, int NA>
+__device__ __forceinline__ void dots_point(double (&acc)[NA], double xv, double yv, const double (&v)[NV > 0 ? NV : 1]) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    acc[i] += v[i] * xv;
+    if constexpr (HASY) acc[NV + i] += v[i] * yv;
+  }
+  if constexpr (HASY) {
+    acc[2 * NV] += xv * xv;
+    acc[2 * NV + 1] += xv * yv;
+    acc[2 * NV + 2] += yv * yv;
+  } else {
+    acc[NV] += xv * xv;
+  }
+}
+
 template <class T, int NV, bool HASY>
 __global__ void __launch_bounds__(kRedThreads) k_gs_dots(const T* __restrict__ V, long ld,
                                                          const T* __restrict__ x, const T* __restrict__ y,
                                                          double* part, long n) {
   constexpr int NA = HASY ? 2 * NV + 3 : NV + 1;
+  constexpr int W = Vec16<T>::W;
+  using VT = typename Vec16<T>::type;
   double acc[NA];
 #pragma unroll
   for (int i = 0; i < NA; ++i) acc[i] = 0.0;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-    const double xv = (double)x[e];
-    const double yv = HASY ? (double)y[e] : 0.0;
-    T v[NV > 0 ? NV : 1];
+  const long gt = (long)blockIdx.x * blockDim.x + threadIdx.x, gs = (long)gridDim.x * blockDim.x;
+  const long nvec = n / W;
+  for (long e = gt; e < nvec; e += gs) {
+    const VT xw = *(const VT*)(x + e * W);
+    VT yw = xw;
+    if constexpr (HASY) yw = *(const VT*)(y + e * W);
+    VT vw[NV > 0 ? NV : 1];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = V[i * ld + e];
+    for (int i = 0; i < NV; ++i) vw[i] = *(const VT*)(V + i * ld + e * W);
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      acc[i] += (double)v[i] * xv;
-      if constexpr (HASY) acc[NV + i] += (double)v[i] * yv;
+    for (int k = 0; k < W; ++k) {
+      double v[NV > 0 ? NV : 1];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) v[i] = (double)vw[i][k];
+      dots_point<NV, HASY>(acc, (double)xw[k], HASY ? (double)yw[k] : 0.0, v);
     }
-    if constexpr (HASY) {
-      acc[2 * NV] += xv * xv;
-      acc[2 * NV + 1] += xv * yv;
-      acc[2 * NV + 2] += yv * yv;
-    } else {
-      acc[NV] += xv * xv;
-    }
+  }
+  for (long e = nvec * W + gt; e < n; e += gs) {
+    double v[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = (double)V[i * ld + e];
+    dots_point<NV, HASY>(acc, (double)x[e], HASY ? (double)y[e] : 0.0, v);
   }
   block_store<NA>(acc, part);
 }
@@ -121,26 +151,58 @@ __global__ void __launch_bounds__(kRedThreads) k_gs_dots(const T* __restrict__ V
 //   x = x - sum_i a_i V_i            (only when NV > 0; in place)
 // and part = |z|^2.
 template <class T, int NV>
+__device__ __forceinline__ void update_point(const Coef& a, const Coef& b, double g, const double (&v)[NV > 0 ? NV : 1],
+                                             double xo, double yv, T& zt, T& xt) {
+  double zv = yv - g * xo;
+  double xn = xo;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    zv -= b.c[i] * v[i];
+    xn -= a.c[i] * v[i];
+  }
+  zt = (T)zv;
+  xt = (T)xn;
+}
+
+template <class T, int NV>
 __global__ void __launch_bounds__(kRedThreads) k_gs_update(const T* __restrict__ V, long ld, const Coef a,
                                                            const Coef b, double g, T* __restrict__ x,
                                                            const T* __restrict__ y, T* __restrict__ z,
                                                            double* part, long n) {
+  constexpr int W = Vec16<T>::W;
+  using VT = typename Vec16<T>::type;
   double acc[1] = {0.0};
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-    T v[NV > 0 ? NV : 1];
+  const long gt = (long)blockIdx.x * blockDim.x + threadIdx.x, gs = (long)gridDim.x * blockDim.x;
+  const long nvec = n / W;
+  for (long e = gt; e < nvec; e += gs) {
+    VT vw[NV > 0 ? NV : 1];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = V[i * ld + e];
-    const double xo = (double)x[e];
-    double zv = (double)y[e] - g * xo;
-    double xn = xo;
+    for (int i = 0; i < NV; ++i) vw[i] = *(const VT*)(V + i * ld + e * W);
+    const VT xw = *(const VT*)(x + e * W);
+    const VT yw = *(const VT*)(y + e * W);
+    VT zw, xn;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      zv -= b.c[i] * (double)v[i];
-      xn -= a.c[i] * (double)v[i];
+    for (int k = 0; k < W; ++k) {
+      double v[NV > 0 ? NV : 1];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) v[i] = (double)vw[i][k];
+      T zt, xt;
+      update_point<T, NV>(a, b, g, v, (double)xw[k], (double)yw[k], zt, xt);
+      zw[k] = zt;
+      xn[k] = xt;
+      acc[0] += (double)zt * (double)zt;
     }
-    const T zt = (T)zv;
+    *(VT*)(z + e * W) = zw;
+    if (NV > 0) *(VT*)(x + e * W) = xn;
+  }
+  for (long e = nvec * W + gt; e < n; e += gs) {
+    double v[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = (double)V[i * ld + e];
+    T zt, xt;
+    update_point<T, NV>(a, b, g, v, (double)x[e], (double)y[e], zt, xt);
     z[e] = zt;
-    if (NV > 0) x[e] = (T)xn;
+    if (NV > 0) x[e] = xt;
     acc[0] += (double)zt * (double)zt;
   }
   block_store<1>(acc, part);
@@ -150,13 +212,28 @@ __global__ void __launch_bounds__(kRedThreads) k_gs_update(const T* __restrict__
 template <class T, int NV>
 __global__ void k_update(const T* __restrict__ V, long ld, const Coef c, const T* __restrict__ dinv,
                          double* __restrict__ x, long n) {
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-    T v[NV];
+  constexpr int W = Vec16<T>::W;
+  using VT = typename Vec16<T>::type;
+  const long gt = (long)blockIdx.x * blockDim.x + threadIdx.x, gs = (long)gridDim.x * blockDim.x;
+  const long nvec = n / W;
+  for (long e = gt; e < nvec; e += gs) {
+    VT vw[NV];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = V[i * ld + e];
+    for (int i = 0; i < NV; ++i) vw[i] = *(const VT*)(V + i * ld + e * W);
+    VT dw = vw[0];
+    if (dinv) dw = *(const VT*)(dinv + e * W);
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) s += c.c[i] * (double)vw[i][k];
+      x[e * W + k] += dinv ? (double)dw[k] * s : s;
+    }
+  }
+  for (long e = nvec * W + gt; e < n; e += gs) {
     double s = 0.0;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) s += c.c[i] * (double)v[i];
+    for (int i = 0; i < NV; ++i) s += c.c[i] * (double)V[i * ld + e];
     x[e] += dinv ? (double)dinv[e] * s : s;
   }
 }
