@@ -206,6 +206,23 @@ dg_status dg_implicit_term(dg_ctx* ctx, const double* U_dev, double* F_dev);
 dg_status dg_apply_helmholtz(dg_ctx* ctx, double dt_a, const void* h_dev, const void* p_dev,
                              void* Ap_dev, int32_t prec);
 
+/* z = P^{-1} v: the cell-wise fast-diagonalisation preconditioner of the Helmholtz operator that
+ * right-preconditions the GMRES solves (DG_PREC_CELL_FDM; an extension: the paper names stronger
+ * preconditioning as future work, Section 3.2), with its per-cell coefficients formed from h as in
+ * the step:
+ *   P^{-1} = (1/Jbar) (S x S [x S]) diag(1 / (1/(gamma-1) + sum_k alpha_k mu_{i_k})) (S x S [x S])^T,
+ *   alpha_k = dt_a^2 hbar (2/D_k)^2,
+ * per cell, with hbar and Jbar the means of h and of the map's Jacobian over the cell's nodes,
+ * D_k the cell size (the vertical one times the mean terrain stretching Jbar / prod(D_k / 2)),
+ * and (mu, S) the generalised eigenpairs L s = mu W s, S^T W S = I, of the middle-cell block L of
+ * the 1D central-flux operator B^T W^{-1} B on a periodic row of three reference cells (W the
+ * Gauss weights).  The node order is that of U (x fastest).  h is double (N values) for both
+ * precisions; v and z are float with prec = DG_FP32_INNER (context set up with that precision,
+ * else DG_EINVAL), double otherwise.  Overwrites the context's per-cell coefficients (the step
+ * recomputes them); not reentrant per context. */
+dg_status dg_apply_preconditioner(dg_ctx* ctx, double dt_a, const double* h_dev, const void* v_dev,
+                                  void* z_dev, int32_t prec);
+
 /* One IMEX-RK2 step of size dt, in place.  On any error U is left unchanged.  stats may be NULL. */
 dg_status imex_rk2_step(dg_ctx* ctx, double* U_dev, double dt, dg_step_stats* stats);
 

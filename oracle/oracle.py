@@ -371,6 +371,85 @@ class Oracle:
         s = np.repeat(s, self.nloc)
         return self.wJ * (1.0 / (GAMMA - 1.0) + dta * dta * h * s)
 
+    # -------------------------------------------- cell-wise fast-diagonalisation preconditioner
+    # Not from the paper (which names stronger preconditioning as future work, Section 3.2): the
+    # right preconditioner of the GPU path's Krylov solves, written here from its definition.
+    @staticmethod
+    def fdm_line_operator(r: int, nc: int = 3):
+        """The 1D second-order operator G = B^T W^{-1} B on a periodic row of nc reference cells
+        [-1, 1] (cell K covers [2K - 1, 2K + 1]), with B the weak gradient of a nodal degree-r field
+        on the Gauss points with the central flux {p} at the two cell ends:
+            (B p)_i = -sum_j w_j p_j l_i'(x_j) + l_i(1) {p}(1) - l_i(-1) {p}(-1),
+        and W the Gauss weights.  Returns (L, G, W), L the block of G on cell 1 (the preconditioner
+        uses nc = 3: the middle cell)."""
+        n1 = r + 1
+        x, w = gauss(n1)
+        lm = lagrange_eval(x, -1.0)[0]
+        lp = lagrange_eval(x, 1.0)[0]
+        dl = np.array([lagrange_eval(x, xj)[1] for xj in x])  # dl[j, i] = l_i'(x_j)
+        B = np.zeros((nc * n1, nc * n1))
+        for K in range(nc):
+            own = slice(K * n1, (K + 1) * n1)
+            right = slice(((K + 1) % nc) * n1, ((K + 1) % nc + 1) * n1)
+            left = slice(((K - 1) % nc) * n1, ((K - 1) % nc + 1) * n1)
+            B[own, own] += -(dl * w[:, None]).T  # -sum_j w_j l_i'(x_j) p_j
+            B[own, own] += 0.5 * np.outer(lp, lp) - 0.5 * np.outer(lm, lm)
+            B[own, right] += 0.5 * np.outer(lp, lm)
+            B[own, left] -= 0.5 * np.outer(lm, lp)
+        W = np.tile(w, nc)
+        G = B.T @ (B / W[:, None])
+        return G[n1:2 * n1, n1:2 * n1], G, W
+
+    @classmethod
+    def fdm_eigen(cls, r: int):
+        """Generalised eigenpairs L s = mu W s of the middle-cell block, S^T W S = I."""
+        from scipy.linalg import eigh
+        L, _, W = cls.fdm_line_operator(r)
+        mu, S = eigh(L, np.diag(W[:r + 1]))
+        return mu, S
+
+    def node_weights(self) -> np.ndarray:
+        """Tensor Gauss weight of every node of a cell (x fastest, the vertical axis slowest)."""
+        _, w = gauss(self.r + 1)
+        wn = w
+        for _ in range(self.d - 1):
+            wn = np.kron(w, wn)
+        return wn
+
+    def fdm_coefficients(self, dta: float, h: np.ndarray):
+        """Per cell: Jbar = mean over the nodes of the map's Jacobian wJ / w, hbar = mean of h,
+        alpha_k = dta^2 hbar (2 / D_k)^2 with D_k the cell size and the vertical one multiplied by
+        the mean terrain stretching Jbar / prod(D_k / 2).  Returns (Jbar, alpha[ncell, d])."""
+        J = (self.wJ.reshape(self.ncell, self.nloc) / self.node_weights()[None, :])
+        Jbar = J.mean(axis=1)
+        hbar = np.asarray(h, dtype=np.float64).reshape(self.ncell, self.nloc).mean(axis=1)
+        D = self.cell_sizes[:, :self.d].copy()
+        stretch = Jbar / np.prod(0.5 * D, axis=1)
+        D[:, self.d - 1] *= stretch
+        alpha = dta * dta * hbar[:, None] * (2.0 / D) ** 2
+        return Jbar, alpha
+
+    def fdm_apply(self, dta: float, h: np.ndarray, v: np.ndarray) -> np.ndarray:
+        """z = (1/Jbar) (S x .. x S) diag(1 / (1/(gamma-1) + sum_k alpha_k mu_{i_k})) (S x .. x S)^T v
+        in every cell (i_k the index along axis k; the transforms act along each axis of the cell's
+        node array)."""
+        n1, d = self.r + 1, self.d
+        mu, S = self.fdm_eigen(self.r)
+        Jbar, alpha = self.fdm_coefficients(dta, h)
+        V = np.asarray(v, dtype=np.float64).reshape((self.ncell,) + (n1,) * d)  # [cell][(z,) y/z .. x]
+        if d == 3:
+            Vh = np.einsum("za,yb,xc,nzyx->nabc", S, S, S, V)
+            den = (1.0 / (GAMMA - 1.0) + alpha[:, 2, None, None, None] * mu[None, :, None, None]
+                   + alpha[:, 1, None, None, None] * mu[None, None, :, None]
+                   + alpha[:, 0, None, None, None] * mu[None, None, None, :])
+            Z = np.einsum("za,yb,xc,nabc->nzyx", S, S, S, Vh / den)
+        else:
+            Vh = np.einsum("za,xc,nzx->nac", S, S, V)
+            den = (1.0 / (GAMMA - 1.0) + alpha[:, 1, None, None] * mu[None, :, None]
+                   + alpha[:, 0, None, None] * mu[None, None, :])
+            Z = np.einsum("za,xc,nac->nzx", S, S, Vh / den)
+        return (Z / Jbar.reshape((-1,) + (1,) * d)).reshape(-1)
+
     # ------------------------------------------------------------------------------------ GMRES
     @staticmethod
     def gmres(apply, b: np.ndarray, dinv: np.ndarray, rtol: float, atol: float, restart: int,

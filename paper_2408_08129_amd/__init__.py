@@ -27,7 +27,8 @@ MAX_RULES = 8
 
 EXPORTED = ("dg_default_options", "dg_setup", "dg_footprint", "dg_mesh_info", "dg_set_stream", "dg_set_timing",
             "dg_sizes", "dg_cell_table", "dg_node_geometry", "dg_init_state",
-            "dg_explicit_residual", "dg_implicit_term", "dg_apply_helmholtz", "imex_rk2_step",
+            "dg_explicit_residual", "dg_implicit_term", "dg_apply_helmholtz", "dg_apply_preconditioner",
+            "imex_rk2_step",
             "imex_rk2_step_batched", "dg_diagnostics", "dg_last_error", "dg_destroy")
 
 
@@ -134,6 +135,7 @@ def lib():
         L.dg_explicit_residual.argtypes = [vp, vp, vp]
         L.dg_implicit_term.argtypes = [vp, vp, vp]
         L.dg_apply_helmholtz.argtypes = [vp, d, vp, vp, vp, i32]
+        L.dg_apply_preconditioner.argtypes = [vp, d, vp, vp, vp, i32]
         L.imex_rk2_step.argtypes = [vp, vp, d, ctypes.POINTER(dg_step_stats)]
         L.imex_rk2_step_batched.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp),
                                             ctypes.POINTER(d), i32, ctypes.POINTER(dg_step_stats),
@@ -259,6 +261,10 @@ def dg_apply_helmholtz(ctx: int, dt_a: float, h, p, Ap, prec: int = DG_FP64):
     _check(lib().dg_apply_helmholtz(ctypes.c_void_p(ctx), float(dt_a), _ptr(h), _ptr(p), _ptr(Ap), prec))
 
 
+def dg_apply_preconditioner(ctx: int, dt_a: float, h, v, z, prec: int = DG_FP64):
+    _check(lib().dg_apply_preconditioner(ctypes.c_void_p(ctx), float(dt_a), _ptr(h), _ptr(v), _ptr(z), prec))
+
+
 def imex_rk2_step(ctx: int, U, dt: float) -> dg_step_stats:
     st = dg_step_stats()
     _check(lib().imex_rk2_step(ctypes.c_void_p(ctx), _ptr(U), float(dt), ctypes.byref(st)))
@@ -359,6 +365,11 @@ class Solver:
         Ap = self.torch.empty_like(p)
         dg_apply_helmholtz(self.ctx, dt_a, h, p, Ap, prec)
         return Ap
+
+    def apply_preconditioner(self, dt_a, h, v, prec=DG_FP64):
+        z = self.torch.empty_like(v)
+        dg_apply_preconditioner(self.ctx, dt_a, h, v, z, prec)
+        return z
 
     def step(self, U, dt) -> dg_step_stats:
         return imex_rk2_step(self.ctx, U, dt)

@@ -1794,6 +1794,28 @@ dg_status dg_apply_helmholtz(dg_ctx* c, double dta, const void* h, const void* p
   return fail(c, DG_EINVAL, "bad precision");
 }
 
+dg_status dg_apply_preconditioner(dg_ctx* c, double dta, const double* h, const void* v, void* z, int32_t prec) {
+  if (!c || !h || !v || !z) return fail(nullptr, DG_EINVAL, "null argument");
+  const bool mixed = prec == DG_FP32_INNER;
+  if (prec != DG_FP64 && !mixed) return fail(c, DG_EINVAL, "bad precision");
+  if (mixed && c->opt.precision != DG_FP32_INNER)
+    return fail(c, DG_EINVAL, "context was set up without the FP32 workspace (precision option)");
+  // per-cell coefficients from h, as in the step (FP64, with an FP32 copy for the mixed form)
+  if (launch_cellcoef(c->md, c->degree, h, c->wJ, dta, c->lam, mixed ? c->lam32 : nullptr, c->coef,
+                      mixed ? c->coef32 : nullptr, c->stream))
+    return fail(c, DG_EDEVICE, "launch failed");
+  int rf;
+  if (mixed) {
+    FdmArgs<float> f{(const float*)v, 1.0f, c->coef32, (float*)z};
+    rf = launch_fdm32(c->md, c->degree, f, c->stream);
+  } else {
+    FdmArgs<double> f{(const double*)v, 1.0, c->coef, (double*)z};
+    rf = launch_fdm64(c->md, c->degree, f, c->stream);
+  }
+  if (rf) return fail(c, DG_EDEVICE, "launch failed");
+  return DG_OK;
+}
+
 dg_status imex_rk2_step(dg_ctx* c, double* U, double dt, dg_step_stats* stats) {
   if (!c || !U) return fail(nullptr, DG_EINVAL, "null argument");
   if (!(dt > 0.0)) return fail(c, DG_EINVAL, "dt must be positive");
