@@ -216,10 +216,12 @@ dg_status dg_apply_helmholtz(dg_ctx* ctx, double dt_a, const void* h_dev, const 
  * D_k the cell size (the vertical one times the mean terrain stretching Jbar / prod(D_k / 2)),
  * and (mu, S) the generalised eigenpairs L s = mu W s, S^T W S = I, of the middle-cell block L of
  * the 1D central-flux operator B^T W^{-1} B on a periodic row of three reference cells (W the
- * Gauss weights).  The node order is that of U (x fastest).  h is double (N values) for both
- * precisions; v and z are float with prec = DG_FP32_INNER (context set up with that precision,
- * else DG_EINVAL), double otherwise.  Overwrites the context's per-cell coefficients (the step
- * recomputes them); not reentrant per context. */
+ * Gauss weights).  The node order is that of U (x fastest).  h_dev, v_dev, z_dev: caller-owned
+ * device arrays of N values; h is double for both precisions, v and z are float with
+ * prec = DG_FP32_INNER (context set up with that precision, else DG_EINVAL), double otherwise.
+ * Null pointers or an unknown prec give DG_EINVAL.  Overwrites the context's per-cell
+ * coefficients and sound speeds (the step and dg_apply_helmholtz recompute them); not reentrant
+ * per context. */
 dg_status dg_apply_preconditioner(dg_ctx* ctx, double dt_a, const double* h_dev, const void* v_dev,
                                   void* z_dev, int32_t prec);
 
