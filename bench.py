@@ -39,10 +39,10 @@ def run_gpu(w, precision, steps, warmup, timing=True):
     import torch
 
     import paper_2408_08129_amd as P
-    from tests import _common as C
+    from paper_2408_08129_amd import cases
 
     opt = P.options(precision=precision, gmres_rtol=w.get("rtol", 1e-8), quad_extra=w.get("quad_extra", 0))
-    s = P.Solver(C.product_case(w), w["degree"], opt)
+    s = P.Solver(cases.product_case(w), w["degree"], opt)
     U = s.init_state(w["ubar"])
     for i in range(warmup):
         s.step(U, w["dt"])

@@ -39,15 +39,6 @@ from . import cases
 PAPER_WALL_S = {"uniform": 36500.0, "nonconforming": 2560.0}
 
 
-def case_of(w: dict):
-    """Workload dict -> Case of the binding."""
-    from . import Case
-    return Case(dim=w["dim"], nbase=tuple(w["nbase"]), length=tuple(w["length"]),
-                periodic=tuple(w["periodic"]), rules=list(w["rules"]), orography=w["orography"],
-                oro=tuple(w["oro"]), atmosphere=w["atmosphere"], atm=tuple(w["atm"]),
-                sponge=tuple(w.get("sponge", (0.0,) * 5)))
-
-
 def terrain_height(w: dict, x, y):
     """Orography height at horizontal positions (the five profiles of the case description)."""
     kind = w["orography"]
@@ -199,7 +190,7 @@ def run_case(w: dict, steps: int, precision: int, label: str) -> dict:
 
     opt = P.options(precision=precision, gmres_rtol=w.get("rtol", 1e-8),
                     enthalpy_split=w.get("enthalpy_split", 0), penalty_beta=w.get("penalty_beta", 1.0))
-    s = P.Solver(case_of(w), w["degree"], opt)
+    s = P.Solver(cases.product_case(w), w["degree"], opt)
     U = s.init_state(w["ubar"])
     mass0, _ = s.diagnostics(U)
     torch.cuda.synchronize()

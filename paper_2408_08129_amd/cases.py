@@ -67,6 +67,15 @@ WORKLOADS = {
 }
 
 
+def product_case(w: dict):
+    """Workload dict -> the binding's Case (the problem description passed to dg_setup)."""
+    from . import Case
+    return Case(dim=w["dim"], nbase=tuple(w["nbase"]), length=tuple(w["length"]),
+                periodic=tuple(w.get("periodic", (1, 1))), rules=list(w.get("rules", [])),
+                orography=w["orography"], oro=tuple(w["oro"]), atmosphere=w["atmosphere"],
+                atm=tuple(w["atm"]), sponge=tuple(w.get("sponge", (0.0,) * 5)))
+
+
 def column_sample(w: dict, nx: int, ny: int) -> dict:
     """The same workload restricted to nx (x ny) base columns around the orography: full height,
     same cell sizes and refinement rules, the hill centred in the sample."""

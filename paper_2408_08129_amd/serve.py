@@ -134,11 +134,7 @@ class Server:
         self.used = 0
 
     def _case(self, w):
-        P = self.P
-        return P.Case(dim=w["dim"], nbase=tuple(w["nbase"]), length=tuple(w["length"]),
-                      periodic=tuple(w["periodic"]), rules=list(w["rules"]),
-                      orography=w["orography"], oro=tuple(w["oro"]), atmosphere=w["atmosphere"],
-                      atm=tuple(w["atm"]))
+        return cases.product_case(w)
 
     def member_bytes(self, req: Request) -> int:
         w = req.work
