@@ -58,6 +58,8 @@ typedef struct {
   double rules[OC_MAXRULES][5];  /* zeta_max, x_c, half-width x (<=0: any), y_c, half-width y */
   double oro[4];                 /* height, width (a or sigma), x_c, y_c */
   double atm[3];                 /* isothermal: p0, T0; stratified: p_ref, T_ref, N */
+  double grav;                   /* gravitational acceleration g of Eq. (1) (9.81; 0 switches the
+                                    gravity terms off, isothermal atmosphere only) */
 } oc_case;
 
 typedef struct {
@@ -189,20 +191,24 @@ static void terrain(const oc_case* c, double x, double y, double* h, double* hx,
 
 /* Hydrostatic background (Section 3.1, Eq. (4)-(5) with the g^2 / N^2 factor that makes
  * dp/dz = -rho g hold; or an isothermal atmosphere). */
-void oc_background(int kind, const double* atm, double z, double* p, double* rho) {
+static void background_g(int kind, const double* atm, double g, double z, double* p, double* rho) {
   if (kind == OC_ISOTHERMAL) {
     double p0 = atm[0], T0 = atm[1];
-    *p = p0 * exp(-OC_G * z / (OC_R * T0));
+    *p = p0 * exp(-g * z / (OC_R * T0));
     *rho = *p / (OC_R * T0);
   } else {
     double pref = atm[0], Tref = atm[1], N = atm[2];
     double G = (OC_GAMMA - 1.0) / OC_GAMMA;
     double rhoref = pref / (OC_R * Tref);
-    double s = exp(-N * N * z / OC_G);
-    double base = 1.0 - (OC_G * OC_G / (N * N)) * G * (rhoref / pref) * (1.0 - s);
+    double s = exp(-N * N * z / g);
+    double base = 1.0 - (g * g / (N * N)) * G * (rhoref / pref) * (1.0 - s);
     *p = pref * pow(base, 1.0 / G);
     *rho = rhoref * pow(*p / pref, 1.0 / OC_GAMMA) * s;
   }
+}
+
+void oc_background(int kind, const double* atm, double z, double* p, double* rho) {
+  background_g(kind, atm, OC_G, z, p, rho);
 }
 
 /* Metric of the map (cell affine map at level lev composed with the terrain-following map) at
@@ -267,6 +273,7 @@ int oc_mesh_build(const oc_case* cs, oc_mesh** out) {
   if (cs->dim != 2 && cs->dim != 3) return -1;
   if (cs->degree < 1 || cs->degree > OC_MAXNP - 1) return -1;
   if (cs->n_rules < 0 || cs->n_rules > OC_MAXRULES) return -1;
+  if (!(cs->grav > 0.0) && !(cs->grav == 0.0 && cs->atm_kind == OC_ISOTHERMAL)) return -1;
   oc_mesh* m = (oc_mesh*)calloc(1, sizeof(oc_mesh));
   m->cs = *cs;
   int d = m->d = cs->dim;
@@ -624,7 +631,7 @@ void oc_background_nodes(const oc_mesh* m, double* pbar, double* rbar) {
       node_X(m, c, q, X);
       metric(m, m->lev[c], X, Gam, &J, &zp);
       long n = (long)c * m->nloc + q;
-      oc_background(m->cs.atm_kind, m->cs.atm, zp, &pbar[n], &rbar[n]);
+      background_g(m->cs.atm_kind, m->cs.atm, m->cs.grav, zp, &pbar[n], &rbar[n]);
     }
 }
 
@@ -741,6 +748,10 @@ static void wall_flux(int d, const double* U, const double* N, double* out) {
   out[1 + d] = 0.0;
 }
 
+/* The slip-wall flux at one point, exported for the oracle's own tests (closed-form check against
+ * the Rusanov flux with the mirror state). */
+void oc_wall_flux(int d, const double* U, const double* N, double* out) { wall_flux(d, U, N, out); }
+
 /* R = M^{-1} (explicit weak form): the explicit time derivative of U, layout [field][cell][node].
  * Volume: + int F . grad(phi_i); faces: - int (F^.n) phi_i; gravity work -g (rho w) on energy. */
 void oc_explicit_residual(const oc_mesh* m, const double* U, double* R) {
@@ -811,7 +822,7 @@ void oc_explicit_residual(const oc_mesh* m, const double* U, double* R) {
       metric(m, m->lev[c], X, Gam, &J, &zp);
       double mJ = m->wq[q] * J;
       for (int f = 0; f < NF; ++f) R[f * N + (long)c * nloc + q] = W[f][q] / mJ;
-      R[(1 + d) * N + (long)c * nloc + q] -= OC_G * U[d * N + (long)c * nloc + q];
+      R[(1 + d) * N + (long)c * nloc + q] -= m->cs.grav * U[d * N + (long)c * nloc + q];
     }
   }
 }
@@ -931,7 +942,7 @@ int oc_explicit_residual_oi(const oc_mesh* m, const double* U, double* R) {
       metric(m, l, X, Gam, &J, &zp);
       double mJ = m->wq[q] * J;
       for (int f = 0; f < NF; ++f) R[f * N + (long)c * nloc + q] = W[f][q] / mJ;
-      R[(1 + d) * N + (long)c * nloc + q] -= OC_G * U[d * N + (long)c * nloc + q];
+      R[(1 + d) * N + (long)c * nloc + q] -= m->cs.grav * U[d * N + (long)c * nloc + q];
     }
   }
   return 0;

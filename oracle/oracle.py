@@ -78,7 +78,7 @@ class _Case(ctypes.Structure):
         ("n_rules", ctypes.c_int32), ("oro_kind", ctypes.c_int32), ("atm_kind", ctypes.c_int32),
         ("pad_", ctypes.c_int32),
         ("length", ctypes.c_double * 3), ("rules", (ctypes.c_double * 5) * 8),
-        ("oro", ctypes.c_double * 4), ("atm", ctypes.c_double * 3),
+        ("oro", ctypes.c_double * 4), ("atm", ctypes.c_double * 3), ("grav", ctypes.c_double),
     ]
 
 
@@ -111,6 +111,7 @@ def lib():
         L.oc_cell_sizes.argtypes = [P, dp]
         L.oc_bottom_normals.argtypes = [P, dp]
         L.oc_bottom_normals.restype = ctypes.c_int
+        L.oc_wall_flux.argtypes = [ctypes.c_int, dp, dp, dp]
         L.oc_gauss.argtypes = [ctypes.c_int, dp, dp]
         L.oc_lagrange_eval.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp, dp]
         L.oc_background.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp, dp]
@@ -128,6 +129,15 @@ def gauss(n: int):
     w = np.zeros(n)
     lib().oc_gauss(n, _p(x), _p(w))
     return x, w
+
+
+def wall_flux(d: int, U: np.ndarray, N: np.ndarray) -> np.ndarray:
+    """The oracle's slip-wall flux at one point: conserved state U (d + 2 values) and outward
+    area-weighted normal N (d values)."""
+    out = np.zeros(d + 2)
+    lib().oc_wall_flux(d, _p(np.ascontiguousarray(U, dtype=np.float64)),
+                       _p(np.ascontiguousarray(N, dtype=np.float64)), _p(out))
+    return out
 
 
 def lagrange_eval(nodes: np.ndarray, x: float):
@@ -161,6 +171,9 @@ class Case:
     atm: tuple = (1.0e5, 250.0, 0.0)
     # absorbing layers: (top depth, top rate, lateral width, lateral rate, reference wind u_ref)
     sponge: tuple = (0.0, 0.0, 0.0, 0.0, 0.0)
+    # gravitational acceleration of Eq. (1); 0 (isothermal atmosphere only) switches the gravity
+    # terms off, for the exact isentropic-vortex solution of the Euler equations
+    gravity: float = G
 
     def to_struct(self) -> _Case:
         c = _Case()
@@ -182,6 +195,7 @@ class Case:
         atm = list(self.atm) + [0.0] * (3 - len(self.atm))
         for i in range(3):
             c.atm[i] = float(atm[i])
+        c.grav = float(self.gravity)
         return c
 
 
@@ -216,6 +230,7 @@ class Oracle:
         self.nloc = L.oc_nloc(h)
         self.nhang = L.oc_nhang(h)
         self.lmax = L.oc_lmax(h)
+        self.g = float(case.gravity)
         self.N = self.ncell * self.nloc
         cells = np.zeros((self.ncell, 4), dtype=np.int32)
         L.oc_cell_table(h, cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
@@ -297,7 +312,7 @@ class Oracle:
         if self.case.atm_kind == STRATIFIED:
             Nb = float(self.case.atm[2])
             T = self.pbar / (RGAS * self.rbar)
-            dhbar = -G + GAMMA * RGAS / (GAMMA - 1.0) * T * Nb * Nb / G
+            dhbar = -self.g + GAMMA * RGAS / (GAMMA - 1.0) * T * Nb * Nb / self.g
         else:
             dhbar = np.zeros(self.N)
         return hbar, dhbar
@@ -539,7 +554,7 @@ class Oracle:
         F = np.zeros_like(U)
         q = self.grad(pp)
         F[1:1 + d] = -q
-        F[d] -= (rho - self.rbar) * G
+        F[d] -= (rho - self.rbar) * self.g
         e = self.enthalpy_flux_div(h, U[1:1 + d])
         if self.beta != 0.0:
             e = e + self.beta / (2.0 * (GAMMA - 1.0)) * self.penalty(lam, pp)
@@ -565,7 +580,7 @@ class Oracle:
             et = U[1 + d] + dt * sum(A[i, j] * FE[j][1 + d] + At[i, j] * FI[j][1 + d]
                                      for j in range(i))
             mprime = mt.copy()
-            mprime[d - 1] -= dta * (rho_i - self.rbar) * G
+            mprime[d - 1] -= dta * (rho_i - self.rbar) * self.g
             pp = pp_prev.copy()
             m = m_prev.copy()
             for _ in range(fp_iters):
