@@ -14,7 +14,7 @@
  *
  * Conventions shared by every call.
  *   - Status: every function returns dg_status (DG_OK = 0, errors negative); no exception crosses
- *     the ABI.  dg_last_error() returns a message for the calling thread's last error.
+ *     the ABI.  dg_last_error(ctx) returns a message for the last error.
  *   - Memory: pointers named *_dev are device pointers (HIP device memory, e.g. torch tensors on a
  *     ROCm device), borrowed for the duration of the call.  All device work is ordered on the HIP
  *     stream given to dg_setup (or dg_set_stream); a call returns when its work is queued, except
@@ -129,18 +129,29 @@ typedef struct {
   int32_t enthalpy_split;
 } dg_options;
 
-/* Per-step statistics ([implicit stage][fixed-point iteration]). */
+/* Per-step statistics ([implicit stage][fixed-point iteration]) of the pressure fixed-point loop
+ * and its GMRES solves (Section 3.2). */
 typedef struct {
   int32_t gmres_iters[2][8];    /* Krylov iterations (FP32 inner iterations in mixed mode) */
   int32_t outer_iters[2][8];    /* defect-correction sweeps (mixed mode), 0 for FP64 */
   double gmres_relres[2][8];    /* final ||r|| / ||r0|| */
+  double fp_incr[2][8];         /* fixed-point increment ||delta||_2 / ||p'||_2 after the iteration */
+  double t_phase_ms[8];         /* with dg_set_timing on: device time per phase of the step, from HIP
+                                   events at the phase boundaries on the context's stream:
+                                   0 explicit residuals, 1 implicit term at U^n, 2 stage predictors,
+                                   stage ends and final combination, 3 fixed-point coefficients,
+                                   4 Helmholtz right-hand side and initial residual, 5 Krylov
+                                   solves, 6 back-substitution, 7 non-finite check, copy-out and
+                                   diagnostics */
   double t_kernel_ms[8];        /* with dg_set_timing on: device time summed per kernel class,
                                    from HIP events around every launch on the context's stream:
-                                   0 explicit residual, 1 weak gradient M^-1 B (Helmholtz pass 1),
-                                   2 weak divergence with penalty (Helmholtz pass 2, right-hand
-                                   side, implicit term), 3 Gram-Schmidt reduction pass (k_gs_dots),
-                                   4 pointwise vector work, 5 Gram-Schmidt update pass (k_gs_update),
-                                   6 Krylov solution update and final reductions */
+                                   0 explicit residual, 1 Helmholtz apply pass 1 (h M^-1 B p),
+                                   2 Helmholtz apply pass 2 (divergence, penalty, mass),
+                                   3 Gram-Schmidt reduction pass (k_gs_dots), 4 pointwise vector
+                                   work and preconditioner, 5 Gram-Schmidt update pass
+                                   (k_gs_update), 6 Krylov solution update and final reductions,
+                                   7 the other operator passes (right-hand side divergence,
+                                   implicit term, back-substitution gradient) */
   int32_t n_kernel[8];          /* launches per class (timing on) */
   double bytes_kernel[8];       /* algorithmic HBM bytes per class (timing on): the arrays each
                                    launch must read and write once, as the kernels are designed */
@@ -156,13 +167,21 @@ typedef struct dg_ctx dg_ctx;
  * the orthogonalisation traffic.) */
 void dg_default_options(dg_options* opt);
 
-/* Builds the mesh (refinement by rules, 2:1 balance check, Morton order), uploads it, and
- * allocates the workspace.  degree in [1, 5]; stream: a hipStream_t (NULL = default stream).
- * Errors: DG_EINVAL (bad description, 2:1 violation), DG_EUNSUPPORTED, DG_ENOMEM, DG_EDEVICE. */
+/* Sets up the discretisation of Section 2 on the mesh of Section 3.1 / Fig. 1: builds the mesh
+ * (base grid refined by the rules, 2:1 balance check, Morton order of the leaves), uploads its
+ * tables and allocates the whole workspace (dg_footprint bytes) on the current device.
+ * degree r in [1, 5]: the paper runs r = 4 (and r = 2 in its scaling study, Section 3.2); r = 6
+ * would need 343-node cells, beyond the 256-thread workgroups and the static LDS budget of the
+ * cell kernels, so it is rejected with DG_EUNSUPPORTED.  desc and opt (NULL: defaults) are copied;
+ * stream: a hipStream_t (NULL = default stream); *out receives the new context, owned by the
+ * caller until dg_destroy.  Errors: DG_EINVAL (null pointers, bad description, 2:1 violation),
+ * DG_EUNSUPPORTED, DG_ENOMEM (device memory), DG_EDEVICE; *out is left NULL on error. */
 dg_status dg_setup(const dg_case_desc* desc, int32_t degree, const dg_options* opt, void* stream,
                    dg_ctx** out);
 
-/* Exact device bytes dg_setup would allocate for this description, without allocating. */
+/* Exact device bytes dg_setup would allocate for this description (mesh tables, geometry and the
+ * step and Krylov workspace of Section 3.2's solver), without allocating or touching the device;
+ * used to admit ensemble members by HBM footprint.  Errors as dg_setup. */
 dg_status dg_footprint(const dg_case_desc* desc, int32_t degree, const dg_options* opt,
                        size_t* bytes);
 
@@ -172,37 +191,75 @@ dg_status dg_footprint(const dg_case_desc* desc, int32_t degree, const dg_option
 dg_status dg_mesh_info(const dg_case_desc* desc, int32_t degree, int64_t* n_cells,
                        int64_t* n_hanging, int32_t* cells_out);
 
+/* Replaces the HIP stream on which the context orders its work (the caller keeps ownership of the
+ * stream and synchronises any switch).  DG_EINVAL for a null ctx. */
 dg_status dg_set_stream(dg_ctx* ctx, void* stream);
+
+/* enable != 0: every later step records HIP events around its launches and phases (the per-class
+ * and per-phase device times of dg_step_stats); allocates the event pool on first use.
+ * DG_EINVAL for a null ctx, DG_EDEVICE if an event cannot be created. */
 dg_status dg_set_timing(dg_ctx* ctx, int32_t enable);
 
-/* Cells, nodes per scalar field, fields (d + 2). */
+/* Cells, nodes per scalar field N = cells (r + 1)^d (the per-scalar unknown count of Section 3.2)
+ * and fields d + 2 (Eq. (1): rho, the d momentum components, rho E); any output may be NULL. */
 dg_status dg_sizes(const dg_ctx* ctx, int64_t* n_cells, int64_t* nodes_per_field,
                    int32_t* n_fields);
 
-/* Host output, 4 int32 per cell: (level, i_x, i_y, i_z) at the cell's own level (i_y = 0 in 2D);
- * the cell's logical box is [i L / (n 2^level), (i + 1) L / (n 2^level)) per axis. */
+/* The cells of the non-conforming mesh (Section 3.1, Fig. 1) in the order of the state arrays.
+ * host_out: caller-owned, 4 int32 per cell: (level, i_x, i_y, i_z) at the cell's own level
+ * (i_y = 0 in 2D); the cell's logical box is [i L / (n 2^level), (i + 1) L / (n 2^level)) per
+ * axis.  DG_EINVAL for null pointers. */
 dg_status dg_cell_table(const dg_ctx* ctx, int32_t* host_out);
 
-/* Device outputs (any may be NULL), [cell][node]: physical x, y, z of every node and the
- * quadrature weight times the Jacobian determinant (the diagonal mass matrix). */
+/* Geometry of the terrain-following map over the orography of Section 3.1 at every node.
+ * Device outputs (caller-owned, N doubles each, any may be NULL), [cell][node]: physical x, y, z
+ * and the quadrature weight times the Jacobian determinant (the diagonal mass matrix).
+ * Errors: DG_EINVAL for a null ctx, DG_EDEVICE. */
 dg_status dg_node_geometry(dg_ctx* ctx, double* x_dev, double* y_dev, double* z_dev,
                            double* wJ_dev);
 
-/* Initial state (Section 3.1): hydrostatic background with uniform wind (ubar, 0, 0); with
- * dT_dev != NULL a temperature perturbation per node is added at constant pressure. */
-dg_status dg_init_state(dg_ctx* ctx, double ubar, const double* dT_dev, double* U_dev);
+/* Initial-condition kinds of dg_init_state. */
+enum { DG_IC_HYDROSTATIC_WIND = 0 };
 
-/* R = M^{-1} (explicit weak form): the explicit time derivative (advective fluxes with a
- * Rusanov flux on the advective speed, slip walls, gravity work on the energy), shape of U. */
+/* Initial state (Section 3.1, Eq. (4)-(5)) written to U_dev (caller-owned, F x N doubles, layout
+ * of U).  DG_IC_HYDROSTATIC_WIND: the hydrostatic background of the context's atmosphere with the
+ * uniform wind (ic_params[0], 0, 0) m/s.  With noise_sigma_K > 0 every node's temperature is
+ * perturbed by sigma * n at constant pressure (rho = pbar / (R (Tbar + sigma n))), where n is a
+ * standard normal deviate drawn in the library from SplitMix64 (Steele, Lea, Flood 2014) used as a
+ * counter-based generator keyed by the node's identity, so the field does not depend on the
+ * cell order or on the launch:
+ *   mix(z) = z ^ (z >> 30), * 0xbf58476d1ce4e5b9; ^ (>> 27), * 0x94d049bb133111eb; ^ (>> 31)
+ *   (64-bit wrap-around arithmetic), G = 0x9e3779b97f4a7c15,
+ *   k = mix(seed + G (level + 1)); k = mix(k + G (i_x + 1)); k = mix(k + G (i_y + 1));
+ *   k = mix(k + G (i_z + 1)); k = mix(k + G (node + 1))   (cell table entries, node in the cell),
+ *   u1 = (mix(k + G) >> 11) 2^-53, u2 = (mix(k + 2 G) >> 11) 2^-53,
+ *   n = sqrt(-2 ln(1 - u1)) cos(2 pi u2)   (Box-Muller).
+ * Errors: DG_EINVAL for a null ctx / U_dev / ic_params, an unknown ic_kind or a negative or
+ * non-finite sigma; U_dev is not written then. */
+dg_status dg_init_state(dg_ctx* ctx, int32_t ic_kind, const double* ic_params, uint64_t noise_seed,
+                        double noise_sigma_K, double* U_dev);
+
+/* R = M^{-1} (explicit weak form): the explicit part of the IMEX split of Section 2 (continuity,
+ * the advective momentum flux and the kinetic-energy flux of Eq. (1), with a Rusanov flux on the
+ * advective speed, slip walls, 2:1 faces on the fine side, and the gravity work -rho g w on the
+ * energy), plus the absorbing-layer friction if the case has layers.  U_dev and R_dev:
+ * caller-owned device arrays of F x N doubles (layout of U), not aliased.  Errors: DG_EINVAL for
+ * null pointers, DG_EDEVICE for a failed launch. */
 dg_status dg_explicit_residual(dg_ctx* ctx, const double* U_dev, double* R_dev);
 
-/* F = M^{-1} (implicit weak form) at U: (0, -B p' - M (rho - rhobar) g k,
- * -C(h m) - beta/(2(gamma-1)) P p'), the implicit time derivative, shape of U. */
+/* F = M^{-1} (implicit weak form) at U, the implicit part of the IMEX split of Section 2
+ * (pressure gradient and buoyancy in the momentum, the enthalpy flux in the energy):
+ * (0, -B p' - M (rho - rhobar) g k, -C(h m) - beta/(2(gamma-1)) P p'), with p' = p - pbar.
+ * U_dev, F_dev: caller-owned device arrays of F x N doubles (the density row of F is not written).
+ * Uses the context's workspace; errors as dg_explicit_residual. */
 dg_status dg_implicit_term(dg_ctx* ctx, const double* U_dev, double* F_dev);
 
-/* Ap = A(h) p = M p/(gamma-1) + dt_a beta/(2(gamma-1)) P p - dt_a^2 C (h M^{-1} B p), in weak
- * (test-space) form; P uses per-cell sound speeds from h.  With prec = DG_FP32_INNER all three
- * arrays are float, else double.  Uses the context's workspace; not reentrant per context. */
+/* The operator of the pressure system of Section 3.2 (non-symmetric, applied matrix-free):
+ * Ap = A(h) p = M p/(gamma-1) + dt_a beta/(2(gamma-1)) P p - dt_a^2 C (h M^{-1} B p), in weak
+ * (test-space) form; P uses per-cell sound speeds from h.  h_dev, p_dev, Ap_dev: caller-owned
+ * device arrays of N values, float with prec = DG_FP32_INNER (context set up with that precision,
+ * else DG_EINVAL), double with DG_FP64.  Uses the context's workspace; not reentrant per context.
+ * Errors: DG_EINVAL (null pointers, bad prec), DG_EDEVICE. */
 dg_status dg_apply_helmholtz(dg_ctx* ctx, double dt_a, const void* h_dev, const void* p_dev,
                              void* Ap_dev, int32_t prec);
 
@@ -225,7 +282,14 @@ dg_status dg_apply_helmholtz(dg_ctx* ctx, double dt_a, const void* h_dev, const 
 dg_status dg_apply_preconditioner(dg_ctx* ctx, double dt_a, const double* h_dev, const void* v_dev,
                                   void* z_dev, int32_t prec);
 
-/* One IMEX-RK2 step of size dt, in place.  On any error U is left unchanged.  stats may be NULL. */
+/* One step of the second-order IMEX Runge-Kutta method of Section 2 (ARK2 of Giraldo, Kelly and
+ * Constantinescu 2013: explicit first stage, two implicit stages), each implicit stage running the
+ * pressure fixed-point loop with GMRES of Section 3.2, in place on U_dev (caller-owned F x N
+ * doubles).  stats (host, may be NULL) receives iteration counts, residuals, fixed-point
+ * increments, the diagnostics of the new state and, with timing on, device times.  Errors:
+ * DG_EINVAL (null pointers, dt <= 0), DG_ENOCONV (a solve missed its tolerance within maxit),
+ * DG_ENAN (a non-finite value in a solve or in the new state), DG_EDEVICE; on any error U is left
+ * unchanged. */
 dg_status imex_rk2_step(dg_ctx* ctx, double* U_dev, double dt, dg_step_stats* stats);
 
 /* One step for each of n contexts (ensemble members of any sizes): each member runs on its own
@@ -236,10 +300,19 @@ dg_status imex_rk2_step(dg_ctx* ctx, double* U_dev, double dt, dg_step_stats* st
 dg_status imex_rk2_step_batched(dg_ctx* const* ctxs, double* const* U_devs, const double* dts,
                                 int32_t n, dg_step_stats* stats, int32_t* status);
 
-/* Total mass sum(w J rho) and max |w| (host outputs). */
+/* Invariants of the step (mass is conserved to rounding by the explicit continuity equation,
+ * Section 2): total mass sum(w J rho) and max |w| = max |rho w| / rho over the nodes, as host
+ * outputs (either may be NULL); synchronises the context's stream.  Errors: DG_EINVAL for a null
+ * ctx or U_dev, DG_EDEVICE. */
 dg_status dg_diagnostics(dg_ctx* ctx, const double* U_dev, double* mass, double* max_w);
 
-const char* dg_last_error(void);
+/* Message of the last error: the context's own (set by any call on it, including the member steps
+ * of imex_rk2_step_batched, which run on other threads) if ctx is non-NULL and has one, else the
+ * calling thread's (setup and argument errors).  The string stays valid until the next call on
+ * that context or thread. */
+const char* dg_last_error(const dg_ctx* ctx);
+
+/* Releases the context's device memory, events and pinned host buffer (waits for its stream). */
 void dg_destroy(dg_ctx* ctx);
 
 #ifdef __cplusplus

@@ -529,6 +529,34 @@ class Oracle:
             if beta <= tol:
                 return x, its, beta, True
 
+    # ------------------------------------------------------------------------ initial-state noise
+    def temperature_noise(self, seed: int, sigma: float) -> np.ndarray:
+        """sigma times a standard normal deviate per node, from SplitMix64 (Steele, Lea, Flood 2014)
+        used as a counter-based generator keyed by the seed, the node's cell (level, i_x, i_y, i_z)
+        and its index in the cell, then Box-Muller:
+            mix(z) = z ^ (z >> 30), times 0xbf58476d1ce4e5b9, ^ (>> 27), times 0x94d049bb133111eb,
+                     ^ (>> 31), in 64-bit wrap-around arithmetic;  G = 0x9e3779b97f4a7c15;
+            k = mix(seed + G (level + 1)), then k = mix(k + G (i + 1)) for i_x, i_y, i_z and the
+            node index;  u1, u2 = the top 53 bits of mix(k + G), mix(k + 2 G) times 2^-53;
+            n = sqrt(-2 ln(1 - u1)) cos(2 pi u2)."""
+        u64 = np.uint64
+        G_ = u64(0x9e3779b97f4a7c15)
+
+        def mix(z):
+            z = (z ^ (z >> u64(30))) * u64(0xbf58476d1ce4e5b9)
+            z = (z ^ (z >> u64(27))) * u64(0x94d049bb133111eb)
+            return z ^ (z >> u64(31))
+
+        with np.errstate(over="ignore"):
+            cells = np.repeat(self.cells.astype(np.uint64), self.nloc, axis=0)
+            node = np.tile(np.arange(self.nloc, dtype=np.uint64), self.ncell)
+            k = mix(u64(seed) + G_ * (cells[:, 0] + u64(1)))
+            for col in (cells[:, 1], cells[:, 2], cells[:, 3], node):
+                k = mix(k + G_ * (col + u64(1)))
+            u1 = (mix(k + G_) >> u64(11)).astype(np.float64) * 2.0 ** -53
+            u2 = (mix(k + u64(2) * G_) >> u64(11)).astype(np.float64) * 2.0 ** -53
+        return sigma * np.sqrt(-2.0 * np.log(1.0 - u1)) * np.cos(2.0 * math.pi * u2)
+
     # ------------------------------------------------------------------------------ time step
     def initial_state(self, ubar: float = 0.0, dT: np.ndarray | None = None) -> np.ndarray:
         """Hydrostatic background with uniform horizontal wind ubar; with a temperature

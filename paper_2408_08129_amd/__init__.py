@@ -23,6 +23,7 @@ DG_FP64, DG_FP32_INNER = 0, 1
 DG_PREC_DIAGONAL, DG_PREC_CELL_FDM = 0, 1
 ORO_FLAT, ORO_AGNESI, ORO_BELL, ORO_GAUSS_HILL, ORO_GAUSS_RIDGE = range(5)
 ATM_ISOTHERMAL, ATM_STRATIFIED = range(2)
+DG_IC_HYDROSTATIC_WIND = 0
 MAX_RULES = 8
 
 EXPORTED = ("dg_default_options", "dg_setup", "dg_footprint", "dg_mesh_info", "dg_set_stream", "dg_set_timing",
@@ -59,19 +60,24 @@ class dg_options(ctypes.Structure):
 
 class dg_step_stats(ctypes.Structure):
     _fields_ = [("gmres_iters", (ctypes.c_int32 * 8) * 2), ("outer_iters", (ctypes.c_int32 * 8) * 2),
-                ("gmres_relres", (ctypes.c_double * 8) * 2), ("t_kernel_ms", ctypes.c_double * 8),
+                ("gmres_relres", (ctypes.c_double * 8) * 2), ("fp_incr", (ctypes.c_double * 8) * 2),
+                ("t_phase_ms", ctypes.c_double * 8), ("t_kernel_ms", ctypes.c_double * 8),
                 ("n_kernel", ctypes.c_int32 * 8), ("bytes_kernel", ctypes.c_double * 8),
                 ("t_step_ms", ctypes.c_double),
                 ("mass", ctypes.c_double), ("max_w", ctypes.c_double)]
 
-    KERNEL_CLASSES = ("explicit_residual", "weak_gradient", "weak_divergence", "gs_dots",
-                      "pointwise", "gs_update", "krylov_other")
+    KERNEL_CLASSES = ("explicit_residual", "helmholtz_pass1", "helmholtz_pass2", "gs_dots",
+                      "pointwise", "gs_update", "krylov_other", "operator_other")
+    PHASES = ("explicit_residuals", "implicit_term", "stage_updates", "fixed_point_coefficients",
+              "helmholtz_rhs", "krylov", "back_substitution", "checks_and_diagnostics")
 
     def as_dict(self, fp_iters: int = 8) -> dict:
         return {
             "gmres_iters": [[self.gmres_iters[s][l] for l in range(fp_iters)] for s in range(2)],
             "outer_iters": [[self.outer_iters[s][l] for l in range(fp_iters)] for s in range(2)],
             "gmres_relres": [[self.gmres_relres[s][l] for l in range(fp_iters)] for s in range(2)],
+            "fp_incr": [[self.fp_incr[s][l] for l in range(fp_iters)] for s in range(2)],
+            "t_phase_ms": {k: self.t_phase_ms[i] for i, k in enumerate(self.PHASES)},
             "t_kernel_ms": {k: self.t_kernel_ms[i] for i, k in enumerate(self.KERNEL_CLASSES)},
             "n_kernel": {k: self.n_kernel[i] for i, k in enumerate(self.KERNEL_CLASSES)},
             "bytes_kernel": {k: self.bytes_kernel[i] for i, k in enumerate(self.KERNEL_CLASSES)},
@@ -131,7 +137,7 @@ def lib():
         L.dg_sizes.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]
         L.dg_cell_table.argtypes = [vp, ctypes.POINTER(i32)]
         L.dg_node_geometry.argtypes = [vp, vp, vp, vp, vp]
-        L.dg_init_state.argtypes = [vp, d, vp, vp]
+        L.dg_init_state.argtypes = [vp, i32, ctypes.POINTER(d), ctypes.c_uint64, d, vp]
         L.dg_explicit_residual.argtypes = [vp, vp, vp]
         L.dg_implicit_term.argtypes = [vp, vp, vp]
         L.dg_apply_helmholtz.argtypes = [vp, d, vp, vp, vp, i32]
@@ -141,7 +147,7 @@ def lib():
                                             ctypes.POINTER(d), i32, ctypes.POINTER(dg_step_stats),
                                             ctypes.POINTER(i32)]
         L.dg_diagnostics.argtypes = [vp, vp, ctypes.POINTER(d), ctypes.POINTER(d)]
-        L.dg_last_error.argtypes = []
+        L.dg_last_error.argtypes = [vp]
         L.dg_last_error.restype = ctypes.c_char_p
         L.dg_destroy.argtypes = [vp]
         L.dg_destroy.restype = None
@@ -152,9 +158,9 @@ def lib():
     return _lib
 
 
-def _check(rc: int):
+def _check(rc: int, ctx: int | None = None):
     if rc != DG_OK:
-        raise DGError(rc, lib().dg_last_error().decode())
+        raise DGError(rc, lib().dg_last_error(ctypes.c_void_p(ctx)).decode())
 
 
 # ----------------------------------------------------------------------------------- descriptions
@@ -249,25 +255,32 @@ def _ptr(t) -> ctypes.c_void_p:
     return ctypes.c_void_p(0 if t is None else t.data_ptr())
 
 
+def dg_init_state(ctx: int, U, ubar: float = 0.0, noise_seed: int = 0, noise_sigma_K: float = 0.0,
+                  ic_kind: int = DG_IC_HYDROSTATIC_WIND):
+    params = (ctypes.c_double * 4)(float(ubar), 0.0, 0.0, 0.0)
+    _check(lib().dg_init_state(ctypes.c_void_p(ctx), ic_kind, params, ctypes.c_uint64(int(noise_seed)),
+                               float(noise_sigma_K), _ptr(U)), ctx)
+
+
 def dg_explicit_residual(ctx: int, U, R):
-    _check(lib().dg_explicit_residual(ctypes.c_void_p(ctx), _ptr(U), _ptr(R)))
+    _check(lib().dg_explicit_residual(ctypes.c_void_p(ctx), _ptr(U), _ptr(R)), ctx)
 
 
 def dg_implicit_term(ctx: int, U, F):
-    _check(lib().dg_implicit_term(ctypes.c_void_p(ctx), _ptr(U), _ptr(F)))
+    _check(lib().dg_implicit_term(ctypes.c_void_p(ctx), _ptr(U), _ptr(F)), ctx)
 
 
 def dg_apply_helmholtz(ctx: int, dt_a: float, h, p, Ap, prec: int = DG_FP64):
-    _check(lib().dg_apply_helmholtz(ctypes.c_void_p(ctx), float(dt_a), _ptr(h), _ptr(p), _ptr(Ap), prec))
+    _check(lib().dg_apply_helmholtz(ctypes.c_void_p(ctx), float(dt_a), _ptr(h), _ptr(p), _ptr(Ap), prec), ctx)
 
 
 def dg_apply_preconditioner(ctx: int, dt_a: float, h, v, z, prec: int = DG_FP64):
-    _check(lib().dg_apply_preconditioner(ctypes.c_void_p(ctx), float(dt_a), _ptr(h), _ptr(v), _ptr(z), prec))
+    _check(lib().dg_apply_preconditioner(ctypes.c_void_p(ctx), float(dt_a), _ptr(h), _ptr(v), _ptr(z), prec), ctx)
 
 
 def imex_rk2_step(ctx: int, U, dt: float) -> dg_step_stats:
     st = dg_step_stats()
-    _check(lib().imex_rk2_step(ctypes.c_void_p(ctx), _ptr(U), float(dt), ctypes.byref(st)))
+    _check(lib().imex_rk2_step(ctypes.c_void_p(ctx), _ptr(U), float(dt), ctypes.byref(st)), ctx)
     return st
 
 
@@ -288,7 +301,7 @@ def imex_rk2_step_batched(ctxs, Us, dts, raise_on_error: bool = True):
 def dg_diagnostics(ctx: int, U):
     m = ctypes.c_double()
     w = ctypes.c_double()
-    _check(lib().dg_diagnostics(ctypes.c_void_p(ctx), _ptr(U), ctypes.byref(m), ctypes.byref(w)))
+    _check(lib().dg_diagnostics(ctypes.c_void_p(ctx), _ptr(U), ctypes.byref(m), ctypes.byref(w)), ctx)
     return m.value, w.value
 
 
@@ -346,9 +359,9 @@ class Solver:
         self._sync()
         return x, y, z, wJ
 
-    def init_state(self, ubar: float = 0.0, dT=None):
+    def init_state(self, ubar: float = 0.0, noise_seed: int = 0, noise_sigma_K: float = 0.0):
         U = self.empty_state()
-        _check(lib().dg_init_state(ctypes.c_void_p(self.ctx), float(ubar), _ptr(dT), _ptr(U)))
+        dg_init_state(self.ctx, U, ubar, noise_seed, noise_sigma_K)
         return U
 
     def explicit_residual(self, U):

@@ -535,14 +535,39 @@ __global__ void k_final(const double* __restrict__ U, const double* __restrict__
   }
 }
 
+// SplitMix64 (Steele, Lea, Flood 2014) as a counter-based generator: the output mix of the state
+// seed + G k.  A node's deviates are keyed by the seed, its cell's (level, i_x, i_y, i_z) and its
+// index in the cell, so the noise field does not depend on the cell order or on the launch.
+__device__ __forceinline__ uint64_t sm64_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+constexpr uint64_t kSmGolden = 0x9e3779b97f4a7c15ull;
+
+// Standard normal deviate of node q of a cell with table entry (level, i_x, i_y, i_z) (Box-Muller).
+__device__ __forceinline__ double node_normal(uint64_t seed, int4 cl, int D, int q) {
+  const int iy = D == 3 ? cl.z : 0, iz = D == 3 ? cl.w : cl.z;
+  uint64_t k = sm64_mix(seed + kSmGolden * (uint64_t)(cl.x + 1));
+  k = sm64_mix(k + kSmGolden * (uint64_t)(cl.y + 1));
+  k = sm64_mix(k + kSmGolden * (uint64_t)(iy + 1));
+  k = sm64_mix(k + kSmGolden * (uint64_t)(iz + 1));
+  k = sm64_mix(k + kSmGolden * (uint64_t)(q + 1));
+  const double u1 = (double)(sm64_mix(k + kSmGolden) >> 11) * 0x1.0p-53;
+  const double u2 = (double)(sm64_mix(k + 2 * kSmGolden) >> 11) * 0x1.0p-53;
+  return sqrt(-2.0 * log(1.0 - u1)) * cos(2.0 * kPi * u2);
+}
+
+// Hydrostatic background with uniform wind; with sigma > 0 the temperature of every node is
+// perturbed by sigma n at constant pressure.
 template <int D>
 __global__ void k_init_state(const double* __restrict__ pbar, const double* __restrict__ rbar,
-                             const double* __restrict__ dT, double ubar, long N, long ld,
-                             double* __restrict__ U) {
+                             const int4* __restrict__ cell, int nloc, uint64_t seed, double sigma,
+                             double ubar, long N, long ld, double* __restrict__ U) {
   GRID_LOOP(e, N) {
     double rho = rbar[e];
-    if (dT) {
-      const double T = pbar[e] / (kR * rbar[e]) + dT[e];
+    if (sigma > 0.0) {
+      const double T = pbar[e] / (kR * rbar[e]) + sigma * node_normal(seed, cell[e / nloc], D, (int)(e % nloc));
       rho = pbar[e] / (kR * T);
     }
     U[e] = rho;
@@ -780,13 +805,22 @@ struct dg_ctx {
   std::vector<int> ev_cls;
   int ev_n = 0;
   double kbytes[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // per-phase HIP events (timing on): pairs around the phases of a step, tagged with the phase
+  std::vector<hipEvent_t> pev;
+  std::vector<int> pev_cls;
+  int pev_n = 0;
+  mutable std::string err;  // last error of a call on this context
 };
 
 namespace {
 
-dg_status fail(dg_ctx* c, dg_status st, const std::string& msg) {
+void set_error(const dg_ctx* c, const std::string& msg) {
   g_last_error = msg;
-  (void)c;
+  if (c) c->err = msg;
+}
+
+dg_status fail(const dg_ctx* c, dg_status st, const std::string& msg) {
+  set_error(c, msg);
   return st;
 }
 
@@ -808,6 +842,25 @@ struct Timed {
     if (slot >= 0) (void)hipEventRecord(c->ev[2 * slot + 1], c->stream);
   }
 };
+// Records a HIP event pair around a phase of the step when timing is on.
+constexpr int kPhasePool = 512;
+struct Phase {
+  dg_ctx* c;
+  int slot = -1;
+  Phase(dg_ctx* c_, int ph) : c(c_) {
+    if (c->timing && c->pev_n < kPhasePool) {
+      slot = c->pev_n++;
+      c->pev_cls[slot] = ph;
+      (void)hipEventRecord(c->pev[2 * slot], c->stream);
+    }
+  }
+  void end() {
+    if (slot >= 0) (void)hipEventRecord(c->pev[2 * slot + 1], c->stream);
+    slot = -1;
+  }
+  ~Phase() { end(); }
+};
+
 #define TIMED(cls, stmt) \
   do {                   \
     Timed t_(c, cls);    \
@@ -824,7 +877,7 @@ struct Timed {
   do {                                                                            \
     hipError_t e_ = (call);                                                       \
     if (e_ != hipSuccess) {                                                       \
-      g_last_error = std::string(#call) + ": " + hipGetErrorString(e_);          \
+      set_error(c, std::string(#call) + ": " + hipGetErrorString(e_));          \
       return DG_EDEVICE;                                                          \
     }                                                                             \
   } while (0)
@@ -832,7 +885,7 @@ struct Timed {
   do {                                                                            \
     int e_ = (call);                                                              \
     if (e_ != 0) {                                                                \
-      g_last_error = std::string("launch failed: ") + #call;                     \
+      set_error(c, std::string("launch failed: ") + #call);                     \
       return e_ == -6 ? DG_EUNSUPPORTED : DG_EDEVICE;                             \
     }                                                                             \
   } while (0)
@@ -1387,7 +1440,7 @@ dg_status implicit_term(dg_ctx* c, const double* U, double* F) {
   TIMED(4, split_update(c));
   GradArgs<double> g{c->pp, nullptr, 1.0, c->q, nullptr, nullptr};
   int rg;
-  TIMED(1, rg = launch_grad64(c->md, c->degree, g, c->stream));
+  TIMED(7, rg = launch_grad64(c->md, c->degree, g, c->stream));
   LCHK(rg);
   if (D == 2)
     TIMED(4, hipLaunchKernelGGL((k_fi_momentum<2>), pw_grid(N), dim3(256), 0, c->stream, c->q, U, c->rbar, N, ld, F));
@@ -1397,7 +1450,7 @@ dg_status implicit_term(dg_ctx* c, const double* U, double* F) {
   DivArgs<double> a{U + ld, c->h, c->pp, nullptr, 1.0, c->lam, -1.0,
                     -beta / (2.0 * (kGamma - 1.0)), 0.0, 0, F + (size_t)(1 + D) * ld};
   int rd;
-  TIMED(2, rd = energy_div<double>(c, a));
+  TIMED(7, rd = energy_div<double>(c, a));
   LCHK(rd);
   return DG_OK;
 }
@@ -1415,21 +1468,36 @@ dg_status step_impl(dg_ctx* c, double* U, double dt, dg_step_stats* stats) {
   dg_step_stats st{};
   dg_status rc;
   c->ev_n = 0;
+  c->pev_n = 0;
   for (double& b : c->kbytes) b = 0.0;
   const auto t0 = std::chrono::steady_clock::now();
+  const int G = red_grid(N);
 
-  if ((rc = explicit_residual(c, U, c->FE[0]))) return rc;
-  if ((rc = implicit_term(c, U, c->FI[0]))) return rc;
+  {
+    Phase ph(c, 0);
+    if ((rc = explicit_residual(c, U, c->FE[0]))) return rc;
+  }
+  {
+    Phase ph(c, 1);
+    if ((rc = implicit_term(c, U, c->FI[0]))) return rc;
+  }
   // stage state starts from U^n: momentum, and p' (left in c->pp by implicit_term)
-  TIMED(4, hipLaunchKernelGGL((k_copy_m<D>), pg, bs, 0, s, U, ld, N, c->Us));
+  {
+    Phase ph(c, 2);
+    TIMED(4, hipLaunchKernelGGL((k_copy_m<D>), pg, bs, 0, s, U, ld, N, c->Us));
+  }
   const double beta = c->opt.penalty_beta;
   for (int i = 1; i <= 2; ++i) {
     const double aii = At[i][i], dta = dt * aii;
     // predictor; Us[0] <- rho_i, mt, et, mp
-    TIMED(4, hipLaunchKernelGGL((k_predictor<D>), pg, bs, 0, s, U, c->FE[0], c->FE[1], c->FI[0], c->FI[1], i,
-                       A[i][0], A[i][1], At[i][0], At[i][1], dt, dta, c->rbar, N, ld, c->Us, c->mt,
-                       c->et, c->mp));
+    {
+      Phase ph(c, 2);
+      TIMED(4, hipLaunchKernelGGL((k_predictor<D>), pg, bs, 0, s, U, c->FE[0], c->FE[1], c->FI[0], c->FI[1], i,
+                                  A[i][0], A[i][1], At[i][0], At[i][1], dt, dta, c->rbar, N, ld, c->Us, c->mt,
+                                  c->et, c->mp));
+    }
     for (int l = 0; l < c->opt.fp_iters; ++l) {
+      Phase ph3(c, 3);
       TIMED(4, hipLaunchKernelGGL(k_coef, pg, bs, 0, s, c->Us, c->pbar, c->pp, c->wJ, c->d_cell, c->NL, D,
                          c->hm.L[0], c->hm.L[1], c->hm.L[2], c->hm.nb[0], c->hm.nb[1], c->hm.nb[2],
                          c->degree + 1, dta, N, c->h, c->dinv,
@@ -1443,19 +1511,26 @@ dg_status step_impl(dg_ctx* c, double* U, double dt, dg_step_stats* stats) {
         LCHK(rcc);
       }
       TIMED(4, split_update(c));
-      // b = -dta C(h m') + M (e~ - rho k - pbar/(gamma-1))
-      DivArgs<double> a{c->mp, c->h, nullptr, nullptr, 1.0, c->lam, -dta, 0.0, 0.0, 1, c->b};
-      int rd;
-      TIMED(2, rd = energy_div<double>(c, a));
-      LCHK(rd);
-      TIMED(4, hipLaunchKernelGGL((k_rhs_add<D>), pg, bs, 0, s, c->b, c->wJ, c->et, c->Us, c->pbar, N, ld));
-      // r0 = b - A p'
-      if (apply_A<double>(c, dta, c->pp, nullptr, 1.0, c->w)) return fail(c, DG_EDEVICE, "operator launch failed");
-      TIMED(4, hipLaunchKernelGGL(k_sub, pg, bs, 0, s, c->b, c->w, N, c->r0));
+      ph3.end();
+      {
+        Phase ph(c, 4);
+        // b = -dta C(h m') + M (e~ - rho k - pbar/(gamma-1))
+        DivArgs<double> a{c->mp, c->h, nullptr, nullptr, 1.0, c->lam, -dta, 0.0, 0.0, 1, c->b};
+        int rd;
+        TIMED(7, rd = energy_div<double>(c, a));
+        LCHK(rd);
+        TIMED(4, hipLaunchKernelGGL((k_rhs_add<D>), pg, bs, 0, s, c->b, c->wJ, c->et, c->Us, c->pbar, N, ld));
+        // r0 = b - A p'
+        if (apply_A<double>(c, dta, c->pp, nullptr, 1.0, c->w)) return fail(c, DG_EDEVICE, "operator launch failed");
+        TIMED(4, hipLaunchKernelGGL(k_sub, pg, bs, 0, s, c->b, c->w, N, c->r0));
+      }
       int its = 0, outer = 0;
       double rel = 0.0;
-      if (c->opt.precision == DG_FP32_INNER) rc = solve_mixed(c, dta, its, outer, rel);
-      else rc = solve64(c, dta, its, rel);
+      {
+        Phase ph(c, 5);
+        if (c->opt.precision == DG_FP32_INNER) rc = solve_mixed(c, dta, its, outer, rel);
+        else rc = solve64(c, dta, its, rel);
+      }
       if (l < 8) {
         st.gmres_iters[i - 1][l] = its;
         st.outer_iters[i - 1][l] = outer;
@@ -1465,20 +1540,40 @@ dg_status step_impl(dg_ctx* c, double* U, double dt, dg_step_stats* stats) {
         if (stats) *stats = st;
         return rc;
       }
-      TIMED(4, hipLaunchKernelGGL(k_add, pg, bs, 0, s, c->pp, c->delta, N));
-      GradArgs<double> gq{c->pp, nullptr, 1.0, c->q, nullptr, nullptr};
-      int rg;
-      TIMED(1, rg = launch_grad64(c->md, c->degree, gq, s));
-      LCHK(rg);
-      TIMED(4, hipLaunchKernelGGL((k_backsub<D>), pg, bs, 0, s, c->mp, c->q, dta, N, ld, c->Us));
+      {
+        Phase ph(c, 6);
+        TIMED(4, hipLaunchKernelGGL(k_add, pg, bs, 0, s, c->pp, c->delta, N));
+        GradArgs<double> gq{c->pp, nullptr, 1.0, c->q, nullptr, nullptr};
+        int rg;
+        TIMED(7, rg = launch_grad64(c->md, c->degree, gq, s));
+        LCHK(rg);
+        TIMED(4, hipLaunchKernelGGL((k_backsub<D>), pg, bs, 0, s, c->mp, c->q, dta, N, ld, c->Us));
+      }
+      if (stats && l < 8) {
+        // fixed-point increment |delta| / |p'| (one reduction pass: delta.delta, delta.p', p'.p')
+        double r3[3];
+        TIMEDB(3, 16.0 * N, launch_gs_dots<double>(0, G, s, (const double*)nullptr, ld, c->delta, c->pp, c->part, N));
+        if ((rc = reduce_to_host(c, 3, G, r3))) return rc;
+        st.fp_incr[i - 1][l] = r3[2] > 0.0 ? std::sqrt(r3[0] / r3[2]) : std::sqrt(r3[0]);
+      }
     }
-    TIMED(4, hipLaunchKernelGGL((k_stage_finish<D>), pg, bs, 0, s, c->Us, c->pp, c->pbar, c->mt, c->et, dta,
-                       N, ld, c->FI[i]));
-    if ((rc = explicit_residual(c, c->Us, c->FE[i]))) return rc;
+    {
+      Phase ph(c, 2);
+      TIMED(4, hipLaunchKernelGGL((k_stage_finish<D>), pg, bs, 0, s, c->Us, c->pp, c->pbar, c->mt, c->et, dta,
+                                  N, ld, c->FI[i]));
+    }
+    {
+      Phase ph(c, 0);
+      if ((rc = explicit_residual(c, c->Us, c->FE[i]))) return rc;
+    }
   }
   (void)beta;
-  TIMED(4, hipLaunchKernelGGL((k_final<D>), pg, bs, 0, s, U, c->FE[0], c->FE[1], c->FE[2], c->FI[0], c->FI[1],
-                     c->FI[2], bw[0], bw[1], bw[2], dt, N, ld, c->Un));
+  {
+    Phase ph(c, 2);
+    TIMED(4, hipLaunchKernelGGL((k_final<D>), pg, bs, 0, s, U, c->FE[0], c->FE[1], c->FE[2], c->FI[0], c->FI[1],
+                                c->FI[2], bw[0], bw[1], bw[2], dt, N, ld, c->Un));
+  }
+  Phase ph7(c, 7);
   HIPCHK(hipMemsetAsync(c->flag, 0, sizeof(int), s));
   for (int f = 0; f < c->F; ++f)
     TIMED(4, hipLaunchKernelGGL(k_nonfinite, pw_grid(N), bs, 0, s, c->Un + (size_t)f * ld, N, c->flag));
@@ -1496,6 +1591,7 @@ dg_status step_impl(dg_ctx* c, double* U, double dt, dg_step_stats* stats) {
     if ((rc = dg_diagnostics(c, U, &mass, &mw))) return rc;
     st.mass = mass;
     st.max_w = mw;
+    ph7.end();
     if (c->timing) {
       HIPCHK(hipStreamSynchronize(s));
       st.t_step_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1506,6 +1602,11 @@ dg_status step_impl(dg_ctx* c, double* U, double dt, dg_step_stats* stats) {
         st.n_kernel[c->ev_cls[e]] += 1;
       }
       for (int k = 0; k < 8; ++k) st.bytes_kernel[k] = c->kbytes[k];
+      for (int e = 0; e < c->pev_n; ++e) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c->pev[2 * e], c->pev[2 * e + 1]));
+        st.t_phase_ms[c->pev_cls[e]] += ms;
+      }
     }
     *stats = st;
   }
@@ -1534,7 +1635,10 @@ void dg_default_options(dg_options* o) {
   o->enthalpy_split = 0;
 }
 
-const char* dg_last_error(void) { return g_last_error.c_str(); }
+const char* dg_last_error(const dg_ctx* c) {
+  if (c && !c->err.empty()) return c->err.c_str();
+  return g_last_error.c_str();
+}
 
 dg_status dg_footprint(const dg_case_desc* desc, int32_t degree, const dg_options* opt, size_t* bytes) {
   if (!bytes) return fail(nullptr, DG_EINVAL, "null output");
@@ -1690,6 +1794,7 @@ void dg_destroy(dg_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   for (auto& e : c->ev) (void)hipEventDestroy(e);
+  for (auto& e : c->pev) (void)hipEventDestroy(e);
   if (c->arena) (void)hipFree(c->arena);
   if (c->hred) (void)hipHostFree(c->hred);
   delete c;
@@ -1708,6 +1813,9 @@ dg_status dg_set_timing(dg_ctx* c, int32_t enable) {
     c->ev.resize(2 * kEvPool);
     c->ev_cls.assign(kEvPool, 0);
     for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+    c->pev.resize(2 * kPhasePool);
+    c->pev_cls.assign(kPhasePool, 0);
+    for (auto& e : c->pev) HIPCHK(hipEventCreate(&e));
   }
   return DG_OK;
 }
@@ -1748,12 +1856,20 @@ dg_status dg_node_geometry(dg_ctx* c, double* x, double* y, double* z, double* w
   return DG_OK;
 }
 
-dg_status dg_init_state(dg_ctx* c, double ubar, const double* dT, double* U) {
-  if (!c || !U) return fail(nullptr, DG_EINVAL, "null argument");
+dg_status dg_init_state(dg_ctx* c, int32_t ic_kind, const double* ic_params, uint64_t noise_seed,
+                        double noise_sigma_K, double* U) {
+  if (!c || !U || !ic_params) return fail(c, DG_EINVAL, "null argument");
+  if (ic_kind != DG_IC_HYDROSTATIC_WIND) return fail(c, DG_EINVAL, "unknown initial-condition kind");
+  if (!(noise_sigma_K >= 0.0) || !std::isfinite(noise_sigma_K))
+    return fail(c, DG_EINVAL, "noise sigma must be finite and >= 0");
+  const double ubar = ic_params[0];
+  if (!std::isfinite(ubar)) return fail(c, DG_EINVAL, "wind must be finite");
   if (c->D == 2)
-    hipLaunchKernelGGL((k_init_state<2>), pw_grid(c->N), dim3(256), 0, c->stream, c->pbar, c->rbar, dT, ubar, c->N, c->ld, U);
+    hipLaunchKernelGGL((k_init_state<2>), pw_grid(c->N), dim3(256), 0, c->stream, c->pbar, c->rbar, c->d_cell,
+                       c->NL, noise_seed, noise_sigma_K, ubar, c->N, c->ld, U);
   else
-    hipLaunchKernelGGL((k_init_state<3>), pw_grid(c->N), dim3(256), 0, c->stream, c->pbar, c->rbar, dT, ubar, c->N, c->ld, U);
+    hipLaunchKernelGGL((k_init_state<3>), pw_grid(c->N), dim3(256), 0, c->stream, c->pbar, c->rbar, c->d_cell,
+                       c->NL, noise_seed, noise_sigma_K, ubar, c->N, c->ld, U);
   HIPCHK(hipGetLastError());
   return DG_OK;
 }
@@ -1833,7 +1949,7 @@ dg_status imex_rk2_step_batched(dg_ctx* const* ctxs, double* const* Us, const do
   for (int i = 0; i < n; ++i)
     th.emplace_back([&, i]() {
       rc[i] = imex_rk2_step(ctxs[i], Us[i], dts[i], stats ? &stats[i] : nullptr);
-      if (rc[i]) msg[i] = g_last_error;
+      if (rc[i]) msg[i] = ctxs[i] ? ctxs[i]->err : g_last_error;
       if (ctxs[i]) (void)hipStreamSynchronize(ctxs[i]->stream);
       if (stats)
         stats[i].t_step_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

@@ -140,7 +140,7 @@ class Server:
         w = req.work
         ctx_bytes = self.P.dg_footprint(self._case(w), w["degree"], self.opt)
         n = w["cells"] * (w["degree"] + 1) ** w["dim"]
-        return ctx_bytes + (w["dim"] + 2) * n * 8 + n * 8  # + state + noise
+        return ctx_bytes + (w["dim"] + 2) * n * 8  # + state
 
     # -- device side (replaceable in tests) --------------------------------------------------
     def _admit(self, req: Request, res: MemberResult) -> _Member:
@@ -149,9 +149,8 @@ class Server:
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
             solver = P.Solver(self._case(w), w["degree"], self.opt, stream=stream)
-            rng = np.random.default_rng(req.noise_seed)
-            dT = torch.from_numpy(req.noise_sigma * rng.standard_normal(solver.N)).to("cuda")
-            U = solver.init_state(w["ubar"], dT)
+            # the temperature noise is drawn in the library (seeded, per node)
+            U = solver.init_state(w["ubar"], req.noise_seed, req.noise_sigma)
         stream.synchronize()
         res.dofs = solver.nf * solver.N
         res.ncell = solver.ncell

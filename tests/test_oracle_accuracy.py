@@ -260,3 +260,44 @@ def test_wall_flux_enters_the_residual():
     assert abs(got[2] - total[2]) < 1e-12 * scale
     assert abs(got[0]) < 1e-12 * np.sum(np.abs(o.wJ * R[0]))
     assert abs(got[1]) < 1e-12 * np.sum(np.abs(o.wJ * R[1]))
+
+
+# ------------------------------------------------------------------- initial-state noise
+def test_noise_generator_is_splitmix64():
+    """The oracle's temperature noise follows SplitMix64's published definition: its output mix of
+    the state G = 0x9e3779b97f4a7c15 (seed 0, first draw) is 0xe220a8397b1dcdaf.  A one-node,
+    one-cell mesh pins the key chain: the first deviate equals the Box-Muller transform of the two
+    draws that follow the chain, written out here from the definition."""
+    def mix(z):
+        m = (1 << 64) - 1
+        z = ((z ^ (z >> 30)) * 0xbf58476d1ce4e5b9) & m
+        z = ((z ^ (z >> 27)) * 0x94d049bb133111eb) & m
+        return z ^ (z >> 31)
+    G_ = 0x9e3779b97f4a7c15
+    m64 = (1 << 64) - 1
+    assert mix(G_) == 0xe220a8397b1dcdaf
+    o = O.Oracle(O.Case(dim=2, degree=1, nbase=(3, 1, 2), length=(3000.0, 1.0, 2000.0)))
+    seed = 2408
+    n = o.temperature_noise(seed, 1.0)
+    for cell in (0, 4):
+        lev, ix, iy, iz = (int(v) for v in o.cells[cell])
+        for q in range(o.nloc):
+            k = mix((seed + G_ * (lev + 1)) & m64)
+            for v in (ix, iy, iz, q):
+                k = mix((k + G_ * (v + 1)) & m64)
+            u1 = (mix((k + G_) & m64) >> 11) * 2.0 ** -53
+            u2 = (mix((k + 2 * G_) & m64) >> 11) * 2.0 ** -53
+            ref = math.sqrt(-2.0 * math.log(1.0 - u1)) * math.cos(2.0 * math.pi * u2)
+            assert abs(n[cell * o.nloc + q] - ref) < 1e-15
+
+
+def test_noise_is_standard_normal_and_seeded():
+    from scipy import stats
+    o = O.Oracle(O.Case(dim=3, degree=3, nbase=(12, 12, 6), length=(1e4, 1e4, 5e3)))
+    n = o.temperature_noise(2408, 1.0)
+    assert abs(n.mean()) < 5.0 / math.sqrt(len(n))
+    assert abs(n.std() - 1.0) < 0.01
+    assert stats.kstest(n, "norm").pvalue > 1e-3
+    assert np.array_equal(n, o.temperature_noise(2408, 1.0))
+    assert abs(np.corrcoef(n, o.temperature_noise(2409, 1.0))[0, 1]) < 0.02
+    assert np.allclose(o.temperature_noise(2408, 0.1), 0.1 * n, rtol=1e-15, atol=0)
