@@ -838,7 +838,10 @@ __global__ void __launch_bounds__(256) k_fdm_col(const FdmArgs<T> a, const MeshD
   const unsigned base = (unsigned)cl * NL + c;
   T v[NP], w[NP];
 #pragma unroll
-  for (int z = 0; z < NP; ++z) v[z] = a.scale * a.v[base + NC * z];
+  for (int z = 0; z < NP; ++z) v[z] = a.v[base + NC * z];
+  const T sc = a.dscale ? (T)*a.dscale : a.scale;
+#pragma unroll
+  for (int z = 0; z < NP; ++z) v[z] *= sc;
   const T cf0 = a.coef[cl * 4 + 0], cfx = a.coef[cl * 4 + 1], cfy = a.coef[cl * 4 + 2];
   const T cfz = a.coef[cl * 4 + D];
   // vertical forward: w_j = sum_q S[q][j] v_q

@@ -117,6 +117,7 @@ struct FdmArgs {
   T scale;
   const T* coef;
   T* z;
+  const double* dscale;  // if non-null: the scale is read from device memory (*dscale) instead
 };
 
 // --------------------------------------------------------------------------------- launchers

@@ -28,6 +28,8 @@ namespace dg {
 namespace {
 
 constexpr int kMaxV = 32;  // max Krylov vectors per pass (restart <= 31)
+// meshes of at most this many nodes per field run the GMRES iteration with one host round trip
+constexpr long kOneSyncMaxNodes = 1L << 23;
 constexpr int kRedThreads = 256;
 
 thread_local std::string g_last_error;
@@ -297,6 +299,24 @@ __global__ void k_maxabs_ratio(const double* __restrict__ num, const double* __r
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+// Second stage of the candidate-norm reduction of the one-round-trip GMRES iteration: out[0] =
+// |v|^2, out[1] = 1/|v| (0 for a zero vector), the scale the next operator application reads.
+__global__ void __launch_bounds__(kRedThreads) k_reduce_norm(const double* part, int G, double* out) {
+  __shared__ double s[kRedThreads / 64];
+  double t = 0.0;
+  for (int b = threadIdx.x; b < G; b += kRedThreads) t += part[b];
+  t = wave_sum(t);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double u = 0.0;
+#pragma unroll
+    for (int k = 0; k < kRedThreads / 64; ++k) u += s[k];
+    out[0] = u;
+    out[1] = u > 0.0 ? 1.0 / sqrt(u) : 0.0;
+  }
 }
 
 __global__ void k_nonfinite(const double* __restrict__ x, long n, int* flag) {
@@ -964,7 +984,7 @@ void make_plan(dg_ctx* c, Plan& P) {
     P.add((void**)&c->V, (size_t)(c->m + 1) * ld * d8);
   }
   P.add((void**)&c->part, (size_t)(2 * kMaxV + 3) * kMaxGrid * d8);
-  P.add((void**)&c->red, (2 * kMaxV + 3) * d8);
+  P.add((void**)&c->red, (2 * kMaxV + 5) * d8);
   P.add((void**)&c->flag, 256);
 }
 
@@ -1101,10 +1121,10 @@ int apply_A(dg_ctx* c, double dta, const T* v, const T* dinv, T scale, T* w) {
 
 // w = A P^{-1} (scale v): the right-preconditioned operator of the Krylov solve.
 template <class T>
-int apply_AP(dg_ctx* c, double dta, const T* v, const T* dinv, T scale, T* w) {
+int apply_AP(dg_ctx* c, double dta, const T* v, const T* dinv, T scale, T* w, const double* dscale = nullptr) {
   using PB = PrecBuf<T>;
   if (c->opt.preconditioner == DG_PREC_CELL_FDM) {
-    FdmArgs<T> f{v, scale, PB::coef(c), PB::z(c)};
+    FdmArgs<T> f{v, scale, PB::coef(c), PB::z(c), dscale};
     int rf;
     TIMEDB(4, 2.0 * sizeof(T) * c->N, rf = PB::fdm(c->md, c->degree, f, c->stream));
     if (rf) return -1;
@@ -1114,12 +1134,14 @@ int apply_AP(dg_ctx* c, double dta, const T* v, const T* dinv, T scale, T* w) {
 }
 
 // reduce nv partial sums to host
-dg_status reduce_to_host(dg_ctx* c, int nv, int G, double* out) {
+// reduce nv partial sums into red[2..2+nv) and copy red[first..2+nv) to out (first = 0 also
+// brings the candidate norm and scale that k_reduce_norm left in red[0], red[1])
+dg_status reduce_to_host(dg_ctx* c, int nv, int G, double* out, int first = 2) {
   if (nv < 1 || nv > 2 * kMaxV + 3) return fail(c, DG_EINVAL, "reduction of " + std::to_string(nv) + " values");
-  TIMED(6, hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(kRedThreads), 0, c->stream, c->part, G, c->red));
-  HIPCHK(hipMemcpyAsync(c->hred, c->red, nv * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  TIMED(6, hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(kRedThreads), 0, c->stream, c->part, G, c->red + 2));
+  HIPCHK(hipMemcpyAsync(c->hred, c->red + first, (2 + nv - first) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  memcpy(out, c->hred, nv * sizeof(double));
+  memcpy(out, c->hred, (2 + nv - first) * sizeof(double));
   return DG_OK;
 }
 
@@ -1215,14 +1237,37 @@ dg_status gmres_cycle(dg_ctx* c, double dta, T* V, T* w, const T* dinv, int m, d
     res = H.rotate(j, col, true);
     done = j;
   };
+  // Latency-bound sizes run one host round trip per iteration: the update pass leaves the
+  // candidate's norm and scale on the device (k_reduce_norm), the next operator application reads
+  // the scale there, and the host receives the norm with the next reduction.  The residual of
+  // column j is then known only after the operator has been applied to the next candidate, so a
+  // converging solve pays one extra application; large meshes keep the second round trip.
+  const bool one_rt = c->opt.preconditioner == DG_PREC_CELL_FDM && N <= kOneSyncMaxNodes;
+  double hb[2 * kMaxV + 5];
   for (int j = 0; j < m; ++j) {
     T* Vj = V + (size_t)j * ld;
-    if (apply_AP<T>(c, dta, Vj, dinv, (T)sigma, w)) return fail(c, DG_EDEVICE, "operator launch failed");
+    const bool dev_sigma = one_rt && j > 0;
+    if (apply_AP<T>(c, dta, Vj, dinv, (T)sigma, w, dev_sigma ? c->red + 1 : nullptr))
+      return fail(c, DG_EDEVICE, "operator launch failed");
     cr.its++;
     // one reduction: Q_j^T V_j, Q_j^T w, V_j.V_j, V_j.w, w.w
     TIMEDB(3, (j + 2.0) * tsz, launch_gs_dots<T>(j, G, c->stream, V, ld, Vj, w, c->part, N));
-    dg_status st = reduce_to_host(c, 2 * j + 3, G, dots);
-    if (st) return st;
+    dg_status st;
+    if (dev_sigma) {
+      st = reduce_to_host(c, 2 * j + 3, G, hb, 0);
+      if (st) return st;
+      if (!std::isfinite(hb[0])) return fail(c, DG_ENAN, "non-finite value in the Krylov solve");
+      if (hb[0] == 0.0) {
+        // A q_{j-1} lies in span(Q_j) exactly: column j-1 is exact with a zero
+        finalize(j - 1, nullptr, 0.0);
+        break;
+      }
+      sigma = hb[1];
+      std::copy(hb + 2, hb + 2 + 2 * j + 3, dots);
+    } else {
+      st = reduce_to_host(c, 2 * j + 3, G, dots);
+      if (st) return st;
+    }
     if (nonfinite(2 * j + 3)) return fail(c, DG_ENAN, "non-finite value in the Krylov solve");
     double aa = 0.0, ab = 0.0;
     for (int i = 0; i < j; ++i) {
@@ -1269,6 +1314,35 @@ dg_status gmres_cycle(dg_ctx* c, double dta, T* V, T* w, const T* dinv, int m, d
     T* Vn = V + (size_t)(j + 1) * ld;
     TIMEDB(5, (j + 3.0 + (j > 0 ? 1.0 : 0.0)) * tsz,
            launch_gs_update<T>(j, G, c->stream, V, ld, ca, cb, gj * sigma, Vj, (const T*)w, Vn, c->part, N));
+    if (one_rt) {
+      TIMED(6, hipLaunchKernelGGL(k_reduce_norm, dim3(1), dim3(kRedThreads), 0, c->stream, c->part, G, c->red));
+      s[j] = sigma / rho;
+      kappa = rho;
+      for (int i = 0; i <= j; ++i) H.hr(i, j) = t[i];
+      jd = j + 1;
+      if (j + 1 == m || cr.its >= maxits) {
+        // finalise the last column exactly: Q^T V_{j+1} and |V_{j+1}|^2 with V_{j+1}'s scale
+        TIMEDB(3, (j + 2.0) * tsz, launch_gs_dots<T>(j + 1, G, c->stream, V, ld, Vn, (const T*)nullptr, c->part, N));
+        st = reduce_to_host(c, j + 2, G, hb, 0);
+        if (st) return st;
+        if (!std::isfinite(hb[0])) return fail(c, DG_ENAN, "non-finite value in the Krylov solve");
+        if (hb[0] == 0.0) {
+          finalize(j, nullptr, 0.0);
+          break;
+        }
+        sigma = hb[1];
+        double a2 = 0.0;
+        for (int i = 0; i <= j; ++i) {
+          a[i] = s[i] * sigma * hb[2 + i];
+          a2 += a[i] * a[i];
+        }
+        if (!std::isfinite(hb[2 + j + 1])) return fail(c, DG_ENAN, "non-finite value in the Krylov solve");
+        const double c2 = sigma * sigma * hb[2 + j + 1];
+        finalize(j, a.data(), std::sqrt(std::max(c2 - a2, 0.0)));
+        break;
+      }
+      continue;
+    }
     double nn;
     st = reduce_to_host(c, 1, G, &nn);
     if (st) return st;
