@@ -306,6 +306,18 @@ dg_status imex_rk2_step_batched(dg_ctx* const* ctxs, double* const* U_devs, cons
  * ctx or U_dev, DG_EDEVICE. */
 dg_status dg_diagnostics(dg_ctx* ctx, const double* U_dev, double* mass, double* max_w);
 
+/* dg_diagnostics for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same two reductions, the same
+ * results bit for bit, with their partial sums in a fixed 64 KiB device array of the library (one
+ * per GPU, held until the process ends) instead of the context's workspace, and the maximum's
+ * second stage on the device.  Calls no hipMalloc, hipFree or allocating routine; mass and max_w
+ * are host pointers (written before the call returns: the call synchronises the context's
+ * stream).  The array is shared by every call on a GPU and keeps the last call's contents: calls
+ * that overlap on one GPU (other threads, other streams) race and must be serialised by the
+ * caller.  Any mesh size fits (the reductions use at most 2048 workgroups).  Errors: DG_EINVAL
+ * for null pointers, DG_EDEVICE for a failed HIP call. */
+dg_status dg_diagnostics_noalloc(dg_ctx* ctx, const double* U_dev, double* mass, double* max_w);
+
 /* Message of the last error: the context's own (set by any call on it, including the member steps
  * of imex_rk2_step_batched, which run on other threads) if ctx is non-NULL and has one, else the
  * calling thread's (setup and argument errors).  The string stays valid until the next call on

@@ -30,7 +30,8 @@ EXPORTED = ("dg_default_options", "dg_setup", "dg_footprint", "dg_mesh_info", "d
             "dg_sizes", "dg_cell_table", "dg_node_geometry", "dg_init_state",
             "dg_explicit_residual", "dg_implicit_term", "dg_apply_helmholtz", "dg_apply_preconditioner",
             "imex_rk2_step",
-            "imex_rk2_step_batched", "dg_diagnostics", "dg_last_error", "dg_destroy")
+            "imex_rk2_step_batched", "dg_diagnostics", "dg_diagnostics_noalloc", "dg_last_error",
+            "dg_destroy")
 
 
 class dg_refine_rule(ctypes.Structure):
@@ -147,6 +148,7 @@ def lib():
                                             ctypes.POINTER(d), i32, ctypes.POINTER(dg_step_stats),
                                             ctypes.POINTER(i32)]
         L.dg_diagnostics.argtypes = [vp, vp, ctypes.POINTER(d), ctypes.POINTER(d)]
+        L.dg_diagnostics_noalloc.argtypes = [vp, vp, ctypes.POINTER(d), ctypes.POINTER(d)]
         L.dg_last_error.argtypes = [vp]
         L.dg_last_error.restype = ctypes.c_char_p
         L.dg_destroy.argtypes = [vp]
@@ -302,6 +304,13 @@ def dg_diagnostics(ctx: int, U):
     m = ctypes.c_double()
     w = ctypes.c_double()
     _check(lib().dg_diagnostics(ctypes.c_void_p(ctx), _ptr(U), ctypes.byref(m), ctypes.byref(w)), ctx)
+    return m.value, w.value
+
+
+def dg_diagnostics_noalloc(ctx: int, U):
+    m = ctypes.c_double()
+    w = ctypes.c_double()
+    _check(lib().dg_diagnostics_noalloc(ctypes.c_void_p(ctx), _ptr(U), ctypes.byref(m), ctypes.byref(w)), ctx)
     return m.value, w.value
 
 

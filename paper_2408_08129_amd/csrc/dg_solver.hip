@@ -19,6 +19,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -33,6 +34,17 @@ constexpr long kOneSyncMaxNodes = 1L << 23;
 constexpr int kRedThreads = 256;
 
 thread_local std::string g_last_error;
+
+// Device scratch of the allocation-free diagnostics entry point (dg_diagnostics_noalloc): the
+// per-block partial sums of its two reductions (3 values x kMaxGrid blocks for the mass pass,
+// kMaxGrid for the maximum) and their results.  One copy per GPU for the life of the process; in
+// host code its address is only ever taken through hipGetSymbolAddress (scratch_ptr).
+constexpr int kScratchGrid = 2048;
+constexpr int kScratchDoubles = 4 * kScratchGrid + 8;
+__device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+double* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
 
 struct Coef { double c[kMaxV]; };
 
@@ -317,6 +329,20 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce_norm(const double* part,
     out[0] = u;
     out[1] = u > 0.0 ? 1.0 / sqrt(u) : 0.0;
   }
+}
+
+// Second stage of the max reduction: one workgroup, fixed order.
+__global__ void __launch_bounds__(kRedThreads) k_reduce_max(const double* part, int G, double* out) {
+  __shared__ double s[kRedThreads];
+  double m = 0.0;
+  for (int b = threadIdx.x; b < G; b += kRedThreads) m = fmax(m, part[b]);
+  s[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = s[0];
 }
 
 __global__ void k_nonfinite(const double* __restrict__ x, long n, int* flag) {
@@ -842,6 +868,24 @@ void set_error(const dg_ctx* c, const std::string& msg) {
 dg_status fail(const dg_ctx* c, dg_status st, const std::string& msg) {
   set_error(c, msg);
   return st;
+}
+
+// Device address of the scratch array on the current device, looked up once per device.
+dg_status scratch_ptr(const dg_ctx* c, double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return fail(c, DG_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(c, DG_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return DG_OK;
 }
 
 constexpr int kEvPool = 8192;
@@ -1754,6 +1798,11 @@ dg_status dg_setup(const dg_case_desc* desc, int32_t degree, const dg_options* o
   dg_status st = prepare(c, desc, degree, opt);
   if (st) { delete c; return st; }
   c->stream = (hipStream_t)stream;
+  {
+    double* sp = nullptr;
+    st = scratch_ptr(c, &sp);
+    if (st) { delete c; return st; }
+  }
   Plan P;
   make_plan(c, P);
   hipError_t e = hipMalloc((void**)&c->arena, P.total);
@@ -2057,6 +2106,29 @@ dg_status dg_diagnostics(dg_ctx* c, const double* U, double* mass, double* max_w
     for (double v : parts) m = std::max(m, v);
     *max_w = m;
   }
+  return DG_OK;
+}
+
+dg_status dg_diagnostics_noalloc(dg_ctx* c, const double* U, double* mass, double* max_w) {
+  if (!c || !U || !mass || !max_w) return fail(c, DG_EINVAL, "null argument");
+  const long N = c->N;
+  const int G = red_grid(N);
+  if (G > kScratchGrid) return fail(c, DG_EINVAL, "reduction grid exceeds the scratch array");
+  double* sp = nullptr;
+  dg_status st = scratch_ptr(c, &sp);
+  if (st) return st;
+  double* part = sp;                      // 3 x G partials of the mass pass
+  double* pmax = sp + 3 * kScratchGrid;   // G partials of the maximum
+  double* res = sp + 4 * kScratchGrid;    // [0..2] the mass pass's sums, [3] the maximum
+  // every partial the second stages read is written by the first stages of this call
+  launch_gs_dots<double>(0, G, c->stream, (const double*)nullptr, c->ld, c->wJ, U, part, N);
+  hipLaunchKernelGGL(k_reduce, dim3(3), dim3(kRedThreads), 0, c->stream, part, G, res);
+  hipLaunchKernelGGL(k_maxabs_ratio, dim3(G), dim3(kRedThreads), 0, c->stream, U + (size_t)c->D * c->ld, U, pmax, N);
+  hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(kRedThreads), 0, c->stream, pmax, G, res + 3);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(mass, res + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(max_w, res + 3, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
   return DG_OK;
 }
 
