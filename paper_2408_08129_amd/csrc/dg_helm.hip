@@ -63,12 +63,17 @@ __device__ __forceinline__ int offs(int k, int q, int a) {
 
 // FP32 up to degree 4: the divergence fits 5 waves per SIMD (<= 96 VGPRs) and the gradient 6
 // (<= 80) without spills; the FP64 forms are limited by LDS (divergence) or would spill.
-template <int D, int NP, class T, bool DIV, class A, bool HH = false>
+// SPLIT (with DIV and HH, a.h = h - hbar): the enthalpy-split energy flux in one pass,
+// out = C((h - hbar) qv) + hbar C(qv) + adiv M (d hbar/dz) qv_z (+ penalty and mass terms): qv and
+// h - hbar are exchanged separately, and a second accumulator carries C(qv).
+template <int D, int NP, class T, bool DIV, class A, bool HH = false, bool SPLIT = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NP <= 5 ? (DIV ? (HH ? 1 : 5) : 6) : 1))) k_col(const A a, const MeshDev m) {
+  static_assert(!SPLIT || (DIV && HH), "the split form is a divergence with the h multiplier");
   using C = Col<D, NP>;
   constexpr int NC = C::NC, NL = C::NL, NF = C::NF, CPB = C::CPB, NHC = C::NHC;
   constexpr TabLayout TL{NP};
-  constexpr int NX = DIV ? D : 1;  // exchanged fields: grad p; div w_0 .. w_{d-2}, p
+  constexpr int NX = DIV ? (SPLIT ? D + 1 : D) : 1;  // exchanged fields: grad p; div w_0 .. w_{d-2}, p
+                                                     // (split: qv_0 .. qv_{d-2}, p, h - hbar)
   constexpr int NH = D - 1;        // horizontal axes
 
   __shared__ T sTab[TL.size()];
@@ -76,6 +81,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
   __shared__ T sFc[CPB][NC];               // e (1 - h/H) per column
   __shared__ T sHf[CPB][NH][2][NHC];       // e (1 - h/H) at the x / y face samples
   __shared__ T sPhi[CPB][2 * NH][NC];      // fluxes on the x / y faces
+  __shared__ T sPhi2[SPLIT ? CPB : 1][SPLIT ? 2 * NH : 1][SPLIT ? NC : 1];  // split: those of C(qv)
 
   const int tid = threadIdx.x;
   const bool lane = tid < C::NTA;
@@ -104,10 +110,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
   const bool active = lane && pos < m.ncell;
   const unsigned base = (unsigned)cell * NL + c;
   T pv[NP];            // grad: p; div: p (penalty / mass)
-  T wv[D][NP];         // div: h qv
+  T wv[D][NP];         // div: h qv (split: qv)
+  T hv[SPLIT ? NP : 1];  // split: h - hbar
 #pragma unroll
   for (int z = 0; z < NP; ++z) {
-    if constexpr (DIV) {
+    if constexpr (SPLIT) {
+      const unsigned idx = base + NC * z;
+#pragma unroll
+      for (int l = 0; l < D; ++l) wv[l][z] = a.qv[l * N + idx];
+      hv[z] = a.h[idx];
+      pv[z] = a.p ? a.p[idx] : T(0);
+    } else if constexpr (DIV) {
       T w[D];
       div_in<D, T, HH>(a, N, base + NC * z, (1 << D) - 1, w, pv[z]);
 #pragma unroll
@@ -118,11 +131,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
   }
   // neighbour traces at this thread's point of every face (tn[f][0..D-1] = w, tn[f][D] = p)
   T tn[NF][D + 1];
+  T tn2[SPLIT ? NF : 1][SPLIT ? D : 1];  // split: traces of qv
 #pragma unroll
   for (int f = 0; f < NF; ++f) {
     const int k = f >> 1, s = f & 1;
 #pragma unroll
     for (int g = 0; g <= D; ++g) tn[f][g] = 0;
+    if constexpr (SPLIT) {
+#pragma unroll
+      for (int g = 0; g < D; ++g) tn2[f][g] = 0;
+    }
     if (kind[f] != kConf) continue;
     const unsigned nbase = (unsigned)nb[f] * NL;
     const int mask = k == D - 1 ? (1 << D) - 1 : (1 << k);
@@ -135,6 +153,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         if constexpr (HH) {
           T hl[NP];
           load_line<NP>(a.h + idx, hl);
+          if constexpr (SPLIT) {
+#pragma unroll
+            for (int q = 0; q < NP; ++q) tn2[f][0] += gtab[TL.lb() + (1 - s) * NP + q] * wl[q];
+          }
 #pragma unroll
           for (int q = 0; q < NP; ++q) wl[q] *= hl[q];
         }
@@ -157,7 +179,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     for (int q = 0; q < NP; ++q) {
       const T lq = gtab[TL.lb() + (1 - s) * NP + q];
       const unsigned idx = nbase + offs<D, NP>(k, q, c);
-      if constexpr (DIV) {
+      if constexpr (SPLIT) {
+        const T hh = a.h[idx];
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+          if ((mask >> l) & 1) {
+            const T qq = a.qv[l * N + idx];
+            tn2[f][l] += lq * qq;
+            tn[f][l] += lq * (hh * qq);
+          }
+        }
+        tn[f][D] += lq * (a.p ? a.p[idx] : T(0));
+      } else if constexpr (DIV) {
         T w[D], p;
         div_in<D, T, HH>(a, N, idx, mask, w, p);
 #pragma unroll
@@ -214,6 +247,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 #pragma unroll
     for (int g = 0; g <= D; ++g)
       if (DIV || g == D) pin(tn[f][g]);
+  if constexpr (SPLIT) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int g = 0; g < D; ++g) pin(tn2[f][g]);
+  }
   if (lane) {
     sFc[lc][c] = fcol;
 #pragma unroll
@@ -222,6 +261,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 #pragma unroll
         for (int l = 0; l < D - 1; ++l) sX[lc][l][c + NC * z] = wv[l][z];
         sX[lc][D - 1][c + NC * z] = pv[z];
+        if constexpr (SPLIT) sX[lc][SPLIT ? D : 0][c + NC * z] = hv[z];
       } else {
         sX[lc][0][c + NC * z] = pv[z];
       }
@@ -239,34 +279,54 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
   const T* Wtu = gtab + TL.w();
   constexpr int NO = DIV ? 1 : D;
   T acc[NO][NP];
+  T acc2[SPLIT ? NP : 1];  // split: C(qv)
 #pragma unroll
   for (int o = 0; o < NO; ++o)
 #pragma unroll
     for (int z = 0; z < NP; ++z) acc[o][z] = 0;
+  if constexpr (SPLIT) {
+#pragma unroll
+    for (int z = 0; z < NP; ++z) acc2[z] = 0;
+  }
 
   // ---------------------------------------------------------------- horizontal contractions
   // Gam[0][0] = b f (3D) / f (2D) and Gam[1][1] = a f depend on the column only.
   const T g00 = D == 3 ? hb : T(1);
 #pragma unroll
   for (int z = 0; z < NP; ++z) {
-    T sx = 0;
+    T sx = 0, sx2 = 0;
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
       const int col = q + NP * i1;
-      sx += Dt[i0 * NP + q] * (sFc[lc][col] * sX[lc][0][col + NC * z]);
+      if constexpr (SPLIT) {
+        const T fq = sFc[lc][col] * sX[lc][0][col + NC * z];
+        sx += Dt[i0 * NP + q] * (sX[lc][SPLIT ? D : 0][col + NC * z] * fq);
+        sx2 += Dt[i0 * NP + q] * fq;
+      } else {
+        sx += Dt[i0 * NP + q] * (sFc[lc][col] * sX[lc][0][col + NC * z]);
+      }
     }
     if constexpr (DIV) acc[0][z] += -a.adiv * g00 * sx;
     else acc[0][z] += -g00 * sx;
+    if constexpr (SPLIT) acc2[z] += -a.adiv * g00 * sx2;
     if constexpr (D == 3) {
-      T sy = 0;
+      T sy = 0, sy2 = 0;
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
         const int col = i0 + NP * q;
-        sy += Dt[i1 * NP + q] * (sFc[lc][col] * sX[lc][DIV ? 1 : 0][col + NC * z]);
+        if constexpr (SPLIT) {
+          const T fq = sFc[lc][col] * sX[lc][1][col + NC * z];
+          sy += Dt[i1 * NP + q] * (sX[lc][SPLIT ? D : 0][col + NC * z] * fq);
+          sy2 += Dt[i1 * NP + q] * fq;
+        } else {
+          sy += Dt[i1 * NP + q] * (sFc[lc][col] * sX[lc][DIV ? 1 : 0][col + NC * z]);
+        }
       }
       if constexpr (DIV) acc[0][z] += -a.adiv * ha * sy;
       else acc[1][z] += -ha * sy;
+      if constexpr (SPLIT) acc2[z] += -a.adiv * ha * sy2;
     }
+    if constexpr (SPLIT) pin(acc2[z]);
 #pragma unroll
     for (int o = 0; o < NO; ++o) pin(acc[o][z]);
   }
@@ -274,6 +334,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
   // vertical row of Gam: 3D (-a b h_x om, -a b h_y om, a b), 2D (-a h_x om, a), om = 1 - zeta/H
   const T gzz = D == 3 ? ha * hb : ha;
   T gvz[NP];  // per node: the vertical flux components before the contraction
+  T gvz2[SPLIT ? NP : 1];
 #pragma unroll
   for (int q = 0; q < NP; ++q) {
     const T zeta = dxz * ((T)iz + T(0.5) * (T(1) + xi[q]));
@@ -281,7 +342,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     if constexpr (DIV) {
       T gw = gzz * wv[D - 1][q] - gzz * (hx * om) * wv[0][q];
       if constexpr (D == 3) gw -= gzz * (hy * om) * wv[1][q];
-      gvz[q] = -a.adiv * gw;
+      if constexpr (SPLIT) {
+        gvz2[q] = -a.adiv * gw;
+        gvz[q] = -a.adiv * (hv[q] * gw);
+      } else {
+        gvz[q] = -a.adiv * gw;
+      }
     } else {
       gvz[q] = om;  // the slope terms are formed below per component
     }
@@ -293,6 +359,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 #pragma unroll
       for (int q = 0; q < NP; ++q) s += Dtu[z * NP + q] * gvz[q];
       acc[0][z] += s;
+      if constexpr (SPLIT) {
+        T s2 = 0;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) s2 += Dtu[z * NP + q] * gvz2[q];
+        acc2[z] += s2;
+        pin(acc2[z]);
+      }
     } else {
       T s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
@@ -318,12 +391,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
   for (int s = 0; s < 2; ++s) {
     const int f = 2 * (D - 1) + s;
     T tm[D + 1];
+    T tm2[SPLIT ? D : 1];
 #pragma unroll
     for (int g = 0; g <= D; ++g) tm[g] = 0;
+    if constexpr (SPLIT) {
+#pragma unroll
+      for (int g = 0; g < D; ++g) tm2[g] = 0;
+    }
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
       const T lq = Lbu[s * NP + q];
-      if constexpr (DIV) {
+      if constexpr (SPLIT) {
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+          tm2[l] += lq * wv[l][q];
+          tm[l] += lq * (hv[q] * wv[l][q]);
+        }
+      } else if constexpr (DIV) {
 #pragma unroll
         for (int l = 0; l < D; ++l) tm[l] += lq * wv[l][q];
       }
@@ -349,6 +433,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
           const T lf = lam_own > lam_nb[f] ? lam_own : lam_nb[f];
           v += a.apen * (lf * sqrt(nn) * (tm[D] - tn[f][D]));
         }
+        if constexpr (SPLIT) {
+          T wm2 = 0, wn2 = 0;
+#pragma unroll
+          for (int l = 0; l < D; ++l) { wm2 += Nv[l] * tm2[l]; wn2 += Nv[l] * tn2[f][l]; }
+          const T wh2 = s ? T(0.5) * (wm2 + wn2) : T(0.5) * (wn2 + wm2);
+          const T v2 = a.adiv * sign * wh2;
+#pragma unroll
+          for (int z = 0; z < NP; ++z) acc2[z] += Lbwu[s * NP + z] * v2;
+        }
       }
 #pragma unroll
       for (int z = 0; z < NP; ++z) acc[0][z] += Lbwu[s * NP + z] * v;
@@ -368,6 +461,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
   for (int o = 0; o < NO; ++o)
 #pragma unroll
     for (int z = 0; z < NP; ++z) pin(acc[o][z]);
+  if constexpr (SPLIT) {
+#pragma unroll
+    for (int z = 0; z < NP; ++z) pin(acc2[z]);
+  }
 
   // ---------------------------------------------------------------- x / y faces: flux at point c
 #pragma unroll
@@ -377,12 +474,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const int f = 2 * k + s;
-      T tmw = 0, tmp = 0;
+      T tmw = 0, tmp = 0, tmw2 = 0;
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
         const int node = offs<D, NP>(k, q, c);
         const T lq = Lbu[s * NP + q];
-        if constexpr (DIV) {
+        if constexpr (SPLIT) {
+          const T qk = sX[lc][k][node];
+          tmw2 += lq * qk;
+          tmw += lq * (sX[lc][SPLIT ? D : 0][node] * qk);
+          tmp += lq * sX[lc][D - 1][node];
+        } else if constexpr (DIV) {
           tmw += lq * sX[lc][k][node];
           tmp += lq * sX[lc][D - 1][node];
         } else {
@@ -403,6 +505,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
             const T lf = lam_own > lam_nb[f] ? lam_own : lam_nb[f];
             phi += a.apen * (lf * sqrt(Nk * Nk) * (tmp - tn[f][D]));
           }
+        }
+        if constexpr (SPLIT) {
+          T phi2 = 0;
+          if (conf) {
+            const T wm2 = Nk * tmw2, wn2 = Nk * tn2[f][k];
+            const T wh2 = s ? T(0.5) * (wm2 + wn2) : T(0.5) * (wn2 + wm2);
+            phi2 = a.adiv * sign * wh2;
+          }
+          if (lane) sPhi2[lc][f][c] = phi2;
         }
       } else {
         T ph = kind[f] == kWall ? tmp : T(0);
@@ -426,6 +537,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         // face point of node (i0, i1, z) on an x face: (i1, z); on a y face: (i0, z)
         const int ap = D == 3 ? (k == 0 ? i1 : i0) + NP * z : z;
         acc[DIV ? 0 : k][z] += lw * sPhi[lc][2 * k + s][ap];
+        if constexpr (SPLIT) acc2[z] += lw * sPhi2[lc][2 * k + s][ap];
       }
     }
   }
@@ -438,8 +550,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 #pragma unroll
     for (int z = 0; z < NP; ++z) {
       const unsigned idx = base + NC * z;
-      if (a.weak) a.out[idx] = (wc * Wtu[z]) * (acc[0][z] + a.amass * J * pv[z]);
-      else a.out[idx] = acc[0][z] / J;
+      if constexpr (SPLIT) {
+        // + hbar C(qv) + adiv M (d hbar/dz) qv_z
+        const T hbz = a.hb[idx], dhz = a.dhb[idx];
+        if (a.weak) {
+          a.out[idx] = (wc * Wtu[z]) * (acc[0][z] + hbz * acc2[z] + a.adiv * J * dhz * wv[D - 1][z] + a.amass * J * pv[z]);
+        } else {
+          a.out[idx] = (acc[0][z] + hbz * acc2[z]) / J + a.adiv * dhz * wv[D - 1][z];
+        }
+      } else {
+        if (a.weak) a.out[idx] = (wc * Wtu[z]) * (acc[0][z] + a.amass * J * pv[z]);
+        else a.out[idx] = acc[0][z] / J;
+      }
     }
   } else {
     const T iJ0 = T(1) / J;
@@ -454,12 +576,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
   }
 }
 
-template <int D, int NP, class T, bool DIV, class A, bool HH = false>
+template <int D, int NP, class T, bool DIV, class A, bool HH = false, bool SPLIT = false>
 int run_col(const A& a, const MeshDev& m, hipStream_t s) {
   using C = Col<D, NP>;
   if (m.ncell <= 0) return 0;
   const int grid = (m.ncell + C::CPB - 1) / C::CPB;
-  hipLaunchKernelGGL((k_col<D, NP, T, DIV, A, HH>), dim3(grid), dim3(C::NT), 0, s, a, m);
+  hipLaunchKernelGGL((k_col<D, NP, T, DIV, A, HH, SPLIT>), dim3(grid), dim3(C::NT), 0, s, a, m);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -965,12 +1087,12 @@ int grad_col(const MeshDev& m, int degree, const GradArgs<T>& a, hipStream_t s) 
     DG_COL_DISPATCH(return (run_col<3, NP, T, false>(a, m, s)));
   }
 }
-template <class T, bool HH = false>
+template <class T, bool HH = false, bool SPLIT = false>
 int div_col(const MeshDev& m, int degree, const DivArgs<T>& a, hipStream_t s) {
   if (m.dim == 2) {
-    DG_COL_DISPATCH(return (run_col<2, NP, T, true, DivArgs<T>, HH>(a, m, s)));
+    DG_COL_DISPATCH(return (run_col<2, NP, T, true, DivArgs<T>, HH, SPLIT>(a, m, s)));
   } else {
-    DG_COL_DISPATCH(return (run_col<3, NP, T, true, DivArgs<T>, HH>(a, m, s)));
+    DG_COL_DISPATCH(return (run_col<3, NP, T, true, DivArgs<T>, HH, SPLIT>(a, m, s)));
   }
 }
 
@@ -1021,6 +1143,33 @@ int launch_div64(const MeshDev& m, int degree, const DivArgs<double>& a, hipStre
   if (r == 0) r = launch_div_hang64(m, degree, a, s);
   return r;
 }
+// The enthalpy-split energy flux in one column pass (a.h = h - hbar, a.hb, a.dhb set), then the
+// 2:1 face terms of C((h - hbar) qv) with the penalty, and of C(qv) multiplied by hbar at the node.
+template <class T>
+int div_split(const MeshDev& m, int degree, const DivArgs<T>& a, hipStream_t s,
+              int (*hang)(const MeshDev&, int, const DivArgs<T>&, hipStream_t)) {
+  if (a.dinv || !a.h || !a.hb || !a.dhb) return -3;
+  int r = div_col<T, true, true>(m, degree, a, s);
+  if (r) return r;
+  r = hang(m, degree, a, s);
+  if (r) return r;
+  DivArgs<T> a2 = a;
+  a2.h = nullptr;
+  a2.p = nullptr;
+  a2.apen = T(0);
+  a2.amass = T(0);
+  a2.hb = nullptr;
+  a2.dhb = nullptr;
+  a2.omul = a.hb;
+  return hang(m, degree, a2, s);
+}
+int launch_div_split64(const MeshDev& m, int degree, const DivArgs<double>& a, hipStream_t s) {
+  return div_split<double>(m, degree, a, s, launch_div_hang64);
+}
+int launch_div_split32(const MeshDev& m, int degree, const DivArgs<float>& a, hipStream_t s) {
+  return div_split<float>(m, degree, a, s, launch_div_hang32);
+}
+
 int launch_grad32(const MeshDev& m, int degree, const GradArgs<float>& a, hipStream_t s) {
   if (a.dinv || a.z) return launch_grad_cells32(m, degree, a, nullptr, m.ncell, s);
   int r = grad_col<float>(m, degree, a, s);

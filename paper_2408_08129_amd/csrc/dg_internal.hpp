@@ -106,6 +106,12 @@ struct DivArgs {
   T adiv, apen, amass;
   int weak;
   T* out;
+  // enthalpy split in one pass (column kernel, h = h - hbar): out also receives
+  // hbar C(qv) + adiv M (d hbar/dz) qv_z, with hbar and its height derivative at the nodes
+  const T* hb;
+  const T* dhb;
+  // faces-only 2:1 pass: multiplier of the added face terms per node (may be null: 1)
+  const T* omul;
 };
 
 // Cell-wise fast-diagonalisation preconditioner: z = P^{-1} (scale v) with, per cell,
@@ -138,6 +144,10 @@ int launch_div64(const MeshDev& m, int degree, const DivArgs<double>& a, hipStre
 int launch_grad32(const MeshDev& m, int degree, const GradArgs<float>& a, hipStream_t s);
 int launch_div32(const MeshDev& m, int degree, const DivArgs<float>& a, hipStream_t s);
 int launch_fdm64(const MeshDev& m, int degree, const FdmArgs<double>& a, hipStream_t s);
+// the enthalpy-split energy flux in one column pass plus the 2:1 face terms (a.h = h - hbar,
+// a.hb = hbar, a.dhb = d hbar / dz)
+int launch_div_split64(const MeshDev& m, int degree, const DivArgs<double>& a, hipStream_t s);
+int launch_div_split32(const MeshDev& m, int degree, const DivArgs<float>& a, hipStream_t s);
 // explicit residual with its flux integrals over-integrated at m.nq points per direction (all
 // cells, general faces); returns -6 for an unsupported (degree, nq)
 int launch_explicit_oi(const MeshDev& m, int degree, const double* U, double* R, hipStream_t s);

@@ -201,8 +201,8 @@ struct OpDiv {
     else a.out[idx] = acc[0] / J;
   }
   __device__ __forceinline__ void finalize_add(unsigned idx, const T* acc, T w, T J) const {
-    if (a.weak) a.out[idx] += w * acc[0];
-    else a.out[idx] += acc[0] / J;
+    const T v = a.weak ? w * acc[0] : acc[0] / J;
+    a.out[idx] += a.omul ? a.omul[idx] * v : v;
   }
   __device__ __forceinline__ T lam(int cell) const { return a.lam ? a.lam[cell] : T(0); }
 };

@@ -525,16 +525,6 @@ __global__ void k_hbar(const double* __restrict__ pbar, const double* __restrict
 
 // Enthalpy split: out += hbar * s2 + adiv (w J if weak) (d hbar/dz) q_z, s2 = adiv C(q) (weak form,
 // or with M^-1 applied when not weak).
-template <class T>
-__global__ void k_split_add(T* __restrict__ out, const T* __restrict__ s2, const T* __restrict__ hb,
-                            const T* __restrict__ dhb, const T* __restrict__ qz, double adiv, int weak,
-                            const double* __restrict__ wJ, long N) {
-  GRID_LOOP(e, N) {
-    const double m = weak ? wJ[e] : 1.0;
-    out[e] = (T)((double)out[e] + (double)hb[e] * (double)s2[e] + adiv * m * (double)dhb[e] * (double)qz[e]);
-  }
-}
-
 template <int D>
 __global__ void k_backsub(const double* __restrict__ mp, const double* __restrict__ q, double dta,
                           long N, long ld, double* __restrict__ Us) {
@@ -1089,9 +1079,9 @@ template <> struct PrecBuf<double> {
   static double* hp(dg_ctx* c) { return c->hp; }
   static double* hb(dg_ctx* c) { return c->hb; }
   static double* dhb(dg_ctx* c) { return c->dhb; }
-  static double* s2(dg_ctx* c) { return c->u; }
   static int grad(const MeshDev& m, int deg, const GradArgs<double>& a, hipStream_t s) { return launch_grad64(m, deg, a, s); }
   static int div(const MeshDev& m, int deg, const DivArgs<double>& a, hipStream_t s) { return launch_div64(m, deg, a, s); }
+  static int div_split(const MeshDev& m, int deg, const DivArgs<double>& a, hipStream_t s) { return launch_div_split64(m, deg, a, s); }
   static int fdm(const MeshDev& m, int deg, const FdmArgs<double>& a, hipStream_t s) { return launch_fdm64(m, deg, a, s); }
 };
 template <> struct PrecBuf<float> {
@@ -1103,30 +1093,24 @@ template <> struct PrecBuf<float> {
   static float* hp(dg_ctx* c) { return c->hp32; }
   static float* hb(dg_ctx* c) { return c->hb32; }
   static float* dhb(dg_ctx* c) { return c->dhb32; }
-  static float* s2(dg_ctx* c) { return c->u32; }
   static int grad(const MeshDev& m, int deg, const GradArgs<float>& a, hipStream_t s) { return launch_grad32(m, deg, a, s); }
   static int div(const MeshDev& m, int deg, const DivArgs<float>& a, hipStream_t s) { return launch_div32(m, deg, a, s); }
+  static int div_split(const MeshDev& m, int deg, const DivArgs<float>& a, hipStream_t s) { return launch_div_split32(m, deg, a, s); }
   static int fdm(const MeshDev& m, int deg, const FdmArgs<float>& a, hipStream_t s) { return launch_fdm32(m, deg, a, s); }
 };
 
 // Weak divergence of the implicit energy flux h qv with the penalty / mass terms of a (a.h = h):
-// plain C(h qv), or with the enthalpy split C((h - hbar) qv) + hbar C(qv) + M (d hbar/dz) qv_z.
+// plain C(h qv), or with the enthalpy split C((h - hbar) qv) + hbar C(qv) + M (d hbar/dz) qv_z,
+// the latter in one column pass.
 template <class T>
 int energy_div(dg_ctx* c, const DivArgs<T>& a) {
   using PB = PrecBuf<T>;
   if (!c->opt.enthalpy_split) return PB::div(c->md, c->degree, a, c->stream);
   DivArgs<T> a1 = a;
   a1.h = PB::hp(c);
-  int r = PB::div(c->md, c->degree, a1, c->stream);
-  if (r) return r;
-  // qv stands in for the (unused: no penalty, no mass) scalar so that the column kernel runs
-  DivArgs<T> a2{a.qv, nullptr, a.qv, nullptr, T(1), a.lam, a.adiv, T(0), T(0), a.weak, PB::s2(c)};
-  r = PB::div(c->md, c->degree, a2, c->stream);
-  if (r) return r;
-  hipLaunchKernelGGL((k_split_add<T>), pw_grid(c->N), dim3(256), 0, c->stream, a.out, (const T*)PB::s2(c),
-                     (const T*)PB::hb(c), (const T*)PB::dhb(c), a.qv + (size_t)(c->D - 1) * c->ld,
-                     (double)a.adiv, a.weak, (const double*)c->wJ, c->N);
-  return hipGetLastError() == hipSuccess ? 0 : -3;
+  a1.hb = PB::hb(c);
+  a1.dhb = PB::dhb(c);
+  return PB::div_split(c->md, c->degree, a1, c->stream);
 }
 
 // h - hbar for the enthalpy split, after h (and h32) changed
