@@ -82,13 +82,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
   __shared__ T sHf[CPB][NH][2][NHC];       // e (1 - h/H) at the x / y face samples
   __shared__ T sPhi[CPB][2 * NH][NC];      // fluxes on the x / y faces
   __shared__ T sPhi2[SPLIT ? CPB : 1][SPLIT ? 2 * NH : 1][SPLIT ? NC : 1];  // split: those of C(qv)
+  // gradient: the workgroup's cells are pieces of vertical runs, and a cell passes its p traces on
+  // the bottom / top faces to the run neighbour in the same workgroup through LDS; the divergence
+  // passes keep the Morton order and gather (the exchange cost them registers, the run order
+  // locality)
+  constexpr bool XZ = !DIV;
+  __shared__ T sZ[XZ ? CPB : 1][2][XZ ? NC : 1];
 
   const int tid = threadIdx.x;
   const bool lane = tid < C::NTA;
   const int lc = lane ? tid / NC : CPB - 1;
   const int c = tid % NC;
-  const int pos = xcd_block(blockIdx.x, gridDim.x) * CPB + lc;
-  const int cell = lane && pos < m.ncell ? pos : 0;
+  const int slot = xcd_block(blockIdx.x, gridDim.x) * CPB + lc;
+  int rcell = lane && slot < m.ncell ? slot : -1;
+  if constexpr (XZ) rcell = lane ? m.runs[slot] : -1;  // see MeshDev::runs
+  const int cell = rcell >= 0 ? rcell : 0;
+  const int rflag = (XZ && rcell >= 0) ? m.rflag[slot] : 0;
   const unsigned N = (unsigned)m.N;
   const int i0 = c % NP;
   const int i1 = D == 3 ? c / NP : 0;
@@ -107,7 +116,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     kind[f] = m.fkind[cell * NF + f];
     nb[f] = m.fnbr[cell * NF + f].x;
   }
-  const bool active = lane && pos < m.ncell;
+  const bool active = rcell >= 0;
   const unsigned base = (unsigned)cell * NL + c;
   T pv[NP];            // grad: p; div: p (penalty / mass)
   T wv[D][NP];         // div: h qv (split: qv)
@@ -142,6 +151,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
       for (int g = 0; g < D; ++g) tn2[f][g] = 0;
     }
     if (kind[f] != kConf) continue;
+    if (k == D - 1 && ((rflag >> s) & 1)) continue;  // the neighbour's trace comes through LDS
     const unsigned nbase = (unsigned)nb[f] * NL;
     const int mask = k == D - 1 ? (1 << D) - 1 : (1 << k);
     if (k == 0) {
@@ -265,6 +275,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
       } else {
         sX[lc][0][c + NC * z] = pv[z];
       }
+    }
+    // own p traces on the bottom and top faces for a run neighbour in this workgroup
+    if (XZ && (rflag & 3)) {
+      const T* lb0 = gtab + TL.lb();
+      const T* lb1 = lb0 + NP;
+      T tp0 = 0, tp1 = 0;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) { tp0 += lb0[q] * pv[q]; tp1 += lb1[q] * pv[q]; }
+      sZ[XZ ? lc : 0][0][XZ ? c : 0] = tp0;
+      sZ[XZ ? lc : 0][1][XZ ? c : 0] = tp1;
     }
   }
   __syncthreads();
@@ -421,6 +441,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     Nv[D - 1] = gzz;
     const T sign = s ? T(1) : T(-1);
     const bool conf = kind[f] == kConf;
+    // gradient: the run neighbour across this face in the same workgroup wrote its trace to LDS
+    const bool inrun = (rflag >> s) & 1;
+    const int ln = s ? lc + 1 : lc - 1;
     if constexpr (DIV) {
       T v = 0;
       if (conf) {
@@ -447,7 +470,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
       for (int z = 0; z < NP; ++z) acc[0][z] += Lbwu[s * NP + z] * v;
     } else {
       T ph = kind[f] == kWall ? tm[D] : T(0);
-      if (conf) ph = s ? T(0.5) * (tm[D] + tn[f][D]) : T(0.5) * (tn[f][D] + tm[D]);
+      const T pn = inrun ? sZ[XZ ? ln : 0][1 - s][XZ ? c : 0] : tn[f][D];
+      if (conf) ph = s ? T(0.5) * (tm[D] + pn) : T(0.5) * (pn + tm[D]);
 #pragma unroll
       for (int l = 0; l < D; ++l) {
         const T phi = sign * ph * Nv[l];
@@ -580,7 +604,11 @@ template <int D, int NP, class T, bool DIV, class A, bool HH = false, bool SPLIT
 int run_col(const A& a, const MeshDev& m, hipStream_t s) {
   using C = Col<D, NP>;
   if (m.ncell <= 0) return 0;
-  const int grid = (m.ncell + C::CPB - 1) / C::CPB;
+  int grid = (m.ncell + C::CPB - 1) / C::CPB;
+  if (!DIV) {  // the gradient walks the vertical runs
+    if (m.nrwg * C::CPB < m.ncell) return -3;  // the run lists were built for this layout
+    grid = m.nrwg;
+  }
   hipLaunchKernelGGL((k_col<D, NP, T, DIV, A, HH, SPLIT>), dim3(grid), dim3(C::NT), 0, s, a, m);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }

@@ -47,6 +47,12 @@ struct MeshDev {
   int nreg;
   const int* irr;
   int nirr;
+  // workgroup cell lists of the gradient column kernel: vertical runs of cells joined by
+  // conforming bottom / top faces, packed CPB cells per workgroup (-1 pads the last one); flag
+  // bit 0 (1): the bottom (top) neighbour is the previous (next) cell of the same workgroup
+  const int* runs;
+  const int* rflag;
+  int nrwg;
   // over-integration of the explicit flux: NQ Gauss points per direction and their tables
   // (OiLayout), or nq = 0
   const double* oitab;

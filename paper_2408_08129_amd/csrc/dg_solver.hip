@@ -809,6 +809,8 @@ struct dg_ctx {
   int* d_fkind = nullptr;
   int4* d_fnbr = nullptr;
   int* d_lists = nullptr;  // cells with conforming faces only, then cells with a 2:1 face
+  int* d_runs = nullptr;   // vertical runs for the gradient column kernel (cells, then flags)
+  int nrun_slots = 0;
   double* d_tab = nullptr;
   float* d_tabf = nullptr;
   double* d_oitab = nullptr;  // over-integration table (quad_extra > 0)
@@ -953,6 +955,48 @@ struct Plan {
   }
 };
 
+// Cells per workgroup of the Helmholtz column kernels, and the padded length of their run lists.
+int col_cpb(const dg_ctx* c) {
+  int nc = 1;
+  for (int a = 0; a < c->D - 1; ++a) nc *= c->degree + 1;
+  return 256 / nc;
+}
+long run_slots(const dg_ctx* c) {
+  const long cpb = col_cpb(c);
+  return (c->hm.ncell + cpb - 1) / cpb * cpb;
+}
+
+// Vertical runs for the gradient column kernel (Helmholtz pass 1): chains of cells joined by conforming bottom /
+// top faces, taken from bottom to top in the order of their lowest cell (Morton), concatenated and
+// cut into workgroups of cpb cells.  A cell's flag says whether its bottom (bit 0) or top (bit 1)
+// neighbour sits in the previous or next slot of the same workgroup, where the kernel reads that
+// neighbour's face trace from LDS instead of gathering its vertical line.
+void build_runs(const HostMesh& M, int D, int cpb, std::vector<int>& runs, std::vector<int>& flags) {
+  const int NF = 2 * D, fb = 2 * (D - 1), ft = fb + 1;
+  const long n = M.ncell;
+  std::vector<int> up(n, -1), down(n, -1);
+  for (long i = 0; i < n; ++i) {
+    if (M.fkind[i * NF + ft] == kConf) up[i] = M.fnbr[(i * NF + ft) * 4];
+    if (M.fkind[i * NF + fb] == kConf) down[i] = M.fnbr[(i * NF + fb) * 4];
+  }
+  runs.clear();
+  runs.reserve(n);
+  for (long i = 0; i < n; ++i) {
+    if (down[i] >= 0) continue;  // not the lowest cell of its chain
+    long steps = 0;
+    for (long j = i; j >= 0 && steps <= n; j = up[j], ++steps) runs.push_back((int)j);
+  }
+  const long slots = (n + cpb - 1) / cpb * cpb;
+  runs.resize(slots, -1);
+  flags.assign(slots, 0);
+  for (long k = 0; k < slots; ++k) {
+    const int cc = runs[k];
+    if (cc < 0) continue;
+    if (k % cpb != 0 && runs[k - 1] >= 0 && down[cc] == runs[k - 1]) flags[k] |= 1;
+    if ((k + 1) % cpb != 0 && k + 1 < slots && runs[k + 1] >= 0 && up[cc] == runs[k + 1]) flags[k] |= 2;
+  }
+}
+
 // Every device allocation of a context, in bytes; used by dg_setup and dg_footprint.
 void make_plan(dg_ctx* c, Plan& P) {
   const int D = c->D, F = c->F;
@@ -963,6 +1007,7 @@ void make_plan(dg_ctx* c, Plan& P) {
   P.add((void**)&c->d_cell, nc * sizeof(int4));
   P.add((void**)&c->d_fkind, nc * 2 * D * sizeof(int));
   P.add((void**)&c->d_lists, nc * sizeof(int));
+  P.add((void**)&c->d_runs, (size_t)2 * run_slots(c) * sizeof(int));
   P.add((void**)&c->d_fnbr, nc * 2 * D * sizeof(int4));
   P.add((void**)&c->d_tab, TL.size() * d8);
   P.add((void**)&c->d_tabf, TL.size() * f4);
@@ -1843,6 +1888,26 @@ dg_status dg_setup(const dg_case_desc* desc, int32_t degree, const dg_options* o
   }
   if (M.ncell > 0)
     SETUP_CHK(hipMemcpyAsync(c->d_lists, lists.data(), lists.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  std::vector<int> runs, rflags;
+  build_runs(M, c->D, col_cpb(c), runs, rflags);
+  if (runs.size() != (size_t)run_slots(c)) {
+    dg_destroy(c);
+    return fail(nullptr, DG_EINVAL, "vertical runs do not cover the mesh");
+  }
+  {
+    long seen = 0;
+    for (int v : runs) seen += v >= 0;
+    if (seen != M.ncell) {
+      dg_destroy(c);
+      return fail(nullptr, DG_EINVAL, "vertical runs do not cover every cell once");
+    }
+  }
+  c->nrun_slots = (int)runs.size();
+  if (!runs.empty()) {
+    SETUP_CHK(hipMemcpyAsync(c->d_runs, runs.data(), runs.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    SETUP_CHK(hipMemcpyAsync(c->d_runs + runs.size(), rflags.data(), rflags.size() * sizeof(int),
+                             hipMemcpyHostToDevice, s));
+  }
   SETUP_CHK(hipMemcpyAsync(c->d_fnbr, nbr.data(), nbr.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   SETUP_CHK(hipMemcpyAsync(c->d_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s));
   SETUP_CHK(hipMemcpyAsync(c->d_tabf, tabf.data(), tabf.size() * sizeof(float), hipMemcpyHostToDevice, s));
@@ -1858,6 +1923,9 @@ dg_status dg_setup(const dg_case_desc* desc, int32_t degree, const dg_options* o
   md.reg = c->d_lists;
   md.nreg = nreg;
   md.irr = c->d_lists + nreg;
+  md.runs = c->d_runs;
+  md.rflag = c->d_runs + c->nrun_slots;
+  md.nrwg = c->nrun_slots / col_cpb(c);
   md.nirr = M.ncell - nreg;
   md.tab = c->d_tab;
   md.tabf = c->d_tabf;
