@@ -207,6 +207,19 @@ def serving_leg(n=16, steps=5, max_cells=50000):
                                        "step_ms_p50", "step_ms_p99", "e2e_s_p50", "e2e_s_p99")}
         print("[bench] serving %s: %s" % (name, out[name]), file=sys.stderr, flush=True)
     out["gain_fp32_inner_vs_fp64"] = round(out["fp32_inner"]["dof_updates_per_s"] / out["fp64"]["dof_updates_per_s"], 3)
+    # throughput of the shared launches: every request present from the start, served together
+    # (up to 64 members in flight) and one at a time (a batch of one per round: the same per-member
+    # arithmetic, so the same bits and the same accuracy), FP64; admission, setup and release
+    # included in both
+    thr = {}
+    for name, act in (("served", 64), ("one_at_a_time", 1)):
+        r = serve.Server(max_active=act, precision=P.DG_FP64).run(reqs, realtime=False)
+        r.pop("members")
+        thr[name] = {k: r[k] for k in ("done", "failed", "rounds", "wall_s", "dof_updates_per_s",
+                                       "step_ms_p50", "step_ms_p99")}
+        print("[bench] serving fp64 %s, all requests present: %s" % (name, thr[name]), file=sys.stderr, flush=True)
+    thr["gain_served_vs_one_at_a_time"] = round(thr["served"]["dof_updates_per_s"] / thr["one_at_a_time"]["dof_updates_per_s"], 3)
+    out["fp64_all_present"] = thr
     return out
 
 

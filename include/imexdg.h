@@ -292,10 +292,19 @@ dg_status dg_apply_preconditioner(dg_ctx* ctx, double dt_a, const double* h_dev,
  * unchanged. */
 dg_status imex_rk2_step(dg_ctx* ctx, double* U_dev, double dt, dg_step_stats* stats);
 
-/* One step for each of n contexts (ensemble members of any sizes): each member runs on its own
- * context stream from its own host thread, so their kernels overlap on the device.  stats: array
- * of n or NULL (t_step_ms = time from the call to the member's completion); status: array of n or
- * NULL (per-member result).  Returns DG_OK or the first member error; a member that fails keeps its
+/* One step for each of n contexts (ensemble members of any mesh size; the serving form of the
+ * step that Section 3.2 sizes per node): members of one class (same dimension, degree, precision,
+ * preconditioner and energy-flux form) advance in lockstep and share every launch of the step.
+ * Each operator, Krylov and pointwise kernel takes a segment table: member k owns a contiguous
+ * range of the grid's workgroups, with its own arguments and mesh view, and keeps the grid shape
+ * of its own launch.  Each host round trip of the Krylov iteration fetches the reductions of all
+ * members at once.  Members keep their own iteration counts, restarts and failures.  A member's
+ * new state is the same bits alone (n = 1) and in any mix.  A class is cut into teams of at most
+ * 32 members, with up to 8 members per launch.  Each team runs on the stream of its first member,
+ * from a host thread of its own; work already queued on the other members' streams is waited
+ * for first, and the call returns when every team is done.  stats: array of n or NULL
+ * (t_step_ms = time from the call to the member's team completion); status: array of n or NULL
+ * (per-member result).  Returns DG_OK or the first member error; a member that fails keeps its
  * state, the others advance. */
 dg_status imex_rk2_step_batched(dg_ctx* const* ctxs, double* const* U_devs, const double* dts,
                                 int32_t n, dg_step_stats* stats, int32_t* status);

@@ -66,9 +66,13 @@ __device__ __forceinline__ int offs(int k, int q, int a) {
 // SPLIT (with DIV and HH, a.h = h - hbar): the enthalpy-split energy flux in one pass,
 // out = C((h - hbar) qv) + hbar C(qv) + adiv M (d hbar/dz) qv_z (+ penalty and mass terms): qv and
 // h - hbar are exchanged separately, and a second accumulator carries C(qv).
-template <int D, int NP, class T, bool DIV, class A, bool HH = false, bool SPLIT = false>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NP <= 5 ? (DIV ? (HH ? 1 : 5) : 6) : 1))) k_col(const A a, const MeshDev m) {
+// S: Direct<A> (one mesh) or Shared<A> (a shared launch over ensemble members).
+template <int D, int NP, class T, bool DIV, class A, bool HH = false, bool SPLIT = false, class S = Direct<A>>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NP <= 5 ? (DIV ? (HH ? 1 : 5) : 6) : 1))) k_col(const S src) {
   static_assert(!SPLIT || (DIV && HH), "the split form is a divergence with the h multiplier");
+  const int sg = src.seg();
+  const A& a = src.args(sg);
+  const MeshDev& m = src.mesh(sg);
   using C = Col<D, NP>;
   constexpr int NC = C::NC, NL = C::NL, NF = C::NF, CPB = C::CPB, NHC = C::NHC;
   constexpr TabLayout TL{NP};
@@ -93,7 +97,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
   const bool lane = tid < C::NTA;
   const int lc = lane ? tid / NC : CPB - 1;
   const int c = tid % NC;
-  const int slot = xcd_block(blockIdx.x, gridDim.x) * CPB + lc;
+  const int slot = xcd_block(src.blk(sg), src.nblk(sg)) * CPB + lc;
   int rcell = lane && slot < m.ncell ? slot : -1;
   if constexpr (XZ) rcell = lane ? m.runs[slot] : -1;  // see MeshDev::runs
   const int cell = rcell >= 0 ? rcell : 0;
@@ -609,7 +613,7 @@ int run_col(const A& a, const MeshDev& m, hipStream_t s) {
     if (m.nrwg * C::CPB < m.ncell) return -3;  // the run lists were built for this layout
     grid = m.nrwg;
   }
-  hipLaunchKernelGGL((k_col<D, NP, T, DIV, A, HH, SPLIT>), dim3(grid), dim3(C::NT), 0, s, a, m);
+  hipLaunchKernelGGL((k_col<D, NP, T, DIV, A, HH, SPLIT>), dim3(grid), dim3(C::NT), 0, s, Direct<A>{a, m});
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -618,9 +622,12 @@ int run_col(const A& a, const MeshDev& m, hipStream_t s) {
 // rho k u) with k = |u|^2 / 2, Rusanov fluxes with the advective speed, the slip-wall flux, and
 // the gravity work -rho g w.  Fields and 1/rho go through LDS for the x / y passes; the same
 // buffer then carries the x / y face fluxes.
-template <int D, int NP>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_col_exp(const double* __restrict__ U, double* __restrict__ R,
-                                                 const MeshDev m) {
+template <int D, int NP, class S = Direct<ExpArgs>>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_col_exp(const S src) {
+  const int sg = src.seg();
+  const MeshDev& m = src.mesh(sg);
+  const double* __restrict__ U = src.args(sg).U;
+  double* __restrict__ R = src.args(sg).R;
   using C = Col<D, NP>;
   using T = double;
   constexpr int NC = C::NC, NL = C::NL, NF = C::NF, CPB = C::CPB, NHC = C::NHC;
@@ -642,7 +649,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   const bool lane = tid < C::NTA;
   const int lc = lane ? tid / NC : CPB - 1;
   const int c = tid % NC;
-  const int pos = xcd_block(blockIdx.x, gridDim.x) * CPB + lc;
+  const int pos = xcd_block(src.blk(sg), src.nblk(sg)) * CPB + lc;
   const int cell = lane && pos < m.ncell ? pos : 0;
   const unsigned N = (unsigned)m.N;
   const int i0 = c % NP;
@@ -953,15 +960,18 @@ int run_col_exp(const double* U, double* R, const MeshDev& m, hipStream_t s) {
   using C = Col<D, NP>;
   if (m.ncell <= 0) return 0;
   const int grid = (m.ncell + C::CPB - 1) / C::CPB;
-  hipLaunchKernelGGL((k_col_exp<D, NP>), dim3(grid), dim3(C::NT), 0, s, U, R, m);
+  hipLaunchKernelGGL((k_col_exp<D, NP>), dim3(grid), dim3(C::NT), 0, s, Direct<ExpArgs>{ExpArgs{U, R}, m});
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
 // Cell-wise fast-diagonalisation preconditioner in the column layout:
 // z = (1/Jbar) (S x S x S) diag(1 / (1/(gamma-1) + sum_k alpha_k mu_{i_k})) (S x S x S)^T (scale v).
 // The vertical transforms stay in the thread's registers, the horizontal ones go through LDS.
-template <int D, int NP, class T>
-__global__ void __launch_bounds__(256) k_fdm_col(const FdmArgs<T> a, const MeshDev m) {
+template <int D, int NP, class T, class Src = Direct<FdmArgs<T>>>
+__global__ void __launch_bounds__(256) k_fdm_col(const Src src) {
+  const int sg = src.seg();
+  const FdmArgs<T>& a = src.args(sg);
+  const MeshDev& m = src.mesh(sg);
   using C = Col<D, NP>;
   constexpr int NC = C::NC, NL = C::NL, CPB = C::CPB;
   constexpr TabLayout TL{NP};
@@ -973,7 +983,7 @@ __global__ void __launch_bounds__(256) k_fdm_col(const FdmArgs<T> a, const MeshD
   const bool lane = tid < C::NTA;
   const int lc = lane ? tid / NC : CPB - 1;
   const int c = tid % NC;
-  const int cell0 = xcd_block(blockIdx.x, gridDim.x) * CPB;
+  const int cell0 = xcd_block(src.blk(sg), src.nblk(sg)) * CPB;
   const int cell = cell0 + lc;
   const bool active = lane && cell < m.ncell;
   const int cl = active ? cell : 0;
@@ -1093,7 +1103,7 @@ int run_fdm_col(const FdmArgs<T>& a, const MeshDev& m, hipStream_t s) {
   using C = Col<D, NP>;
   if (m.ncell <= 0) return 0;
   const int grid = (m.ncell + C::CPB - 1) / C::CPB;
-  hipLaunchKernelGGL((k_fdm_col<D, NP, T>), dim3(grid), dim3(C::NT), 0, s, a, m);
+  hipLaunchKernelGGL((k_fdm_col<D, NP, T>), dim3(grid), dim3(C::NT), 0, s, Direct<FdmArgs<T>>{a, m});
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -1196,6 +1206,161 @@ int launch_div_split64(const MeshDev& m, int degree, const DivArgs<double>& a, h
 }
 int launch_div_split32(const MeshDev& m, int degree, const DivArgs<float>& a, hipStream_t s) {
   return div_split<float>(m, degree, a, s, launch_div_hang32);
+}
+
+// ---------------------------------------------------------------- shared launches
+namespace {
+
+template <int D, int NP, class T, bool DIV, class A, bool HH = false, bool SPLIT = false>
+int run_col_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const A* a, hipStream_t s) {
+  using C = Col<D, NP>;
+  for (int k = 0; k < n; ++k)
+    if (!DIV && mh[k]->ncell > 0 && mh[k]->nrwg * C::CPB < mh[k]->ncell) return -3;
+  return seg_launch<A>(
+      n, md,
+      [&](int k) { return mh[k]->ncell <= 0 ? 0 : DIV ? (mh[k]->ncell + C::CPB - 1) / C::CPB : mh[k]->nrwg; },
+      [&](int k) { return a[k]; },
+      [&](const SegTab<A>& t, int g) {
+        hipLaunchKernelGGL((k_col<D, NP, T, DIV, A, HH, SPLIT, Shared<A>>), dim3(g), dim3(C::NT), 0, s, Shared<A>{t});
+        return hipGetLastError() == hipSuccess ? 0 : -3;
+      });
+}
+
+template <int D, int NP, class T>
+int run_fdm_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const FdmArgs<T>* a, hipStream_t s) {
+  using C = Col<D, NP>;
+  using A = FdmArgs<T>;
+  return seg_launch<A>(
+      n, md, [&](int k) { return (mh[k]->ncell + C::CPB - 1) / C::CPB; }, [&](int k) { return a[k]; },
+      [&](const SegTab<A>& t, int g) {
+        hipLaunchKernelGGL((k_fdm_col<D, NP, T, Shared<A>>), dim3(g), dim3(C::NT), 0, s, Shared<A>{t});
+        return hipGetLastError() == hipSuccess ? 0 : -3;
+      });
+}
+
+template <int D, int NP>
+int run_exp_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const ExpArgs* a, hipStream_t s) {
+  using C = Col<D, NP>;
+  return seg_launch<ExpArgs>(
+      n, md, [&](int k) { return (mh[k]->ncell + C::CPB - 1) / C::CPB; }, [&](int k) { return a[k]; },
+      [&](const SegTab<ExpArgs>& t, int g) {
+        hipLaunchKernelGGL((k_col_exp<D, NP, Shared<ExpArgs>>), dim3(g), dim3(C::NT), 0, s, Shared<ExpArgs>{t});
+        return hipGetLastError() == hipSuccess ? 0 : -3;
+      });
+}
+
+template <class T>
+int grad_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const GradArgs<T>* a, int degree,
+             hipStream_t s, int (*hang)(int, const MeshDev* const*, const MeshDev* const*, const GradArgs<T>*, int, hipStream_t)) {
+  if (n <= 0) return 0;
+  for (int k = 0; k < n; ++k)
+    if (a[k].dinv || a[k].z || mh[k]->dim != mh[0]->dim) return -6;
+  int r;
+  if (mh[0]->dim == 2) {
+    DG_COL_DISPATCH(r = (run_col_seg<2, NP, T, false>(n, mh, md, a, s)); break);
+  } else {
+    DG_COL_DISPATCH(r = (run_col_seg<3, NP, T, false>(n, mh, md, a, s)); break);
+  }
+  return r ? r : hang(n, mh, md, a, degree, s);
+}
+
+template <class T, bool HH, bool SPLIT>
+int div_col_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<T>* a, int degree,
+                hipStream_t s) {
+  if (mh[0]->dim == 2) {
+    DG_COL_DISPATCH(return (run_col_seg<2, NP, T, true, DivArgs<T>, HH, SPLIT>(n, mh, md, a, s)));
+  } else {
+    DG_COL_DISPATCH(return (run_col_seg<3, NP, T, true, DivArgs<T>, HH, SPLIT>(n, mh, md, a, s)));
+  }
+}
+
+template <class T>
+int div_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<T>* a, int degree,
+            hipStream_t s, int (*hang)(int, const MeshDev* const*, const MeshDev* const*, const DivArgs<T>*, int, hipStream_t)) {
+  if (n <= 0) return 0;
+  const bool hh = a[0].h != nullptr;
+  for (int k = 0; k < n; ++k)
+    if (a[k].dinv || (!a[k].h && !a[k].p) || (a[k].h != nullptr) != hh || mh[k]->dim != mh[0]->dim) return -6;
+  const int r = hh ? div_col_seg<T, true, false>(n, mh, md, a, degree, s)
+                   : div_col_seg<T, false, false>(n, mh, md, a, degree, s);
+  return r ? r : hang(n, mh, md, a, degree, s);
+}
+
+// the enthalpy-split form (see div_split) for every member
+template <class T>
+int div_split_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<T>* a, int degree,
+                  hipStream_t s, int (*hang)(int, const MeshDev* const*, const MeshDev* const*, const DivArgs<T>*, int, hipStream_t)) {
+  if (n <= 0) return 0;
+  if (n > 64) return -6;
+  for (int k = 0; k < n; ++k)
+    if (a[k].dinv || !a[k].h || !a[k].hb || !a[k].dhb || mh[k]->dim != mh[0]->dim) return -6;
+  int r = div_col_seg<T, true, true>(n, mh, md, a, degree, s);
+  if (r) return r;
+  r = hang(n, mh, md, a, degree, s);
+  if (r) return r;
+  DivArgs<T> a2[64];
+  for (int k = 0; k < n; ++k) {
+    a2[k] = a[k];
+    a2[k].h = nullptr;
+    a2[k].p = nullptr;
+    a2[k].apen = T(0);
+    a2[k].amass = T(0);
+    a2[k].hb = nullptr;
+    a2[k].dhb = nullptr;
+    a2[k].omul = a[k].hb;
+  }
+  return hang(n, mh, md, a2, degree, s);
+}
+
+template <class T>
+int fdm_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const FdmArgs<T>* a, int degree, hipStream_t s) {
+  if (n <= 0) return 0;
+  for (int k = 0; k < n; ++k)
+    if (mh[k]->dim != mh[0]->dim) return -6;
+  if (mh[0]->dim == 2) {
+    DG_COL_DISPATCH(return (run_fdm_seg<2, NP, T>(n, mh, md, a, s)));
+  } else {
+    DG_COL_DISPATCH(return (run_fdm_seg<3, NP, T>(n, mh, md, a, s)));
+  }
+}
+
+}  // namespace
+
+int launch_grad_seg64(int n, const MeshDev* const* mh, const MeshDev* const* md, const GradArgs<double>* a, int degree, hipStream_t s) {
+  return grad_seg<double>(n, mh, md, a, degree, s, launch_grad_hang_seg64);
+}
+int launch_grad_seg32(int n, const MeshDev* const* mh, const MeshDev* const* md, const GradArgs<float>* a, int degree, hipStream_t s) {
+  return grad_seg<float>(n, mh, md, a, degree, s, launch_grad_hang_seg32);
+}
+int launch_div_seg64(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<double>* a, int degree, hipStream_t s) {
+  return div_seg<double>(n, mh, md, a, degree, s, launch_div_hang_seg64);
+}
+int launch_div_seg32(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<float>* a, int degree, hipStream_t s) {
+  return div_seg<float>(n, mh, md, a, degree, s, launch_div_hang_seg32);
+}
+int launch_div_split_seg64(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<double>* a, int degree, hipStream_t s) {
+  return div_split_seg<double>(n, mh, md, a, degree, s, launch_div_hang_seg64);
+}
+int launch_div_split_seg32(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<float>* a, int degree, hipStream_t s) {
+  return div_split_seg<float>(n, mh, md, a, degree, s, launch_div_hang_seg32);
+}
+int launch_fdm_seg64(int n, const MeshDev* const* mh, const MeshDev* const* md, const FdmArgs<double>* a, int degree, hipStream_t s) {
+  return fdm_seg<double>(n, mh, md, a, degree, s);
+}
+int launch_fdm_seg32(int n, const MeshDev* const* mh, const MeshDev* const* md, const FdmArgs<float>* a, int degree, hipStream_t s) {
+  return fdm_seg<float>(n, mh, md, a, degree, s);
+}
+int launch_explicit_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const ExpArgs* a, int degree, hipStream_t s) {
+  if (n <= 0) return 0;
+  for (int k = 0; k < n; ++k)
+    if (mh[k]->dim != mh[0]->dim || mh[k]->nq > 0) return -6;
+  int r;
+  if (mh[0]->dim == 2) {
+    DG_COL_DISPATCH(r = (run_exp_seg<2, NP>(n, mh, md, a, s)); break);
+  } else {
+    DG_COL_DISPATCH(r = (run_exp_seg<3, NP>(n, mh, md, a, s)); break);
+  }
+  return r ? r : launch_explicit_hang_seg(n, mh, md, a, degree, s);
 }
 
 int launch_grad32(const MeshDev& m, int degree, const GradArgs<float>& a, hipStream_t s) {

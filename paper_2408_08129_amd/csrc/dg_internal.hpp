@@ -59,6 +59,80 @@ struct MeshDev {
   int nq;
 };
 
+// --------------------------------------------------------------- shared launches (segments)
+// A kernel launched for one mesh takes its arguments and mesh view by value (Direct).  A shared
+// launch over several ensemble members (Shared) takes a table: member k owns the workgroups
+// [b0[k], b0[k+1]) of the grid, its arguments a[k] and its mesh view, of which the table holds the
+// device copy (the view is too large to repeat per member in the kernel arguments).  Every member
+// keeps the grid shape of its own launch, so each member's results are the same bits whatever
+// else shares the launch.
+constexpr int kMaxSeg = 8;
+
+template <class A>
+struct SegTab {
+  int n;                       // members in this launch, 1..kMaxSeg
+  int b0[kMaxSeg + 1];         // first workgroup of each member; b0[n] = grid size
+  const MeshDev* m[kMaxSeg];   // device copies of the members' mesh views (may be null)
+  A a[kMaxSeg];
+};
+
+template <class A>
+struct Direct {
+  A a;
+  MeshDev m;
+  __device__ __forceinline__ int seg() const { return 0; }
+  __device__ __forceinline__ const A& args(int) const { return a; }
+  __device__ __forceinline__ const MeshDev& mesh(int) const { return m; }
+  __device__ __forceinline__ int blk(int) const { return blockIdx.x; }
+  __device__ __forceinline__ int nblk(int) const { return gridDim.x; }
+};
+
+template <class A>
+struct Shared {
+  SegTab<A> t;
+  // the member that owns this workgroup (uniform across the workgroup)
+  __device__ __forceinline__ int seg() const {
+    int k = 0;
+#pragma unroll
+    for (int i = 1; i < kMaxSeg; ++i) k += (i < t.n && (int)blockIdx.x >= t.b0[i]) ? 1 : 0;
+    return k;
+  }
+  __device__ __forceinline__ const A& args(int k) const { return t.a[k]; }
+  __device__ __forceinline__ const MeshDev& mesh(int k) const { return *t.m[k]; }
+  __device__ __forceinline__ int blk(int k) const { return (int)blockIdx.x - t.b0[k]; }
+  __device__ __forceinline__ int nblk(int k) const { return t.b0[k + 1] - t.b0[k]; }
+};
+
+// Host side of a shared launch: the members with work (blocks(k) > 0) in order, kMaxSeg per
+// launch; launch(table, grid) returns 0 or an error code.
+template <class A, class Blocks, class Args, class Launch>
+int seg_launch(int n, const MeshDev* const* md, Blocks blocks, Args args, Launch launch) {
+  SegTab<A> t{};
+  int g = 0;
+  auto flush = [&]() {
+    if (t.n == 0) return 0;
+    for (int i = t.n; i <= kMaxSeg; ++i) t.b0[i] = g;
+    const int r = launch(t, g);
+    t.n = 0;
+    g = 0;
+    return r;
+  };
+  for (int k = 0; k < n; ++k) {
+    const int nb = blocks(k);
+    if (nb <= 0) continue;
+    if (t.n == kMaxSeg) {
+      const int r = flush();
+      if (r) return r;
+    }
+    t.b0[t.n] = g;
+    t.m[t.n] = md ? md[k] : nullptr;
+    t.a[t.n] = args(k);
+    t.n++;
+    g += nb;
+  }
+  return flush();
+}
+
 // Offsets into the 1D table for NP = r + 1 points.
 struct TabLayout {
   int np;
@@ -120,6 +194,12 @@ struct DivArgs {
   const T* omul;
 };
 
+// Explicit residual R = F_E(U) ([F][N] each).
+struct ExpArgs {
+  const double* U;
+  double* R;
+};
+
 // Cell-wise fast-diagonalisation preconditioner: z = P^{-1} (scale v) with, per cell,
 // P = Jbar (S^-T (x) ...) [1/(gamma-1) + sum_k alpha_k mu] (S^-1 (x) ...); coef[cell] holds
 // (1/Jbar, alpha_0, alpha_1, alpha_2).
@@ -158,6 +238,27 @@ int launch_div_split32(const MeshDev& m, int degree, const DivArgs<float>& a, hi
 // cells, general faces); returns -6 for an unsupported (degree, nq)
 int launch_explicit_oi(const MeshDev& m, int degree, const double* U, double* R, hipStream_t s);
 int launch_fdm32(const MeshDev& m, int degree, const FdmArgs<float>& a, hipStream_t s);
+
+// Shared launches of the column operators over n members of one class (same dimension and degree):
+// mh[k] the host copy of member k's mesh view (grid sizes), md[k] its device copy (kernels), a[k]
+// its arguments.  Each is the launch of the single-mesh form for every member (column kernel,
+// then the 2:1 faces), with the column-form conditions on the arguments (no Jacobi scaling, no
+// copy of p; the divergence with h or p, the same for all members); returns -6 otherwise.
+int launch_grad_seg64(int n, const MeshDev* const* mh, const MeshDev* const* md, const GradArgs<double>* a, int degree, hipStream_t s);
+int launch_grad_seg32(int n, const MeshDev* const* mh, const MeshDev* const* md, const GradArgs<float>* a, int degree, hipStream_t s);
+int launch_div_seg64(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<double>* a, int degree, hipStream_t s);
+int launch_div_seg32(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<float>* a, int degree, hipStream_t s);
+int launch_div_split_seg64(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<double>* a, int degree, hipStream_t s);
+int launch_div_split_seg32(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<float>* a, int degree, hipStream_t s);
+int launch_fdm_seg64(int n, const MeshDev* const* mh, const MeshDev* const* md, const FdmArgs<double>* a, int degree, hipStream_t s);
+int launch_fdm_seg32(int n, const MeshDev* const* mh, const MeshDev* const* md, const FdmArgs<float>* a, int degree, hipStream_t s);
+int launch_explicit_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const ExpArgs* a, int degree, hipStream_t s);
+// the 2:1-face passes alone (after the column kernels)
+int launch_grad_hang_seg64(int n, const MeshDev* const* mh, const MeshDev* const* md, const GradArgs<double>* a, int degree, hipStream_t s);
+int launch_grad_hang_seg32(int n, const MeshDev* const* mh, const MeshDev* const* md, const GradArgs<float>* a, int degree, hipStream_t s);
+int launch_div_hang_seg64(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<double>* a, int degree, hipStream_t s);
+int launch_div_hang_seg32(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<float>* a, int degree, hipStream_t s);
+int launch_explicit_hang_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const ExpArgs* a, int degree, hipStream_t s);
 // per-cell sound speed (lam) and preconditioner coefficients from h and w J
 int launch_cellcoef(const MeshDev& m, int degree, const double* h, const double* wJ, double dta,
                     double* lam, float* lam32, double* coef, float* coef32, hipStream_t s);

@@ -207,6 +207,15 @@ struct OpDiv {
   __device__ __forceinline__ T lam(int cell) const { return a.lam ? a.lam[cell] : T(0); }
 };
 
+// Arguments of the general cell kernel: the operator and the cells to visit (list[0..n), or the
+// cells 0..n-1 without a list).
+template <class Op>
+struct CellArgs {
+  Op op;
+  const int* list;
+  int n;
+};
+
 template <class Op> struct HasLam { static constexpr bool value = false; };
 template <int D, class T> struct HasLam<OpDiv<D, T>> { static constexpr bool value = true; };
 
@@ -298,9 +307,14 @@ struct TerTab {
 // output (the column kernels have written the rest for these cells).
 // The faces-only mode asks for 4 waves per SIMD up to degree 4: its 2:1-face phases are latency
 // bound, and the register budget that buys (a few dwords of spill in the FP64 divergence) pays.
-template <int D, int NP, class Op, bool HANG>
-__global__ void __launch_bounds__((Cfg<D, NP>::NT)) __attribute__((amdgpu_waves_per_eu(HANG && NP <= 5 ? 4 : 1))) k_cell(const Op op, const MeshDev m,
-                                                             const int* __restrict__ list, int n) {
+// S: Direct<CellArgs<Op>> (one mesh) or Shared<CellArgs<Op>> (a shared launch over members).
+template <int D, int NP, class Op, bool HANG, class S = Direct<CellArgs<Op>>>
+__global__ void __launch_bounds__((Cfg<D, NP>::NT)) __attribute__((amdgpu_waves_per_eu(HANG && NP <= 5 ? 4 : 1))) k_cell(const S src) {
+  const int sg = src.seg();
+  const Op& op = src.args(sg).op;
+  const MeshDev& m = src.mesh(sg);
+  const int* __restrict__ list = src.args(sg).list;
+  const int n = src.args(sg).n;
   using C = Cfg<D, NP>;
   using T = typename Op::T;
   using TT = TerTab<D, NP>;
@@ -333,7 +347,7 @@ __global__ void __launch_bounds__((Cfg<D, NP>::NT)) __attribute__((amdgpu_waves_
   const int tid = threadIdx.x;
   const int lc = tid / TPC;
   const int node = tid % TPC;
-  const int pos0 = xcd_block(blockIdx.x, gridDim.x) * CPB;  // position in the cell list
+  const int pos0 = xcd_block(src.blk(sg), src.nblk(sg)) * CPB;  // position in the cell list
 
   const T* gtab;
   if constexpr (sizeof(T) == 8) gtab = (const T*)m.tab;
@@ -690,8 +704,23 @@ int run(const Op& op, const MeshDev& m, const int* list, int n, hipStream_t s) {
   using C = Cfg<D, NP>;
   if (n <= 0) return 0;
   const int grid = (n + C::CPB - 1) / C::CPB;
-  hipLaunchKernelGGL((k_cell<D, NP, Op, HANG>), dim3(grid), dim3(C::NT), 0, s, op, m, list, n);
+  hipLaunchKernelGGL((k_cell<D, NP, Op, HANG>), dim3(grid), dim3(C::NT), 0, s,
+                     Direct<CellArgs<Op>>{CellArgs<Op>{op, list, n}, m});
   return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// The faces-only 2:1 pass over the members' cells with such faces, in one shared launch.
+template <int D, int NP, class Op, class MakeOp>
+int run_hang_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, MakeOp make, hipStream_t s) {
+  using C = Cfg<D, NP>;
+  using A = CellArgs<Op>;
+  return seg_launch<A>(
+      n, md, [&](int k) { return (mh[k]->nirr + C::CPB - 1) / C::CPB; },
+      [&](int k) { return A{make(k), mh[k]->irr, mh[k]->nirr}; },
+      [&](const SegTab<A>& t, int g) {
+        hipLaunchKernelGGL((k_cell<D, NP, Op, true, Shared<A>>), dim3(g), dim3(C::NT), 0, s, Shared<A>{t});
+        return hipGetLastError() == hipSuccess ? 0 : -3;
+      });
 }
 
 }  // namespace
@@ -763,6 +792,53 @@ int launch_grad_hang32(const MeshDev& m, int degree, const GradArgs<float>& a, h
 }
 int launch_div_hang32(const MeshDev& m, int degree, const DivArgs<float>& a, hipStream_t s) {
   return div_impl<float, true>(m, degree, a, m.irr, m.nirr, s);
+}
+
+template <class T>
+static int grad_hang_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const GradArgs<T>* a,
+                         int degree, hipStream_t s) {
+  if (n <= 0) return 0;
+  if (mh[0]->dim == 2) {
+    auto mk = [&](int k) { return OpGrad<2, T>{a[k], (unsigned)mh[k]->N}; };
+    DG_DISPATCH(2, degree, return (run_hang_seg<2, NP, OpGrad<2, T>>(n, mh, md, mk, s)));
+  } else {
+    auto mk = [&](int k) { return OpGrad<3, T>{a[k], (unsigned)mh[k]->N}; };
+    DG_DISPATCH(3, degree, return (run_hang_seg<3, NP, OpGrad<3, T>>(n, mh, md, mk, s)));
+  }
+}
+template <class T>
+static int div_hang_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<T>* a,
+                        int degree, hipStream_t s) {
+  if (n <= 0) return 0;
+  if (mh[0]->dim == 2) {
+    auto mk = [&](int k) { return OpDiv<2, T>{a[k], (unsigned)mh[k]->N}; };
+    DG_DISPATCH(2, degree, return (run_hang_seg<2, NP, OpDiv<2, T>>(n, mh, md, mk, s)));
+  } else {
+    auto mk = [&](int k) { return OpDiv<3, T>{a[k], (unsigned)mh[k]->N}; };
+    DG_DISPATCH(3, degree, return (run_hang_seg<3, NP, OpDiv<3, T>>(n, mh, md, mk, s)));
+  }
+}
+int launch_grad_hang_seg64(int n, const MeshDev* const* mh, const MeshDev* const* md, const GradArgs<double>* a, int degree, hipStream_t s) {
+  return grad_hang_seg<double>(n, mh, md, a, degree, s);
+}
+int launch_grad_hang_seg32(int n, const MeshDev* const* mh, const MeshDev* const* md, const GradArgs<float>* a, int degree, hipStream_t s) {
+  return grad_hang_seg<float>(n, mh, md, a, degree, s);
+}
+int launch_div_hang_seg64(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<double>* a, int degree, hipStream_t s) {
+  return div_hang_seg<double>(n, mh, md, a, degree, s);
+}
+int launch_div_hang_seg32(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<float>* a, int degree, hipStream_t s) {
+  return div_hang_seg<float>(n, mh, md, a, degree, s);
+}
+int launch_explicit_hang_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const ExpArgs* a, int degree, hipStream_t s) {
+  if (n <= 0) return 0;
+  if (mh[0]->dim == 2) {
+    auto mk = [&](int k) { return OpExplicit<2>{a[k].U, a[k].R, (unsigned)mh[k]->N}; };
+    DG_DISPATCH(2, degree, return (run_hang_seg<2, NP, OpExplicit<2>>(n, mh, md, mk, s)));
+  } else {
+    auto mk = [&](int k) { return OpExplicit<3>{a[k].U, a[k].R, (unsigned)mh[k]->N}; };
+    DG_DISPATCH(3, degree, return (run_hang_seg<3, NP, OpExplicit<3>>(n, mh, md, mk, s)));
+  }
 }
 
 // ------------------------------------------------------------------ per-cell coefficients

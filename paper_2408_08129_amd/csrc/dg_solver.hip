@@ -61,9 +61,9 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Block-reduce NV per-thread sums (fixed order) and write part[i * gridDim.x + blockIdx.x].
+// Block-reduce NV per-thread sums (fixed order) and write part[i * nb + bid] (block bid of nb).
 template <int NV>
-__device__ __forceinline__ void block_store(const double (&acc)[NV], double* part) {
+__device__ __forceinline__ void block_store(const double (&acc)[NV], double* part, int bid, int nb) {
   __shared__ double s[NV][kRedThreads / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -76,25 +76,28 @@ __device__ __forceinline__ void block_store(const double (&acc)[NV], double* par
     double t = 0.0;
 #pragma unroll
     for (int k = 0; k < kRedThreads / 64; ++k) t += s[threadIdx.x][k];
-    part[(long)threadIdx.x * gridDim.x + blockIdx.x] = t;
+    part[(long)threadIdx.x * nb + bid] = t;
   }
 }
 
-// Second stage: one workgroup per reduced value (grid = nv), fixed order.
-__global__ void __launch_bounds__(kRedThreads) k_reduce(const double* part, int G, double* out) {
+// Second stage: value i is the sum of part[i * G + 0 .. G), in a fixed order, by one workgroup.
+__device__ __forceinline__ double reduce_value(const double* part, int G, int i) {
   __shared__ double s[kRedThreads / 64];
-  const int i = blockIdx.x;
   double t = 0.0;
   for (int b = threadIdx.x; b < G; b += kRedThreads) t += part[(long)i * G + b];
   t = wave_sum(t);
   if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = t;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double u = 0.0;
+  double u = 0.0;
 #pragma unroll
-    for (int k = 0; k < kRedThreads / 64; ++k) u += s[k];
-    out[i] = u;
-  }
+  for (int k = 0; k < kRedThreads / 64; ++k) u += s[k];
+  return u;  // valid in thread 0
+}
+
+// Second stage, one workgroup per value (grid = nv).
+__global__ void __launch_bounds__(kRedThreads) k_reduce(const double* part, int G, double* out) {
+  const double u = reduce_value(part, G, blockIdx.x);
+  if (threadIdx.x == 0) out[blockIdx.x] = u;
 }
 
 // The basis kernels stream 16 bytes per lane per access (two doubles or four floats; gfx950
@@ -124,17 +127,29 @@ __device__ __forceinline__ void dots_point(double (&acc)[NA], double xv, double 
   }
 }
 
+template <class T>
+struct DotsArgs {
+  const T* V;
+  long ld;
+  const T* x;
+  const T* y;
+  double* part;
+  long n;
+};
+
 template <class T, int NV, bool HASY>
-__global__ void __launch_bounds__(kRedThreads) k_gs_dots(const T* __restrict__ V, long ld,
-                                                         const T* __restrict__ x, const T* __restrict__ y,
-                                                         double* part, long n) {
+__device__ __forceinline__ void gs_dots_body(const DotsArgs<T>& a, int bid, int nb) {
   constexpr int NA = HASY ? 2 * NV + 3 : NV + 1;
   constexpr int W = Vec16<T>::W;
   using VT = typename Vec16<T>::type;
+  const T* __restrict__ V = a.V;
+  const T* __restrict__ x = a.x;
+  const T* __restrict__ y = a.y;
+  const long ld = a.ld, n = a.n;
   double acc[NA];
 #pragma unroll
   for (int i = 0; i < NA; ++i) acc[i] = 0.0;
-  const long gt = (long)blockIdx.x * blockDim.x + threadIdx.x, gs = (long)gridDim.x * blockDim.x;
+  const long gt = (long)bid * kRedThreads + threadIdx.x, gs = (long)nb * kRedThreads;
   const long nvec = n / W;
   for (long e = gt; e < nvec; e += gs) {
     const VT xw = *(const VT*)(x + e * W);
@@ -157,15 +172,40 @@ __global__ void __launch_bounds__(kRedThreads) k_gs_dots(const T* __restrict__ V
     for (int i = 0; i < NV; ++i) v[i] = (double)V[i * ld + e];
     dots_point<NV, HASY>(acc, (double)x[e], HASY ? (double)y[e] : 0.0, v);
   }
-  block_store<NA>(acc, part);
+  block_store<NA>(acc, a.part, bid, nb);
+}
+
+template <class T, int NV, bool HASY>
+__global__ void __launch_bounds__(kRedThreads) k_gs_dots(const DotsArgs<T> a) {
+  gs_dots_body<T, NV, HASY>(a, blockIdx.x, gridDim.x);
+}
+template <class T, int NV, bool HASY>
+__global__ void __launch_bounds__(kRedThreads) k_gs_dots_seg(const Shared<DotsArgs<T>> src) {
+  const int k = src.seg();
+  gs_dots_body<T, NV, HASY>(src.args(k), src.blk(k), src.nblk(k));
 }
 
 // Update pass of the Gram-Schmidt step, FP64 arithmetic:
 //   z = y - sum_i b_i V_i - g x      (x as read on entry)
 //   x = x - sum_i a_i V_i            (only when NV > 0; in place)
-// and part = |z|^2.
-template <class T, int NV>
-__device__ __forceinline__ void update_point(const Coef& a, const Coef& b, double g, const double (&v)[NV > 0 ? NV : 1],
+// and part = |z|^2.  The coefficients come as kernel arguments (one mesh) or, for a shared launch,
+// from device memory through LDS.
+template <class T>
+struct UpdArgs {
+  const T* V;
+  long ld;
+  const double* coef;  // shared launches: a at coef[0 .. kMaxV), b at coef[kMaxV .. 2 kMaxV)
+  double g;
+  T* x;
+  const T* y;
+  T* z;
+  double* part;
+  long n;
+};
+struct CoefRef { const double* c; };
+
+template <class T, int NV, class CA>
+__device__ __forceinline__ void update_point(const CA& a, const CA& b, double g, const double (&v)[NV > 0 ? NV : 1],
                                              double xo, double yv, T& zt, T& xt) {
   double zv = yv - g * xo;
   double xn = xo;
@@ -178,15 +218,18 @@ __device__ __forceinline__ void update_point(const Coef& a, const Coef& b, doubl
   xt = (T)xn;
 }
 
-template <class T, int NV>
-__global__ void __launch_bounds__(kRedThreads) k_gs_update(const T* __restrict__ V, long ld, const Coef a,
-                                                           const Coef b, double g, T* __restrict__ x,
-                                                           const T* __restrict__ y, T* __restrict__ z,
-                                                           double* part, long n) {
+template <class T, int NV, class CA>
+__device__ __forceinline__ void gs_update_body(const UpdArgs<T>& u, const CA& a, const CA& b, int bid, int nb) {
   constexpr int W = Vec16<T>::W;
   using VT = typename Vec16<T>::type;
+  const T* __restrict__ V = u.V;
+  T* __restrict__ x = u.x;
+  const T* __restrict__ y = u.y;
+  T* __restrict__ z = u.z;
+  const long ld = u.ld, n = u.n;
+  const double g = u.g;
   double acc[1] = {0.0};
-  const long gt = (long)blockIdx.x * blockDim.x + threadIdx.x, gs = (long)gridDim.x * blockDim.x;
+  const long gt = (long)bid * kRedThreads + threadIdx.x, gs = (long)nb * kRedThreads;
   const long nvec = n / W;
   for (long e = gt; e < nvec; e += gs) {
     VT vw[NV > 0 ? NV : 1];
@@ -219,7 +262,24 @@ __global__ void __launch_bounds__(kRedThreads) k_gs_update(const T* __restrict__
     if (NV > 0) x[e] = xt;
     acc[0] += (double)zt * (double)zt;
   }
-  block_store<1>(acc, part);
+  block_store<1>(acc, u.part, bid, nb);
+}
+
+template <class T, int NV>
+__global__ void __launch_bounds__(kRedThreads) k_gs_update(const UpdArgs<T> u, const Coef a, const Coef b) {
+  gs_update_body<T, NV>(u, a, b, blockIdx.x, gridDim.x);
+}
+template <class T, int NV>
+__global__ void __launch_bounds__(kRedThreads) k_gs_update_seg(const Shared<UpdArgs<T>> src) {
+  __shared__ double sc[2][kMaxV];
+  const int k = src.seg();
+  const UpdArgs<T>& u = src.args(k);
+  if (threadIdx.x < NV) {
+    sc[0][threadIdx.x] = u.coef[threadIdx.x];
+    sc[1][threadIdx.x] = u.coef[kMaxV + threadIdx.x];
+  }
+  __syncthreads();
+  gs_update_body<T, NV>(u, CoefRef{sc[0]}, CoefRef{sc[1]}, src.blk(k), src.nblk(k));
 }
 
 // x += dinv * sum_i c_i V_i  (FP64 accumulation)
@@ -252,6 +312,21 @@ __global__ void k_update(const T* __restrict__ V, long ld, const Coef c, const T
   }
 }
 
+// Second stages of a shared launch: value blk of member k's partials (nv blocks per member), and
+// the candidate norm (one block per member).
+struct RedArgs {
+  const double* part;
+  int G;
+  double* out;
+};
+__global__ void __launch_bounds__(kRedThreads) k_reduce_seg(const Shared<RedArgs> src) {
+  const int k = src.seg();
+  const RedArgs& a = src.args(k);
+  const int i = src.blk(k);
+  const double u = reduce_value(a.part, a.G, i);
+  if (threadIdx.x == 0) a.out[i] = u;
+}
+
 #define DG_NV_CASES(X) \
   X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) \
   X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31)
@@ -261,16 +336,35 @@ __global__ void k_update(const T* __restrict__ V, long ld, const Coef c, const T
 template <class T>
 void launch_gs_dots(int nv, int G, hipStream_t s, const T* V, long ld, const T* x, const T* y, double* part,
                     long n) {
+  const DotsArgs<T> a{V, ld, x, y, part, n};
   if (y) {
     switch (nv) {
-#define X(K) case K: hipLaunchKernelGGL((k_gs_dots<T, K, true>), dim3(G), dim3(kRedThreads), 0, s, V, ld, x, y, part, n); break;
+#define X(K) case K: hipLaunchKernelGGL((k_gs_dots<T, K, true>), dim3(G), dim3(kRedThreads), 0, s, a); break;
       DG_NV_CASES0(X)
 #undef X
       default: break;
     }
   } else {
     switch (nv) {
-#define X(K) case K: hipLaunchKernelGGL((k_gs_dots<T, K, false>), dim3(G), dim3(kRedThreads), 0, s, V, ld, x, y, part, n); break;
+#define X(K) case K: hipLaunchKernelGGL((k_gs_dots<T, K, false>), dim3(G), dim3(kRedThreads), 0, s, a); break;
+      DG_NV_CASES0(X)
+#undef X
+      default: break;
+    }
+  }
+}
+template <class T>
+void launch_gs_dots_seg(int nv, bool hasy, int g, hipStream_t s, const Shared<DotsArgs<T>>& t) {
+  if (hasy) {
+    switch (nv) {
+#define X(K) case K: hipLaunchKernelGGL((k_gs_dots_seg<T, K, true>), dim3(g), dim3(kRedThreads), 0, s, t); break;
+      DG_NV_CASES0(X)
+#undef X
+      default: break;
+    }
+  } else {
+    switch (nv) {
+#define X(K) case K: hipLaunchKernelGGL((k_gs_dots_seg<T, K, false>), dim3(g), dim3(kRedThreads), 0, s, t); break;
       DG_NV_CASES0(X)
 #undef X
       default: break;
@@ -280,8 +374,18 @@ void launch_gs_dots(int nv, int G, hipStream_t s, const T* V, long ld, const T* 
 template <class T>
 void launch_gs_update(int nv, int G, hipStream_t s, const T* V, long ld, const Coef& a, const Coef& b, double g,
                       T* x, const T* y, T* z, double* part, long n) {
+  const UpdArgs<T> u{V, ld, nullptr, g, x, y, z, part, n};
   switch (nv) {
-#define X(K) case K: hipLaunchKernelGGL((k_gs_update<T, K>), dim3(G), dim3(kRedThreads), 0, s, V, ld, a, b, g, x, y, z, part, n); break;
+#define X(K) case K: hipLaunchKernelGGL((k_gs_update<T, K>), dim3(G), dim3(kRedThreads), 0, s, u, a, b); break;
+    DG_NV_CASES0(X)
+#undef X
+    default: break;
+  }
+}
+template <class T>
+void launch_gs_update_seg(int nv, int g, hipStream_t s, const Shared<UpdArgs<T>>& t) {
+  switch (nv) {
+#define X(K) case K: hipLaunchKernelGGL((k_gs_update_seg<T, K>), dim3(g), dim3(kRedThreads), 0, s, t); break;
     DG_NV_CASES0(X)
 #undef X
     default: break;
@@ -315,20 +419,19 @@ __global__ void k_maxabs_ratio(const double* __restrict__ num, const double* __r
 
 // Second stage of the candidate-norm reduction of the one-round-trip GMRES iteration: out[0] =
 // |v|^2, out[1] = 1/|v| (0 for a zero vector), the scale the next operator application reads.
-__global__ void __launch_bounds__(kRedThreads) k_reduce_norm(const double* part, int G, double* out) {
-  __shared__ double s[kRedThreads / 64];
-  double t = 0.0;
-  for (int b = threadIdx.x; b < G; b += kRedThreads) t += part[b];
-  t = wave_sum(t);
-  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = t;
-  __syncthreads();
+__device__ __forceinline__ void reduce_norm_body(const double* part, int G, double* out) {
+  const double u = reduce_value(part, G, 0);
   if (threadIdx.x == 0) {
-    double u = 0.0;
-#pragma unroll
-    for (int k = 0; k < kRedThreads / 64; ++k) u += s[k];
     out[0] = u;
     out[1] = u > 0.0 ? 1.0 / sqrt(u) : 0.0;
   }
+}
+__global__ void __launch_bounds__(kRedThreads) k_reduce_norm(const double* part, int G, double* out) {
+  reduce_norm_body(part, G, out);
+}
+__global__ void __launch_bounds__(kRedThreads) k_reduce_norm_seg(const Shared<RedArgs> src) {
+  const int k = src.seg();
+  reduce_norm_body(src.args(k).part, src.args(k).G, src.args(k).out);
 }
 
 // Second stage of the max reduction: one workgroup, fixed order.
@@ -345,21 +448,33 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce_max(const double* part, 
   if (threadIdx.x == 0) *out = s[0];
 }
 
-__global__ void k_nonfinite(const double* __restrict__ x, long n, int* flag) {
-  bool bad = false;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
-    bad |= !isfinite(x[e]);
-  if (bad) atomicOr(flag, 1);
-}
 
 // ----------------------------------------------------------------------------- pointwise kernels
 #define GRID_LOOP(e, n) \
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < (n); e += (long)gridDim.x * blockDim.x)
 
+// The pointwise work of the step as functors over n elements: k_pw runs one over a grid, k_pw_seg
+// runs one per member in a shared launch.  Each element's arithmetic is the functor's alone.
+template <class F>
+__global__ void __launch_bounds__(256) k_pw(const F f) {
+  GRID_LOOP(e, f.n) f(e);
+}
+template <class F>
+__global__ void __launch_bounds__(256) k_pw_seg(const Shared<F> src) {
+  const int k = src.seg();
+  const F& f = src.args(k);
+  for (long e = (long)src.blk(k) * 256 + threadIdx.x; e < f.n; e += (long)src.nblk(k) * 256) f(e);
+}
+
+// p' = p - pbar and h = gamma p / ((gamma - 1) rho) from the state
 template <int D>
-__global__ void k_pressure_h(const double* __restrict__ U, const double* __restrict__ pbar, long N,
-                             long ld, double* __restrict__ pp, double* __restrict__ h) {
-  GRID_LOOP(e, N) {
+struct PwPressureH {
+  long n, ld;
+  const double* U;
+  const double* pbar;
+  double* pp;
+  double* h;
+  __device__ void operator()(long e) const {
     const double rho = U[e];
     double m2 = 0.0;
 #pragma unroll
@@ -368,58 +483,57 @@ __global__ void k_pressure_h(const double* __restrict__ U, const double* __restr
     pp[e] = p - pbar[e];
     h[e] = kGamma * p / ((kGamma - 1.0) * rho);
   }
-}
-
-// per-cell maximum of c = sqrt((gamma - 1) h): one wavefront per cell
-__global__ void k_lam(const double* __restrict__ h, int nloc, int ncell, double* lam, float* lam32) {
-  const int c = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (c >= ncell) return;
-  double m = 0.0;
-  for (int i = lane; i < nloc; i += 64) m = fmax(m, h[(long)c * nloc + i]);
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-  if (lane == 0) {
-    const double v = sqrt((kGamma - 1.0) * m);
-    lam[c] = v;
-    if (lam32) lam32[c] = (float)v;
-  }
-}
+};
 
 // absorbing layers: R_m -= tau (m - rho u_ref e_x) (Rayleigh friction in the explicit part)
 template <int D>
-__global__ void k_friction(const double* __restrict__ U, const double* __restrict__ tau, double uref,
-                           long N, long ld, double* __restrict__ R) {
-  GRID_LOOP(e, N) {
+struct PwFriction {
+  long n, ld;
+  const double* U;
+  const double* tau;
+  double uref;
+  double* R;
+  __device__ void operator()(long e) const {
     const double t = tau[e];
-    if (t == 0.0) continue;
+    if (t == 0.0) return;
     R[ld + e] -= t * (U[ld + e] - U[e] * uref);
 #pragma unroll
     for (int l = 1; l < D; ++l) R[(1 + l) * ld + e] -= t * U[(1 + l) * ld + e];
   }
-}
+};
 
 template <int D>
-__global__ void k_fi_momentum(const double* __restrict__ q, const double* __restrict__ U,
-                              const double* __restrict__ rbar, long N, long ld, double* __restrict__ F) {
-  GRID_LOOP(e, N) {
+struct PwFiMomentum {
+  long n, ld;
+  const double* q;
+  const double* U;
+  const double* rbar;
+  double* F;
+  __device__ void operator()(long e) const {
     F[e] = 0.0;
 #pragma unroll
     for (int l = 0; l < D; ++l) F[(1 + l) * ld + e] = -q[l * ld + e];
     F[D * ld + e] -= (U[e] - rbar[e]) * kG;
   }
-}
+};
 
-// stage predictor from nj previous stages
+// stage predictor from nj previous stages; Us[0] <- rho_i, mt, et, mp
 template <int D>
-__global__ void k_predictor(const double* __restrict__ U, const double* __restrict__ FE0,
-                            const double* __restrict__ FE1, const double* __restrict__ FI0,
-                            const double* __restrict__ FI1, int nj, double a0, double a1,
-                            double t0, double t1, double dt, double dta,
-                            const double* __restrict__ rbar, long N, long ld,
-                            double* __restrict__ Us, double* __restrict__ mt, double* __restrict__ et,
-                            double* __restrict__ mp) {
-  GRID_LOOP(e, N) {
+struct PwPredictor {
+  long n, ld;
+  const double* U;
+  const double* FE0;
+  const double* FE1;
+  const double* FI0;
+  const double* FI1;
+  int nj;
+  double a0, a1, t0, t1, dt, dta;
+  const double* rbar;
+  double* Us;
+  double* mt;
+  double* et;
+  double* mp;
+  __device__ void operator()(long e) const {
     double rho = FE0[e] * a0;
     if (nj > 1) rho += FE1[e] * a1;
     rho = U[e] + dt * rho;
@@ -438,25 +552,37 @@ __global__ void k_predictor(const double* __restrict__ U, const double* __restri
     }
     mp[(D - 1) * ld + e] -= dta * (rho - rbar[e]) * kG;
   }
-}
+};
 
-// stage start: copy momentum and pressure perturbation of the previous stage (or of U^n)
+// stage start: copy the momentum of U^n
 template <int D>
-__global__ void k_copy_m(const double* __restrict__ src, long ld, long N, double* __restrict__ dst) {
-  GRID_LOOP(e, N) {
+struct PwCopyM {
+  long n, ld;
+  const double* src;
+  double* dst;
+  __device__ void operator()(long e) const {
 #pragma unroll
     for (int l = 0; l < D; ++l) dst[(1 + l) * ld + e] = src[(1 + l) * ld + e];
   }
-}
+};
 
 // coefficients of the fixed-point iterate: h, Jacobi diagonal (inverse), FP32 copies
-__global__ void k_coef(const double* __restrict__ rho, const double* __restrict__ pbar,
-                       const double* __restrict__ pp, const double* __restrict__ wJ,
-                       const int4* __restrict__ cell, int nloc, int dim, double L0, double L1,
-                       double L2, int n0, int n1, int n2, int r1, double dta, long N,
-                       double* __restrict__ h, double* __restrict__ dinv, float* __restrict__ h32,
-                       float* __restrict__ dinv32) {
-  GRID_LOOP(e, N) {
+struct PwCoef {
+  long n;
+  const double* rho;
+  const double* pbar;
+  const double* pp;
+  const double* wJ;
+  const int4* cell;
+  int nloc, dim;
+  double L0, L1, L2;
+  int n0, n1, n2, r1;
+  double dta;
+  double* h;
+  double* dinv;
+  float* h32;
+  float* dinv32;
+  __device__ void operator()(long e) const {
     const double hv = kGamma * (pbar[e] + pp[e]) / ((kGamma - 1.0) * rho[e]);
     const int lev = cell[e / nloc].x;
     const double d0 = L0 / (double)(n0 << lev), d1 = L1 / (double)(n1 << lev);
@@ -473,36 +599,86 @@ __global__ void k_coef(const double* __restrict__ rho, const double* __restrict_
       dinv32[e] = (float)dv;
     }
   }
-}
+};
 
 template <int D>
-__global__ void k_rhs_add(double* __restrict__ b, const double* __restrict__ wJ,
-                          const double* __restrict__ et, const double* __restrict__ Us,
-                          const double* __restrict__ pbar, long N, long ld) {
-  GRID_LOOP(e, N) {
+struct PwRhsAdd {
+  long n, ld;
+  double* b;
+  const double* wJ;
+  const double* et;
+  const double* Us;
+  const double* pbar;
+  __device__ void operator()(long e) const {
     const double rho = Us[e];
     double m2 = 0.0;
 #pragma unroll
     for (int l = 0; l < D; ++l) m2 += Us[(1 + l) * ld + e] * Us[(1 + l) * ld + e];
     b[e] += wJ[e] * (et[e] - 0.5 * m2 / rho - pbar[e] / (kGamma - 1.0));
   }
-}
+};
 
-__global__ void k_sub(const double* __restrict__ a, const double* __restrict__ b, long N,
-                      double* __restrict__ out) {
-  GRID_LOOP(e, N) out[e] = a[e] - b[e];
-}
-__global__ void k_add(double* __restrict__ a, const double* __restrict__ b, long N) {
-  GRID_LOOP(e, N) a[e] += b[e];
-}
-__global__ void k_zero(double* __restrict__ a, long N) {
-  GRID_LOOP(e, N) a[e] = 0.0;
-}
-__global__ void k_widen(const float* __restrict__ a, long N, double* __restrict__ out) {
-  GRID_LOOP(e, N) out[e] = (double)a[e];
-}
-__global__ void k_scale_cast(const double* __restrict__ a, double s, long N, float* __restrict__ out) {
-  GRID_LOOP(e, N) out[e] = (float)(s * a[e]);
+struct PwSub {  // out = a - b
+  long n;
+  const double* a;
+  const double* b;
+  double* out;
+  __device__ void operator()(long e) const { out[e] = a[e] - b[e]; }
+};
+struct PwAdd {  // a += b
+  long n;
+  double* a;
+  const double* b;
+  __device__ void operator()(long e) const { a[e] += b[e]; }
+};
+struct PwZero {
+  long n;
+  double* a;
+  __device__ void operator()(long e) const { a[e] = 0.0; }
+};
+struct PwCopy {
+  long n;
+  const double* a;
+  double* out;
+  __device__ void operator()(long e) const { out[e] = a[e]; }
+};
+struct PwWiden {
+  long n;
+  const float* a;
+  double* out;
+  __device__ void operator()(long e) const { out[e] = (double)a[e]; }
+};
+struct PwScaleCast {  // out = (float)(s a)
+  long n;
+  const double* a;
+  double s;
+  float* out;
+  __device__ void operator()(long e) const { out[e] = (float)(s * a[e]); }
+};
+// flag = 1 if any of x[0..n) is not finite (every writer stores the same value)
+struct PwNonfinite {
+  long n;
+  const double* x;
+  double* flag;
+  __device__ void operator()(long e) const {
+    if (!isfinite(x[e])) *flag = 1.0;
+  }
+};
+
+// per-cell maximum of c = sqrt((gamma - 1) h): one wavefront per cell
+__global__ void k_lam(const double* __restrict__ h, int nloc, int ncell, double* lam, float* lam32) {
+  const int c = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= ncell) return;
+  double m = 0.0;
+  for (int i = lane; i < nloc; i += 64) m = fmax(m, h[(long)c * nloc + i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if (lane == 0) {
+    const double v = sqrt((kGamma - 1.0) * m);
+    lam[c] = v;
+    if (lam32) lam32[c] = (float)v;
+  }
 }
 
 // Background enthalpy hbar = gamma pbar / ((gamma - 1) rhobar) and its height derivative from the
@@ -523,23 +699,31 @@ __global__ void k_hbar(const double* __restrict__ pbar, const double* __restrict
   }
 }
 
-// Enthalpy split: out += hbar * s2 + adiv (w J if weak) (d hbar/dz) q_z, s2 = adiv C(q) (weak form,
-// or with M^-1 applied when not weak).
+// momentum back-substitution m = m' - dt a q (q = M^-1 B p')
 template <int D>
-__global__ void k_backsub(const double* __restrict__ mp, const double* __restrict__ q, double dta,
-                          long N, long ld, double* __restrict__ Us) {
-  GRID_LOOP(e, N) {
+struct PwBacksub {
+  long n, ld;
+  const double* mp;
+  const double* q;
+  double dta;
+  double* Us;
+  __device__ void operator()(long e) const {
 #pragma unroll
     for (int l = 0; l < D; ++l) Us[(1 + l) * ld + e] = mp[l * ld + e] - dta * q[l * ld + e];
   }
-}
+};
 
 template <int D>
-__global__ void k_stage_finish(double* __restrict__ Us, const double* __restrict__ pp,
-                               const double* __restrict__ pbar, const double* __restrict__ mt,
-                               const double* __restrict__ et, double dta, long N, long ld,
-                               double* __restrict__ FI) {
-  GRID_LOOP(e, N) {
+struct PwStageFinish {
+  long n, ld;
+  double* Us;
+  const double* pp;
+  const double* pbar;
+  const double* mt;
+  const double* et;
+  double dta;
+  double* FI;
+  __device__ void operator()(long e) const {
     const double rho = Us[e];
     double m2 = 0.0;
 #pragma unroll
@@ -553,15 +737,21 @@ __global__ void k_stage_finish(double* __restrict__ Us, const double* __restrict
     FI[(1 + D) * ld + e] = (E - et[e]) / dta;
     FI[e] = 0.0;
   }
-}
+};
 
 template <int D>
-__global__ void k_final(const double* __restrict__ U, const double* __restrict__ FE0,
-                        const double* __restrict__ FE1, const double* __restrict__ FE2,
-                        const double* __restrict__ FI0, const double* __restrict__ FI1,
-                        const double* __restrict__ FI2, double b0, double b1, double b2,
-                        double dt, long N, long ld, double* __restrict__ Un) {
-  GRID_LOOP(e, N) {
+struct PwFinal {
+  long n, ld;
+  const double* U;
+  const double* FE0;
+  const double* FE1;
+  const double* FE2;
+  const double* FI0;
+  const double* FI1;
+  const double* FI2;
+  double b0, b1, b2, dt;
+  double* Un;
+  __device__ void operator()(long e) const {
     Un[e] = U[e] + dt * (b0 * FE0[e] + b1 * FE1[e] + b2 * FE2[e]);
 #pragma unroll
     for (int f = 1; f < D + 2; ++f) {
@@ -569,7 +759,7 @@ __global__ void k_final(const double* __restrict__ U, const double* __restrict__
       Un[i] = U[i] + dt * ((b0 * FE0[i] + b1 * FE1[i] + b2 * FE2[i]) + (b0 * FI0[i] + b1 * FI1[i] + b2 * FI2[i]));
     }
   }
-}
+};
 
 // SplitMix64 (Steele, Lea, Flood 2014) as a counter-based generator: the output mix of the state
 // seed + G k.  A node's deviates are keyed by the seed, its cell's (level, i_x, i_y, i_z) and its
@@ -802,6 +992,7 @@ struct dg_ctx {
   hipStream_t stream = nullptr;
   bool timing = false;
   MeshDev md{};
+  MeshDev* d_md = nullptr;  // device copy of md (shared launches read the members' views there)
   char* arena = nullptr;
   size_t arena_bytes = 0;
   // mesh
@@ -832,11 +1023,13 @@ struct dg_ctx {
   double *coef = nullptr, *u = nullptr;
   float *coef32 = nullptr, *u32 = nullptr;
   double* rr = nullptr;
-  // reductions
+  // reductions: per-block partials; result slots of the members of a team this context leads
+  // (device, and pinned host followed by the host staging of the update coefficients); the
+  // coefficients of a shared update pass on the device
   double* part = nullptr;
   double* red = nullptr;
-  int* flag = nullptr;
-  double* hred = nullptr;  // pinned host
+  double* hred = nullptr;
+  double* tcoef = nullptr;
   int m = 30, m32 = 30;
   // per-launch HIP events (timing on): pairs around launches, tagged with a kernel class
   std::vector<hipEvent_t> ev;
@@ -882,11 +1075,22 @@ dg_status scratch_ptr(const dg_ctx* c, double** out) {
 
 constexpr int kEvPool = 8192;
 
+// Teams (lockstep members, see step_team) of at most kTeamMax members.
+constexpr int kTeamMax = 32;
+// per-member result slot in the lead context's reduction buffer: [0] |v|^2 and [1] 1/|v| of the
+// Krylov candidate, [2, 2 + nv) the reduced values of the last reduction, [kFlagAt] the non-finite
+// flag of the new state, [kMaxAt] max |w|
+constexpr int kResStride = 72;
+constexpr int kFlagAt = 68, kMaxAt = 69;
+constexpr int kCoefStride = 2 * kMaxV;
+static_assert(2 + 2 * (kMaxV - 2) + 3 <= kFlagAt, "result slot too small");  // restart <= kMaxV - 1
+
 // Records a HIP event pair around the launches of its scope when timing is on.
 struct Timed {
   dg_ctx* c;
   int slot = -1;
   Timed(dg_ctx* c_, int cls, double bytes = 0.0) : c(c_) {
+    if (!c) return;
     if (c->timing) c->kbytes[cls] += bytes;
     if (c->timing && c->ev_n < kEvPool) {
       slot = c->ev_n++;
@@ -904,7 +1108,7 @@ struct Phase {
   dg_ctx* c;
   int slot = -1;
   Phase(dg_ctx* c_, int ph) : c(c_) {
-    if (c->timing && c->pev_n < kPhasePool) {
+    if (c && c->timing && c->pev_n < kPhasePool) {
       slot = c->pev_n++;
       c->pev_cls[slot] = ph;
       (void)hipEventRecord(c->pev[2 * slot], c->stream);
@@ -1063,8 +1267,9 @@ void make_plan(dg_ctx* c, Plan& P) {
     P.add((void**)&c->V, (size_t)(c->m + 1) * ld * d8);
   }
   P.add((void**)&c->part, (size_t)(2 * kMaxV + 3) * kMaxGrid * d8);
-  P.add((void**)&c->red, (2 * kMaxV + 5) * d8);
-  P.add((void**)&c->flag, 256);
+  P.add((void**)&c->red, (size_t)kTeamMax * kResStride * d8);
+  P.add((void**)&c->tcoef, (size_t)kTeamMax * kCoefStride * d8);
+  P.add((void**)&c->d_md, sizeof(MeshDev));
 }
 
 dg_status prepare(dg_ctx* c, const dg_case_desc* desc, int degree, const dg_options* opt) {
@@ -1107,11 +1312,132 @@ dg_status prepare(dg_ctx* c, const dg_case_desc* desc, int degree, const dg_opti
   return DG_OK;
 }
 
-// ----------------------------------------------------------------------------- Krylov driver
-struct ApplyCtx {
-  dg_ctx* c;
-  double dta;
+// ------------------------------------------------------------------------------ lockstep teams
+// A team is a set of members (contexts of one class: dimension, degree, precision, preconditioner
+// and energy-flux form) advanced through the step in lockstep on one stream.  A team of one with
+// direct launches is the single-context step.  Otherwise every operator, Krylov and pointwise
+// launch of the step is shared by the members through segment tables, and each host round trip of
+// the Krylov iteration serves all of them.  Members keep their own control flow (iteration
+// counts, convergence, restarts, failures) by taking part only in the launches they need, and
+// their own grid shapes, so a member's results are the same bits alone and in any mix.
+
+struct Team {
+  std::vector<dg_ctx*> m;
+  hipStream_t s = nullptr;
+  bool shared = false;
+  dg_ctx* lead = nullptr;
+  dg_ctx* tc = nullptr;  // context whose events time the launches (direct launches, timing on)
+  std::vector<dg_status> st;
+  double* slot(int k) const { return lead->red + (size_t)k * kResStride; }
+  const double* hslot(int k) const { return lead->hred + (size_t)k * kResStride; }
+  double* hcoef(int k) const { return lead->hred + (size_t)kTeamMax * kResStride + (size_t)k * kCoefStride; }
+  const double* dcoef(int k) const { return lead->tcoef + (size_t)k * kCoefStride; }
+  bool alive(int k) const { return st[k] == DG_OK; }
+  int n() const { return (int)m.size(); }
 };
+
+Team solo(dg_ctx* c) {
+  Team T;
+  T.m = {c};
+  T.s = c->stream;
+  T.lead = c;
+  T.tc = c->timing ? c : nullptr;
+  T.st.assign(1, DG_OK);
+  return T;
+}
+
+// A member leaves the step with an error of its own; the others go on.
+void drop(Team& Tm, int k, dg_status rc, const std::string& why) {
+  if (!Tm.alive(k)) return;
+  Tm.st[k] = rc;
+  set_error(Tm.m[k], why);
+}
+// A failed launch or copy ends the step for every member.
+dg_status team_fail(Team& Tm, dg_status rc, const std::string& why) {
+  for (int k = 0; k < Tm.n(); ++k) drop(Tm, k, rc, why);
+  return rc;
+}
+#define TCHK(team, call)                                                                    \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return team_fail(team, DG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+std::vector<int> alive_of(const Team& Tm, const std::vector<int>& act) {
+  std::vector<int> r;
+  for (int k : act)
+    if (Tm.alive(k)) r.push_back(k);
+  return r;
+}
+
+// The members' result slots to the host (one copy, one synchronisation).
+dg_status fetch(Team& Tm, const std::vector<int>& act) {
+  int hi = -1;
+  for (int k : act) hi = std::max(hi, k);
+  if (hi < 0) return DG_OK;
+  TCHK(Tm, hipMemcpyAsync(Tm.lead->hred, Tm.lead->red, (size_t)(hi + 1) * kResStride * sizeof(double),
+                      hipMemcpyDeviceToHost, Tm.s));
+  TCHK(Tm, hipStreamSynchronize(Tm.s));
+  return DG_OK;
+}
+
+// Pointwise functor per member: a direct launch each, or shared launches.
+template <class F, class Make>
+dg_status pw(Team& Tm, const std::vector<int>& act, Make mk) {
+  if (act.empty()) return DG_OK;
+  if (!Tm.shared) {
+    for (int k : act) {
+      const F f = mk(k);
+      Timed t_(Tm.tc, 4);
+      hipLaunchKernelGGL((k_pw<F>), pw_grid(f.n), dim3(256), 0, Tm.s, f);
+    }
+  } else {
+    std::vector<F> fs;
+    fs.reserve(act.size());
+    for (int k : act) fs.push_back(mk(k));
+    seg_launch<F>((int)fs.size(), nullptr, [&](int i) { return (int)pw_grid(fs[i].n).x; },
+                  [&](int i) { return fs[i]; },
+                  [&](const SegTab<F>& t, int g) {
+                    hipLaunchKernelGGL((k_pw_seg<F>), dim3(g), dim3(256), 0, Tm.s, Shared<F>{t});
+                    return 0;
+                  });
+  }
+  TCHK(Tm, hipGetLastError());
+  return DG_OK;
+}
+
+// Operator per member: the single-mesh launcher (direct), or the shared launcher, which answers
+// -6 when the arguments need the general cell kernel (then one launch per member).
+template <class A, class Make, class Bytes, class One, class Many>
+dg_status op_launch(Team& Tm, const std::vector<int>& act, int cls, Make mk, Bytes bytes, One one, Many many) {
+  if (act.empty()) return DG_OK;
+  if (!Tm.shared) {
+    for (int k : act) {
+      const A a = mk(k);
+      int r;
+      {
+        Timed t_(Tm.tc, cls, bytes(k));
+        r = one(Tm.m[k], a);
+      }
+      if (r) return team_fail(Tm, r == -6 ? DG_EUNSUPPORTED : DG_EDEVICE, "operator launch failed");
+    }
+    return DG_OK;
+  }
+  std::vector<A> as;
+  std::vector<const MeshDev*> mh, md;
+  for (int k : act) {
+    as.push_back(mk(k));
+    mh.push_back(&Tm.m[k]->md);
+    md.push_back(Tm.m[k]->d_md);
+  }
+  int r = many((int)as.size(), mh.data(), md.data(), as.data());
+  if (r == -6) {
+    r = 0;
+    for (size_t i = 0; i < as.size() && !r; ++i) r = one(Tm.m[act[i]], as[i]);
+  }
+  if (r) return team_fail(Tm, r == -6 ? DG_EUNSUPPORTED : DG_EDEVICE, "operator launch failed");
+  return DG_OK;
+}
 
 // Precision-dependent buffers and launchers.
 template <class T> struct PrecBuf;
@@ -1128,6 +1454,10 @@ template <> struct PrecBuf<double> {
   static int div(const MeshDev& m, int deg, const DivArgs<double>& a, hipStream_t s) { return launch_div64(m, deg, a, s); }
   static int div_split(const MeshDev& m, int deg, const DivArgs<double>& a, hipStream_t s) { return launch_div_split64(m, deg, a, s); }
   static int fdm(const MeshDev& m, int deg, const FdmArgs<double>& a, hipStream_t s) { return launch_fdm64(m, deg, a, s); }
+  static constexpr auto grad_seg = launch_grad_seg64;
+  static constexpr auto div_seg = launch_div_seg64;
+  static constexpr auto div_split_seg = launch_div_split_seg64;
+  static constexpr auto fdm_seg = launch_fdm_seg64;
 };
 template <> struct PrecBuf<float> {
   static float* q(dg_ctx* c) { return c->q32; }
@@ -1142,90 +1472,216 @@ template <> struct PrecBuf<float> {
   static int div(const MeshDev& m, int deg, const DivArgs<float>& a, hipStream_t s) { return launch_div32(m, deg, a, s); }
   static int div_split(const MeshDev& m, int deg, const DivArgs<float>& a, hipStream_t s) { return launch_div_split32(m, deg, a, s); }
   static int fdm(const MeshDev& m, int deg, const FdmArgs<float>& a, hipStream_t s) { return launch_fdm32(m, deg, a, s); }
+  static constexpr auto grad_seg = launch_grad_seg32;
+  static constexpr auto div_seg = launch_div_seg32;
+  static constexpr auto div_split_seg = launch_div_split_seg32;
+  static constexpr auto fdm_seg = launch_fdm_seg32;
 };
 
-// Weak divergence of the implicit energy flux h qv with the penalty / mass terms of a (a.h = h):
+// Weak gradient per member (args from mk), timing class cls.
+template <class T, class Make, class Bytes>
+dg_status grad_team(Team& Tm, const std::vector<int>& act, int cls, Make mk, Bytes bytes) {
+  using PB = PrecBuf<T>;
+  const hipStream_t s = Tm.s;
+  const int deg = act.empty() ? 0 : Tm.m[act[0]]->degree;
+  return op_launch<GradArgs<T>>(
+      Tm, act, cls, mk, bytes, [&](dg_ctx* c, const GradArgs<T>& a) { return PB::grad(c->md, c->degree, a, s); },
+      [&](int n, const MeshDev* const* mh, const MeshDev* const* md, const GradArgs<T>* a) {
+        return PB::grad_seg(n, mh, md, a, deg, s);
+      });
+}
+
+// Weak divergence of the implicit energy flux h qv with the penalty / mass terms (a.h = h):
 // plain C(h qv), or with the enthalpy split C((h - hbar) qv) + hbar C(qv) + M (d hbar/dz) qv_z,
 // the latter in one column pass.
-template <class T>
-int energy_div(dg_ctx* c, const DivArgs<T>& a) {
+template <class T, class Make, class Bytes>
+dg_status energy_div_team(Team& Tm, const std::vector<int>& act, int cls, Make mk, Bytes bytes) {
   using PB = PrecBuf<T>;
-  if (!c->opt.enthalpy_split) return PB::div(c->md, c->degree, a, c->stream);
-  DivArgs<T> a1 = a;
-  a1.h = PB::hp(c);
-  a1.hb = PB::hb(c);
-  a1.dhb = PB::dhb(c);
-  return PB::div_split(c->md, c->degree, a1, c->stream);
+  const hipStream_t s = Tm.s;
+  if (act.empty()) return DG_OK;
+  const int deg = Tm.m[act[0]]->degree;
+  if (!Tm.m[act[0]]->opt.enthalpy_split)
+    return op_launch<DivArgs<T>>(
+        Tm, act, cls, mk, bytes, [&](dg_ctx* c, const DivArgs<T>& a) { return PB::div(c->md, c->degree, a, s); },
+        [&](int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<T>* a) {
+          return PB::div_seg(n, mh, md, a, deg, s);
+        });
+  auto mk2 = [&](int k) {
+    dg_ctx* c = Tm.m[k];
+    DivArgs<T> a = mk(k);
+    a.h = PB::hp(c);
+    a.hb = PB::hb(c);
+    a.dhb = PB::dhb(c);
+    return a;
+  };
+  return op_launch<DivArgs<T>>(
+      Tm, act, cls, mk2, bytes, [&](dg_ctx* c, const DivArgs<T>& a) { return PB::div_split(c->md, c->degree, a, s); },
+      [&](int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<T>* a) {
+        return PB::div_split_seg(n, mh, md, a, deg, s);
+      });
 }
 
 // h - hbar for the enthalpy split, after h (and h32) changed
-void split_update(dg_ctx* c) {
-  if (!c->opt.enthalpy_split) return;
-  hipLaunchKernelGGL(k_sub, pw_grid(c->N), dim3(256), 0, c->stream, c->h, c->hb, c->N, c->hp);
-  if (c->opt.precision == DG_FP32_INNER)
-    hipLaunchKernelGGL(k_scale_cast, pw_grid(c->N), dim3(256), 0, c->stream, c->hp, 1.0, c->N, c->hp32);
+dg_status split_update_team(Team& Tm, const std::vector<int>& act) {
+  if (act.empty() || !Tm.m[act[0]]->opt.enthalpy_split) return DG_OK;
+  dg_status st = pw<PwSub>(Tm, act, [&](int k) { dg_ctx* c = Tm.m[k]; return PwSub{c->N, c->h, c->hb, c->hp}; });
+  if (st || Tm.m[act[0]]->opt.precision != DG_FP32_INNER) return st;
+  return pw<PwScaleCast>(Tm, act, [&](int k) { dg_ctx* c = Tm.m[k]; return PwScaleCast{c->N, c->hp, 1.0, c->hp32}; });
 }
 
-// w = A(h) p in precision T.  With dinv == null and scale == 1, p = v is taken as given; else
-// p = scale * dinv * v is formed on the fly and written to the z buffer by pass 1.
+// One term of a Helmholtz application: w = A(h) p in precision T for member k.  With dinv == null
+// and scale == 1, p = v is taken as given; else p = scale * dinv * v is formed on the fly and
+// written to the z buffer by pass 1.
+template <class T>
+struct ApItem {
+  int k;
+  double dta;
+  const T* v;
+  const T* dinv;
+  T scale;
+  T* w;
+  const double* dscale;  // preconditioned form: scale read from device memory (or null)
+};
+
 // Pass 1 writes h M^{-1} B p (and p); pass 2 takes C of it and the penalty and mass terms of p.
 template <class T>
-int apply_A(dg_ctx* c, double dta, const T* v, const T* dinv, T scale, T* w) {
+dg_status apply_A_team(Team& Tm, const std::vector<ApItem<T>>& it) {
   using PB = PrecBuf<T>;
-  const bool given = (dinv == nullptr && scale == T(1));
-  T* zout = given ? nullptr : PB::z(c);
-  const T* p = given ? v : PB::z(c);
-  // with the enthalpy split pass 1 leaves q = M^-1 B p and pass 2 applies the split flux of h q
-  const bool split = c->opt.enthalpy_split != 0;
-  GradArgs<T> g{v, dinv, scale, PB::q(c), split ? nullptr : PB::h(c), zout};
-  const double nb = (double)sizeof(T) * c->N;
-  int rg;
+  std::vector<int> act;
+  std::vector<int> idx(Tm.n(), -1);
+  for (size_t i = 0; i < it.size(); ++i) {
+    act.push_back(it[i].k);
+    idx[it[i].k] = (int)i;
+  }
+  auto given = [&](const ApItem<T>& e) { return e.dinv == nullptr && e.scale == T(1); };
   // pass 1: v (and dinv), h in; h M^-1 B p (d fields) and, if formed here, p out
-  TIMEDB(1, nb * ((dinv ? 2 : 1) + 1 + c->D + (given ? 0 : 1)), rg = PB::grad(c->md, c->degree, g, c->stream));
-  if (rg) return -1;
-  const double beta = c->opt.penalty_beta;
-  DivArgs<T> a{PB::q(c), split ? PB::h(c) : nullptr, p, nullptr, T(1), PB::lam(c), (T)(-dta * dta),
-               (T)(dta * beta / (2.0 * (kGamma - 1.0))), (T)(1.0 / (kGamma - 1.0)), 1, w};
-  int rd;
+  dg_status st = grad_team<T>(
+      Tm, act, 1,
+      [&](int k) {
+        const ApItem<T>& e = it[idx[k]];
+        dg_ctx* c = Tm.m[k];
+        const bool split = c->opt.enthalpy_split != 0;
+        return GradArgs<T>{e.v, e.dinv, e.scale, PB::q(c), split ? nullptr : PB::h(c), given(e) ? nullptr : PB::z(c)};
+      },
+      [&](int k) {
+        const ApItem<T>& e = it[idx[k]];
+        dg_ctx* c = Tm.m[k];
+        return (double)sizeof(T) * c->N * ((e.dinv ? 2 : 1) + 1 + c->D + (given(e) ? 0 : 1));
+      });
+  if (st) return st;
   // pass 2: d fields and p in; A p out
-  TIMEDB(2, nb * (c->D + 2), rd = energy_div<T>(c, a));
-  return rd;
+  return energy_div_team<T>(
+      Tm, act, 2,
+      [&](int k) {
+        const ApItem<T>& e = it[idx[k]];
+        dg_ctx* c = Tm.m[k];
+        const bool split = c->opt.enthalpy_split != 0;
+        const double beta = c->opt.penalty_beta;
+        return DivArgs<T>{PB::q(c), split ? PB::h(c) : nullptr, given(e) ? e.v : PB::z(c), nullptr, T(1), PB::lam(c),
+                          (T)(-e.dta * e.dta), (T)(e.dta * beta / (2.0 * (kGamma - 1.0))), (T)(1.0 / (kGamma - 1.0)),
+                          1, e.w, nullptr, nullptr, nullptr};
+      },
+      [&](int k) { dg_ctx* c = Tm.m[k]; return (double)sizeof(T) * c->N * (c->D + 2); });
 }
 
 // w = A P^{-1} (scale v): the right-preconditioned operator of the Krylov solve.
 template <class T>
-int apply_AP(dg_ctx* c, double dta, const T* v, const T* dinv, T scale, T* w, const double* dscale = nullptr) {
+dg_status apply_AP_team(Team& Tm, const std::vector<ApItem<T>>& it) {
   using PB = PrecBuf<T>;
-  if (c->opt.preconditioner == DG_PREC_CELL_FDM) {
-    FdmArgs<T> f{v, scale, PB::coef(c), PB::z(c), dscale};
-    int rf;
-    TIMEDB(4, 2.0 * sizeof(T) * c->N, rf = PB::fdm(c->md, c->degree, f, c->stream));
-    if (rf) return -1;
-    return apply_A<T>(c, dta, PB::z(c), (const T*)nullptr, T(1), w);
+  if (it.empty()) return DG_OK;
+  if (Tm.m[it[0].k]->opt.preconditioner != DG_PREC_CELL_FDM) return apply_A_team<T>(Tm, it);
+  std::vector<int> act;
+  std::vector<int> idx(Tm.n(), -1);
+  for (size_t i = 0; i < it.size(); ++i) {
+    act.push_back(it[i].k);
+    idx[it[i].k] = (int)i;
   }
-  return apply_A<T>(c, dta, v, dinv, scale, w);
+  const hipStream_t s = Tm.s;
+  const int deg = Tm.m[act[0]]->degree;
+  dg_status st = op_launch<FdmArgs<T>>(
+      Tm, act, 4,
+      [&](int k) {
+        const ApItem<T>& e = it[idx[k]];
+        dg_ctx* c = Tm.m[k];
+        return FdmArgs<T>{e.v, e.scale, PB::coef(c), PB::z(c), e.dscale};
+      },
+      [&](int k) { return 2.0 * sizeof(T) * Tm.m[k]->N; },
+      [&](dg_ctx* c, const FdmArgs<T>& a) { return PB::fdm(c->md, c->degree, a, s); },
+      [&](int n, const MeshDev* const* mh, const MeshDev* const* md, const FdmArgs<T>* a) {
+        return PB::fdm_seg(n, mh, md, a, deg, s);
+      });
+  if (st) return st;
+  std::vector<ApItem<T>> it2 = it;
+  for (auto& e : it2) {
+    e.v = PB::z(Tm.m[e.k]);
+    e.dinv = nullptr;
+    e.scale = T(1);
+    e.dscale = nullptr;
+  }
+  return apply_A_team<T>(Tm, it2);
 }
 
-// reduce nv partial sums to host
-// reduce nv partial sums into red[2..2+nv) and copy red[first..2+nv) to out (first = 0 also
-// brings the candidate norm and scale that k_reduce_norm left in red[0], red[1])
-dg_status reduce_to_host(dg_ctx* c, int nv, int G, double* out, int first = 2) {
-  if (nv < 1 || nv > 2 * kMaxV + 3) return fail(c, DG_EINVAL, "reduction of " + std::to_string(nv) + " values");
-  TIMED(6, hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(kRedThreads), 0, c->stream, c->part, G, c->red + 2));
-  HIPCHK(hipMemcpyAsync(c->hred, c->red + first, (2 + nv - first) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  memcpy(out, c->hred, (2 + nv - first) * sizeof(double));
+// One reduction pass per member (Gram-Schmidt form: nv basis vectors, x, optional y), its second
+// stage into the member's slot [2, 2 + nvals), nvals = 2 nv + 3 with y, else nv + 1.
+template <class T>
+struct DotItem {
+  int k;
+  const T* V;
+  const T* x;
+  const T* y;
+};
+template <class T>
+dg_status dots_team(Team& Tm, int nv, const std::vector<DotItem<T>>& it) {
+  if (it.empty()) return DG_OK;
+  const bool hasy = it[0].y != nullptr;
+  const int nvals = hasy ? 2 * nv + 3 : nv + 1;
+  if (!Tm.shared) {
+    for (const auto& e : it) {
+      dg_ctx* c = Tm.m[e.k];
+      const int G = red_grid(c->N);
+      {
+        Timed t_(Tm.tc, 3, (nv + (hasy ? 2.0 : 1.0)) * sizeof(T) * c->N);
+        launch_gs_dots<T>(nv, G, Tm.s, e.V, c->ld, e.x, e.y, c->part, c->N);
+      }
+      Timed t_(Tm.tc, 6);
+      hipLaunchKernelGGL(k_reduce, dim3(nvals), dim3(kRedThreads), 0, Tm.s, c->part, G, Tm.slot(e.k) + 2);
+    }
+    TCHK(Tm, hipGetLastError());
+    return DG_OK;
+  }
+  std::vector<DotsArgs<T>> as;
+  std::vector<RedArgs> rs;
+  for (const auto& e : it) {
+    dg_ctx* c = Tm.m[e.k];
+    as.push_back(DotsArgs<T>{e.V, c->ld, e.x, e.y, c->part, c->N});
+    rs.push_back(RedArgs{c->part, red_grid(c->N), Tm.slot(e.k) + 2});
+  }
+  const int n = (int)as.size();
+  seg_launch<DotsArgs<T>>(n, nullptr, [&](int i) { return red_grid(as[i].n); }, [&](int i) { return as[i]; },
+                          [&](const SegTab<DotsArgs<T>>& t, int g) {
+                            launch_gs_dots_seg<T>(nv, hasy, g, Tm.s, Shared<DotsArgs<T>>{t});
+                            return 0;
+                          });
+  seg_launch<RedArgs>(n, nullptr, [&](int) { return nvals; }, [&](int i) { return rs[i]; },
+                      [&](const SegTab<RedArgs>& t, int g) {
+                        hipLaunchKernelGGL(k_reduce_seg, dim3(g), dim3(kRedThreads), 0, Tm.s, Shared<RedArgs>{t});
+                        return 0;
+                      });
+  TCHK(Tm, hipGetLastError());
   return DG_OK;
 }
 
-template <class T>
-dg_status dot(dg_ctx* c, const T* a, const T* b, double* out) {
-  const int G = red_grid(c->N);
-  TIMEDB(3, 2.0 * sizeof(T) * c->N, launch_gs_dots<T>(0, G, c->stream, (const T*)nullptr, c->ld, a, b, c->part, c->N));
-  double r[3];
-  const dg_status st = reduce_to_host(c, 3, G, r);
-  *out = r[1];
-  return st;
+// x.y per member (one reduction pass, one round trip for all); out[k] for the members in act.
+template <class T, class X, class Y>
+dg_status dot_team(Team& Tm, const std::vector<int>& act, X xof, Y yof, std::vector<double>& out) {
+  std::vector<DotItem<T>> it;
+  for (int k : act) it.push_back(DotItem<T>{k, nullptr, xof(k), yof(k)});
+  dg_status st = dots_team<T>(Tm, 0, it);
+  if (st) return st;
+  if ((st = fetch(Tm, act))) return st;
+  out.assign(Tm.n(), 0.0);
+  for (int k : act) out[k] = Tm.hslot(k)[3];
+  return DG_OK;
 }
 
 struct CycleResult {
@@ -1267,8 +1723,46 @@ struct Arnoldi {
   }
 };
 
-// One GMRES(m) cycle on V[0] (unnormalised, norm beta), stopping at residual <= tol or maxits;
-// accumulates x += xscale * P^{-1} V y into the FP64 vector x.
+// One member's GMRES(m) cycle on V[0] (unnormalised, norm beta), stopping at residual <= tol or
+// maxits; accumulates x += xscale * P^{-1} V y into the FP64 vector x.
+template <class T>
+struct Cyc {
+  int k;
+  T* V;
+  T* w;
+  const T* dinv;
+  int m;
+  double beta, tol;
+  int maxits;
+  double* x;
+  double xscale;
+  double dta;
+  Arnoldi H;
+  std::vector<double> s, col, a, t, h;
+  double sigma, kappa, res, rho = 0.0;
+  int done = -1, jd = 0, fin = 0;
+  bool one_rt, run = true;
+  Coef ca{}, cb{};
+  double gsc = 0.0;
+  CycleResult cr;
+  Cyc(int k_, T* V_, T* w_, const T* dinv_, int m_, double beta_, double tol_, int maxits_, double* x_,
+      double xscale_, double dta_, bool one_rt_)
+      : k(k_), V(V_), w(w_), dinv(dinv_), m(m_), beta(beta_), tol(tol_), maxits(maxits_), x(x_), xscale(xscale_),
+        dta(dta_), H(m_, beta_), s(m_ + 1, 0.0), col(m_ + 1, 0.0), a(m_ + 1, 0.0), t(m_ + 1, 0.0), h(m_ + 1, 0.0),
+        sigma(1.0 / beta_), kappa(1.0), res(beta_), one_rt(one_rt_) {}
+  // Column j of the Hessenberg matrix receives the re-orthogonalisation of the candidate that
+  // followed it (coefficients av, norm rho2 of the re-orthogonalised candidate).
+  void finalize(int j, const double* av, double r2) {
+    const double f = 1.0 / (sigma * kappa);
+    for (int i = 0; i <= j; ++i) H.hr(i, j) += av ? av[i] * f : 0.0;
+    H.hr(j + 1, j) = r2 * f;
+    for (int i = 0; i <= j + 1; ++i) col[i] = H.hr(i, j);
+    res = H.rotate(j, col, true);
+    done = j;
+  }
+};
+
+// The GMRES cycles of the members in cy, iteration by iteration in lockstep.
 //
 // Arnoldi with classical Gram-Schmidt and one re-orthogonalisation, the latter delayed by one
 // step so that every step costs one reduction pass and one update pass over the basis:
@@ -1279,484 +1773,738 @@ struct Arnoldi {
 // next candidate.  Basis vectors are stored unnormalised with scale s_i (q_i = s_i V_i).  The
 // residual after column j is estimated from the candidate's norm; once it meets the tolerance
 // (or the cycle ends) one more reduction pass finalises column j exactly.
+//
+// Latency-bound sizes run one host round trip per iteration: the update pass leaves the
+// candidate's norm and scale on the device (k_reduce_norm), the next operator application reads
+// the scale there, and the host receives the norm with the next reduction.  The residual of
+// column j is then known only after the operator has been applied to the next candidate, so a
+// converging solve pays one extra application; large meshes keep the second round trip.
 template <class T>
-dg_status gmres_cycle(dg_ctx* c, double dta, T* V, T* w, const T* dinv, int m, double beta,
-                      double tol, int maxits, double* x, double xscale, CycleResult& cr) {
-  const long ld = c->ld, N = c->N;
-  const int G = red_grid(N);
-  const double tsz = (double)sizeof(T) * N;
-  Arnoldi H(m, beta);
-  std::vector<double> s(m + 1, 0.0), col(m + 1, 0.0), a(m + 1, 0.0), t(m + 1, 0.0), h(m + 1, 0.0);
+dg_status gmres_team(Team& Tm, std::vector<Cyc<T>>& cy) {
+  const std::string nanmsg = "non-finite value in the Krylov solve";
   double dots[2 * kMaxV + 3];
-  double sigma = 1.0 / beta;  // scale of the current candidate (1 / its norm)
-  double kappa = 1.0;         // candidate = kappa (A q_{j-1} - Q h_{j-1})
-  int done = -1;              // last column finalised
-  int jd = 0;
-  double res = beta;
-  cr = CycleResult{};
-  Coef ca{}, cb{};
-  auto nonfinite = [&](int n) {
-    for (int i = 0; i < n; ++i)
-      if (!std::isfinite(dots[i])) return true;
-    return false;
-  };
-  // Column col of the Hessenberg matrix receives the re-orthogonalisation of the candidate that
-  // followed it (coefficients av, norm rho of the re-orthogonalised candidate).
-  auto finalize = [&](int j, const double* av, double rho) {
-    const double f = 1.0 / (sigma * kappa);
-    for (int i = 0; i <= j; ++i) H.hr(i, j) += av ? av[i] * f : 0.0;
-    H.hr(j + 1, j) = rho * f;
-    for (int i = 0; i <= j + 1; ++i) col[i] = H.hr(i, j);
-    res = H.rotate(j, col, true);
-    done = j;
-  };
-  // Latency-bound sizes run one host round trip per iteration: the update pass leaves the
-  // candidate's norm and scale on the device (k_reduce_norm), the next operator application reads
-  // the scale there, and the host receives the norm with the next reduction.  The residual of
-  // column j is then known only after the operator has been applied to the next candidate, so a
-  // converging solve pays one extra application; large meshes keep the second round trip.
-  const bool one_rt = c->opt.preconditioner == DG_PREC_CELL_FDM && N <= kOneSyncMaxNodes;
-  double hb[2 * kMaxV + 5];
-  for (int j = 0; j < m; ++j) {
-    T* Vj = V + (size_t)j * ld;
-    const bool dev_sigma = one_rt && j > 0;
-    if (apply_AP<T>(c, dta, Vj, dinv, (T)sigma, w, dev_sigma ? c->red + 1 : nullptr))
-      return fail(c, DG_EDEVICE, "operator launch failed");
-    cr.its++;
+  for (int j = 0;; ++j) {
+    std::vector<int> A;
+    for (int i = 0; i < (int)cy.size(); ++i)
+      if (cy[i].run && Tm.alive(cy[i].k)) A.push_back(i);
+    if (A.empty()) break;
+    // operator on the current candidates
+    {
+      std::vector<ApItem<T>> it;
+      for (int i : A) {
+        Cyc<T>& c = cy[i];
+        const bool dev_sigma = c.one_rt && j > 0;
+        it.push_back(ApItem<T>{c.k, c.dta, c.V + (size_t)j * Tm.m[c.k]->ld, c.dinv, (T)c.sigma, c.w,
+                               dev_sigma ? Tm.slot(c.k) + 1 : nullptr});
+        c.cr.its++;
+      }
+      dg_status st = apply_AP_team<T>(Tm, it);
+      if (st) return st;
+    }
     // one reduction: Q_j^T V_j, Q_j^T w, V_j.V_j, V_j.w, w.w
-    TIMEDB(3, (j + 2.0) * tsz, launch_gs_dots<T>(j, G, c->stream, V, ld, Vj, w, c->part, N));
-    dg_status st;
-    if (dev_sigma) {
-      st = reduce_to_host(c, 2 * j + 3, G, hb, 0);
-      if (st) return st;
-      if (!std::isfinite(hb[0])) return fail(c, DG_ENAN, "non-finite value in the Krylov solve");
-      if (hb[0] == 0.0) {
-        // A q_{j-1} lies in span(Q_j) exactly: column j-1 is exact with a zero
-        finalize(j - 1, nullptr, 0.0);
-        break;
+    {
+      std::vector<DotItem<T>> it;
+      std::vector<int> ks;
+      for (int i : A) {
+        Cyc<T>& c = cy[i];
+        it.push_back(DotItem<T>{c.k, c.V, c.V + (size_t)j * Tm.m[c.k]->ld, c.w});
+        ks.push_back(c.k);
       }
-      sigma = hb[1];
-      std::copy(hb + 2, hb + 2 + 2 * j + 3, dots);
-    } else {
-      st = reduce_to_host(c, 2 * j + 3, G, dots);
+      dg_status st = dots_team<T>(Tm, j, it);
+      if (!st) st = fetch(Tm, ks);
       if (st) return st;
     }
-    if (nonfinite(2 * j + 3)) return fail(c, DG_ENAN, "non-finite value in the Krylov solve");
-    double aa = 0.0, ab = 0.0;
-    for (int i = 0; i < j; ++i) {
-      a[i] = s[i] * sigma * dots[i];       // q_i . (sigma V_j)
-      t[i] = s[i] * dots[j + i];           // q_i . w   (kept in t until the correction below)
-      aa += a[i] * a[i];
-      ab += a[i] * t[i];
-    }
-    const double cc = sigma * sigma * dots[2 * j];
-    const double dd = sigma * dots[2 * j + 1];
-    const double rho2 = cc - aa;
-    if (j > 0 && !(rho2 > 1e-26 * cc)) {
-      // the candidate lies in span(Q_j): lucky breakdown, column j-1 is exact with a zero
-      if (done < j - 1) finalize(j - 1, a.data(), 0.0);
-      jd = j;
-      break;
-    }
-    const double rho = std::sqrt(rho2);
-    if (j > 0 && done < j - 1) {
-      finalize(j - 1, a.data(), rho);
-      if (res <= tol) {
-        jd = j;
-        break;
-      }
-    }
-    // coefficients of A q_j on Q_{j+1}: (w - A Q_j a) / rho with A Q_j = Q_{j+1} Hr
-    for (int i = 0; i <= j; ++i) {
-      double ti = 0.0;
-      for (int k = 0; k < j; ++k) ti += H.hr(i, k) * a[k];
-      h[i] = ti;  // (Hr a)_i
-    }
-    for (int i = 0; i < j; ++i) {
-      const double bi = t[i];
-      t[i] = (bi - h[i]) / rho;  // h_j[i]
-    }
-    t[j] = ((dd - ab) / rho - h[j]) / rho;  // h_j[j]
-    // next candidate V_{j+1} = rho (A q_j - Q_{j+1} h_j) = w - rho Q_{j+1} gv,  gv = (Hr a)/rho + h_j
-    const double gj = h[j] / rho + t[j];
-    for (int i = 0; i < j; ++i) {
-      const double gi = h[i] / rho + t[i];
-      cb.c[i] = (rho * gi - gj * a[i]) * s[i];
-      ca.c[i] = a[i] * s[i] / sigma;
-    }
-    T* Vn = V + (size_t)(j + 1) * ld;
-    TIMEDB(5, (j + 3.0 + (j > 0 ? 1.0 : 0.0)) * tsz,
-           launch_gs_update<T>(j, G, c->stream, V, ld, ca, cb, gj * sigma, Vj, (const T*)w, Vn, c->part, N));
-    if (one_rt) {
-      TIMED(6, hipLaunchKernelGGL(k_reduce_norm, dim3(1), dim3(kRedThreads), 0, c->stream, c->part, G, c->red));
-      s[j] = sigma / rho;
-      kappa = rho;
-      for (int i = 0; i <= j; ++i) H.hr(i, j) = t[i];
-      jd = j + 1;
-      if (j + 1 == m || cr.its >= maxits) {
-        // finalise the last column exactly: Q^T V_{j+1} and |V_{j+1}|^2 with V_{j+1}'s scale
-        TIMEDB(3, (j + 2.0) * tsz, launch_gs_dots<T>(j + 1, G, c->stream, V, ld, Vn, (const T*)nullptr, c->part, N));
-        st = reduce_to_host(c, j + 2, G, hb, 0);
-        if (st) return st;
-        if (!std::isfinite(hb[0])) return fail(c, DG_ENAN, "non-finite value in the Krylov solve");
+    std::vector<int> Up;
+    for (int i : A) {
+      Cyc<T>& c = cy[i];
+      const double* hb = Tm.hslot(c.k);
+      if (c.one_rt && j > 0) {
+        if (!std::isfinite(hb[0])) { drop(Tm, c.k, DG_ENAN, nanmsg); continue; }
         if (hb[0] == 0.0) {
-          finalize(j, nullptr, 0.0);
-          break;
+          // A q_{j-1} lies in span(Q_j) exactly: column j-1 is exact with a zero
+          c.finalize(j - 1, nullptr, 0.0);
+          c.run = false;
+          continue;
         }
-        sigma = hb[1];
-        double a2 = 0.0;
-        for (int i = 0; i <= j; ++i) {
-          a[i] = s[i] * sigma * hb[2 + i];
-          a2 += a[i] * a[i];
+        c.sigma = hb[1];
+      }
+      std::copy(hb + 2, hb + 2 + 2 * j + 3, dots);
+      bool bad = false;
+      for (int q = 0; q < 2 * j + 3; ++q) bad |= !std::isfinite(dots[q]);
+      if (bad) { drop(Tm, c.k, DG_ENAN, nanmsg); continue; }
+      double aa = 0.0, ab = 0.0;
+      for (int q = 0; q < j; ++q) {
+        c.a[q] = c.s[q] * c.sigma * dots[q];  // q_q . (sigma V_j)
+        c.t[q] = c.s[q] * dots[j + q];        // q_q . w   (kept in t until the correction below)
+        aa += c.a[q] * c.a[q];
+        ab += c.a[q] * c.t[q];
+      }
+      const double cc = c.sigma * c.sigma * dots[2 * j];
+      const double dd = c.sigma * dots[2 * j + 1];
+      const double rho2 = cc - aa;
+      if (j > 0 && !(rho2 > 1e-26 * cc)) {
+        // the candidate lies in span(Q_j): lucky breakdown, column j-1 is exact with a zero
+        if (c.done < j - 1) c.finalize(j - 1, c.a.data(), 0.0);
+        c.jd = j;
+        c.run = false;
+        continue;
+      }
+      const double rho = std::sqrt(rho2);
+      if (j > 0 && c.done < j - 1) {
+        c.finalize(j - 1, c.a.data(), rho);
+        if (c.res <= c.tol) {
+          c.jd = j;
+          c.run = false;
+          continue;
         }
-        if (!std::isfinite(hb[2 + j + 1])) return fail(c, DG_ENAN, "non-finite value in the Krylov solve");
-        const double c2 = sigma * sigma * hb[2 + j + 1];
-        finalize(j, a.data(), std::sqrt(std::max(c2 - a2, 0.0)));
-        break;
       }
-      continue;
-    }
-    double nn;
-    st = reduce_to_host(c, 1, G, &nn);
-    if (st) return st;
-    if (!std::isfinite(nn)) return fail(c, DG_ENAN, "non-finite value in the Krylov solve");
-    s[j] = sigma / rho;
-    kappa = rho;
-    for (int i = 0; i <= j; ++i) H.hr(i, j) = t[i];
-    jd = j + 1;
-    if (nn == 0.0) {
-      // A q_j lies in span(Q_{j+1}) exactly
-      sigma = 1.0;
-      finalize(j, nullptr, 0.0);
-      break;
-    }
-    sigma = 1.0 / std::sqrt(nn);
-    // estimate with the candidate's norm, finalise when it meets the tolerance or the cycle ends
-    for (int i = 0; i <= j; ++i) col[i] = t[i];
-    col[j + 1] = std::sqrt(nn) / rho;
-    const double est = H.rotate(j, col, false);
-    if (est <= tol || j + 1 == m || cr.its >= maxits) {
-      TIMEDB(3, (j + 2.0) * tsz, launch_gs_dots<T>(j + 1, G, c->stream, V, ld, Vn, (const T*)nullptr, c->part, N));
-      st = reduce_to_host(c, j + 2, G, dots);
-      if (st) return st;
-      if (nonfinite(j + 2)) return fail(c, DG_ENAN, "non-finite value in the Krylov solve");
-      double a2 = 0.0;
-      for (int i = 0; i <= j; ++i) {
-        a[i] = s[i] * sigma * dots[i];
-        a2 += a[i] * a[i];
+      // coefficients of A q_j on Q_{j+1}: (w - A Q_j a) / rho with A Q_j = Q_{j+1} Hr
+      for (int q = 0; q <= j; ++q) {
+        double ti = 0.0;
+        for (int r = 0; r < j; ++r) ti += c.H.hr(q, r) * c.a[r];
+        c.h[q] = ti;  // (Hr a)_q
       }
-      const double c2 = sigma * sigma * dots[j + 1];
-      finalize(j, a.data(), std::sqrt(std::max(c2 - a2, 0.0)));
-      if (res <= tol || j + 1 == m || cr.its >= maxits) break;
+      for (int q = 0; q < j; ++q) c.t[q] = (c.t[q] - c.h[q]) / rho;  // h_j[q]
+      c.t[j] = ((dd - ab) / rho - c.h[j]) / rho;                      // h_j[j]
+      // next candidate V_{j+1} = rho (A q_j - Q_{j+1} h_j) = w - rho Q_{j+1} gv,
+      // gv = (Hr a)/rho + h_j
+      const double gj = c.h[j] / rho + c.t[j];
+      for (int q = 0; q < j; ++q) {
+        const double gi = c.h[q] / rho + c.t[q];
+        c.cb.c[q] = (rho * gi - gj * c.a[q]) * c.s[q];
+        c.ca.c[q] = c.a[q] * c.s[q] / c.sigma;
+      }
+      c.gsc = gj * c.sigma;
+      c.rho = rho;
+      Up.push_back(i);
     }
-  }
-  std::vector<double> y(jd, 0.0);
-  for (int i = jd - 1; i >= 0; --i) {
-    double v = H.g[i];
-    for (int k = i + 1; k < jd; ++k) v -= H.r(i, k) * y[k];
-    y[i] = v / H.r(i, i);
-  }
-  Coef cf{};
-  for (int i = 0; i < jd; ++i) cf.c[i] = xscale * y[i] * s[i];
-  if (jd > 0) {
-    if (c->opt.preconditioner == DG_PREC_CELL_FDM) {
-      // x += P^{-1} (V y): combine in FP64, precondition in FP64, add
-      TIMED(4, hipLaunchKernelGGL(k_zero, pw_grid(N), dim3(256), 0, c->stream, c->u, N));
-      TIMEDB(6, jd * tsz + 16.0 * N, launch_update<T>(jd, pw_grid(N), c->stream, (const T*)V, ld, cf, (const T*)nullptr, c->u, N));
-      FdmArgs<double> f{c->u, 1.0, c->coef, c->z};
-      int rf;
-      TIMEDB(4, 16.0 * N, rf = launch_fdm64(c->md, c->degree, f, c->stream));
-      if (rf) return fail(c, DG_EDEVICE, "preconditioner launch failed");
-      TIMED(4, hipLaunchKernelGGL(k_add, pw_grid(N), dim3(256), 0, c->stream, x, c->z, N));
+    if (Up.empty()) continue;
+    // update pass: q_j and the next candidate; its norm (on the device for one round trip)
+    if (!Tm.shared) {
+      for (int i : Up) {
+        Cyc<T>& c = cy[i];
+        dg_ctx* x = Tm.m[c.k];
+        const int G = red_grid(x->N);
+        T* Vj = c.V + (size_t)j * x->ld;
+        T* Vn = c.V + (size_t)(j + 1) * x->ld;
+        {
+          Timed t_(Tm.tc, 5, (j + 3.0 + (j > 0 ? 1.0 : 0.0)) * sizeof(T) * x->N);
+          launch_gs_update<T>(j, G, Tm.s, c.V, x->ld, c.ca, c.cb, c.gsc, Vj, (const T*)c.w, Vn, x->part, x->N);
+        }
+        Timed t_(Tm.tc, 6);
+        if (c.one_rt) hipLaunchKernelGGL(k_reduce_norm, dim3(1), dim3(kRedThreads), 0, Tm.s, x->part, G, Tm.slot(c.k));
+        else hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, Tm.s, x->part, G, Tm.slot(c.k) + 2);
+      }
     } else {
-      TIMEDB(6, (jd + 1.0) * tsz + 16.0 * N, launch_update<T>(jd, pw_grid(N), c->stream, (const T*)V, ld, cf, dinv, x, N));
+      std::vector<UpdArgs<T>> us;
+      std::vector<RedArgs> one, two;
+      int hi = 0;
+      for (int i : Up) {
+        Cyc<T>& c = cy[i];
+        double* hc = Tm.hcoef(c.k);
+        for (int q = 0; q < kMaxV; ++q) {
+          hc[q] = c.ca.c[q];
+          hc[kMaxV + q] = c.cb.c[q];
+        }
+        hi = std::max(hi, c.k);
+      }
+      TCHK(Tm, hipMemcpyAsync(Tm.lead->tcoef, Tm.hcoef(0), (size_t)(hi + 1) * kCoefStride * sizeof(double),
+                          hipMemcpyHostToDevice, Tm.s));
+      for (int i : Up) {
+        Cyc<T>& c = cy[i];
+        dg_ctx* x = Tm.m[c.k];
+        us.push_back(UpdArgs<T>{c.V, x->ld, Tm.dcoef(c.k), c.gsc, c.V + (size_t)j * x->ld, (const T*)c.w,
+                                c.V + (size_t)(j + 1) * x->ld, x->part, x->N});
+        (c.one_rt ? one : two).push_back(RedArgs{x->part, red_grid(x->N), c.one_rt ? Tm.slot(c.k) : Tm.slot(c.k) + 2});
+      }
+      seg_launch<UpdArgs<T>>((int)us.size(), nullptr, [&](int q) { return red_grid(us[q].n); },
+                             [&](int q) { return us[q]; },
+                             [&](const SegTab<UpdArgs<T>>& t, int g) {
+                               launch_gs_update_seg<T>(j, g, Tm.s, Shared<UpdArgs<T>>{t});
+                               return 0;
+                             });
+      seg_launch<RedArgs>((int)one.size(), nullptr, [&](int) { return 1; }, [&](int q) { return one[q]; },
+                          [&](const SegTab<RedArgs>& t, int g) {
+                            hipLaunchKernelGGL(k_reduce_norm_seg, dim3(g), dim3(kRedThreads), 0, Tm.s, Shared<RedArgs>{t});
+                            return 0;
+                          });
+      seg_launch<RedArgs>((int)two.size(), nullptr, [&](int) { return 1; }, [&](int q) { return two[q]; },
+                          [&](const SegTab<RedArgs>& t, int g) {
+                            hipLaunchKernelGGL(k_reduce_seg, dim3(g), dim3(kRedThreads), 0, Tm.s, Shared<RedArgs>{t});
+                            return 0;
+                          });
+    }
+    TCHK(Tm, hipGetLastError());
+    std::vector<int> two_k;
+    for (int i : Up) {
+      Cyc<T>& c = cy[i];
+      c.s[j] = c.sigma / c.rho;
+      c.kappa = c.rho;
+      for (int q = 0; q <= j; ++q) c.H.hr(q, j) = c.t[q];
+      c.jd = j + 1;
+      if (c.one_rt) {
+        if (j + 1 == c.m || c.cr.its >= c.maxits) c.fin = 1;
+      } else {
+        two_k.push_back(c.k);
+      }
+    }
+    if (!two_k.empty()) {
+      dg_status st = fetch(Tm, two_k);
+      if (st) return st;
+      for (int i : Up) {
+        Cyc<T>& c = cy[i];
+        if (c.one_rt) continue;
+        const double nn = Tm.hslot(c.k)[2];
+        if (!std::isfinite(nn)) { drop(Tm, c.k, DG_ENAN, nanmsg); continue; }
+        if (nn == 0.0) {
+          // A q_j lies in span(Q_{j+1}) exactly
+          c.sigma = 1.0;
+          c.finalize(j, nullptr, 0.0);
+          c.run = false;
+          continue;
+        }
+        c.sigma = 1.0 / std::sqrt(nn);
+        // estimate with the candidate's norm, finalise when it meets the tolerance or the cycle ends
+        for (int q = 0; q <= j; ++q) c.col[q] = c.t[q];
+        c.col[j + 1] = std::sqrt(nn) / c.rho;
+        const double est = c.H.rotate(j, c.col, false);
+        if (est <= c.tol || j + 1 == c.m || c.cr.its >= c.maxits) c.fin = 2;
+      }
+    }
+    // finalise the last column exactly: Q^T V_{j+1} and |V_{j+1}|^2 (with V_{j+1}'s scale)
+    std::vector<DotItem<T>> fit;
+    std::vector<int> fks;
+    for (int i : Up) {
+      Cyc<T>& c = cy[i];
+      if (!c.fin || !Tm.alive(c.k)) continue;
+      fit.push_back(DotItem<T>{c.k, c.V, c.V + (size_t)(j + 1) * Tm.m[c.k]->ld, nullptr});
+      fks.push_back(c.k);
+    }
+    if (fit.empty()) continue;
+    {
+      dg_status st = dots_team<T>(Tm, j + 1, fit);
+      if (!st) st = fetch(Tm, fks);
+      if (st) return st;
+    }
+    for (int i : Up) {
+      Cyc<T>& c = cy[i];
+      if (!c.fin || !Tm.alive(c.k)) continue;
+      const int fin = c.fin;
+      c.fin = 0;
+      const double* hb = Tm.hslot(c.k);
+      if (fin == 1) {
+        if (!std::isfinite(hb[0])) { drop(Tm, c.k, DG_ENAN, nanmsg); continue; }
+        if (hb[0] == 0.0) {
+          c.finalize(j, nullptr, 0.0);
+          c.run = false;
+          continue;
+        }
+        c.sigma = hb[1];
+      }
+      bool bad = false;
+      for (int q = 0; q < j + 2; ++q) bad |= !std::isfinite(hb[2 + q]);
+      if (bad) { drop(Tm, c.k, DG_ENAN, nanmsg); continue; }
+      double a2 = 0.0;
+      for (int q = 0; q <= j; ++q) {
+        c.a[q] = c.s[q] * c.sigma * hb[2 + q];
+        a2 += c.a[q] * c.a[q];
+      }
+      const double c2 = c.sigma * c.sigma * hb[2 + j + 1];
+      c.finalize(j, c.a.data(), std::sqrt(std::max(c2 - a2, 0.0)));
+      if (fin == 1 || c.res <= c.tol || j + 1 == c.m || c.cr.its >= c.maxits) c.run = false;
     }
   }
-  cr.res = res;
-  cr.converged = res <= tol;
+  // x += P^{-1} (V y) per member
+  std::vector<int> fz;
+  for (auto& c : cy) {
+    if (!Tm.alive(c.k)) continue;
+    c.cr.res = c.res;
+    c.cr.converged = c.res <= c.tol;
+    if (c.jd > 0) fz.push_back(c.k);
+  }
+  if (fz.empty()) return DG_OK;
+  std::vector<int> pos(Tm.n(), -1);
+  for (int i = 0; i < (int)cy.size(); ++i) pos[cy[i].k] = i;
+  const bool fdm = Tm.m[fz[0]]->opt.preconditioner == DG_PREC_CELL_FDM;
+  if (fdm) {
+    dg_status st = pw<PwZero>(Tm, fz, [&](int k) { return PwZero{Tm.m[k]->N, Tm.m[k]->u}; });
+    if (st) return st;
+  }
+  for (int k : fz) {
+    Cyc<T>& c = cy[pos[k]];
+    dg_ctx* x = Tm.m[k];
+    const double tsz = (double)sizeof(T) * x->N;
+    std::vector<double> y(c.jd, 0.0);
+    for (int i = c.jd - 1; i >= 0; --i) {
+      double v = c.H.g[i];
+      for (int q = i + 1; q < c.jd; ++q) v -= c.H.r(i, q) * y[q];
+      y[i] = v / c.H.r(i, i);
+    }
+    Coef cf{};
+    for (int i = 0; i < c.jd; ++i) cf.c[i] = c.xscale * y[i] * c.s[i];
+    Timed t_(Tm.tc, 6, c.jd * tsz + 16.0 * x->N + (fdm ? 0.0 : tsz));
+    // FDM: combine in FP64 into u, precondition in FP64 below, add; else x += dinv (V y)
+    launch_update<T>(c.jd, pw_grid(x->N), Tm.s, (const T*)c.V, x->ld, cf, fdm ? (const T*)nullptr : c.dinv,
+                     fdm ? x->u : c.x, x->N);
+  }
+  TCHK(Tm, hipGetLastError());
+  if (!fdm) return DG_OK;
+  const int deg = Tm.m[fz[0]]->degree;
+  const hipStream_t s = Tm.s;
+  dg_status st = op_launch<FdmArgs<double>>(
+      Tm, fz, 4, [&](int k) { dg_ctx* x = Tm.m[k]; return FdmArgs<double>{x->u, 1.0, x->coef, x->z, nullptr}; },
+      [&](int k) { return 16.0 * Tm.m[k]->N; },
+      [&](dg_ctx* x, const FdmArgs<double>& a) { return launch_fdm64(x->md, x->degree, a, s); },
+      [&](int n, const MeshDev* const* mh, const MeshDev* const* md, const FdmArgs<double>* a) {
+        return launch_fdm_seg64(n, mh, md, a, deg, s);
+      });
+  if (st) return st;
+  return pw<PwAdd>(Tm, fz, [&](int k) { return PwAdd{Tm.m[k]->N, cy[pos[k]].x, Tm.m[k]->z}; });
+}
+
+bool one_round_trip(const dg_ctx* c) {
+  return c->opt.preconditioner == DG_PREC_CELL_FDM && c->N <= kOneSyncMaxNodes;
+}
+
+struct SolveOut {
+  int its = 0, outer = 0;
+  double relres = 0.0;
+};
+
+// Solve A delta = r0 (FP64) for each member in act, delta zeroed here.
+dg_status solve64_team(Team& Tm, const std::vector<int>& act, const std::vector<double>& dta,
+                       std::vector<SolveOut>& out) {
+  dg_status st = pw<PwZero>(Tm, act, [&](int k) { return PwZero{Tm.m[k]->N, Tm.m[k]->delta}; });
+  if (st) return st;
+  std::vector<double> b2;
+  st = dot_team<double>(Tm, act, [&](int k) { return Tm.m[k]->r0; }, [&](int k) { return Tm.m[k]->r0; }, b2);
+  if (st) return st;
+  std::vector<double> bn(Tm.n(), 0.0), tol(Tm.n(), 0.0), beta(Tm.n(), 0.0);
+  std::vector<int> go;
+  for (int k : act) {
+    dg_ctx* c = Tm.m[k];
+    bn[k] = std::sqrt(b2[k]);
+    if (!std::isfinite(bn[k])) { drop(Tm, k, DG_ENAN, "non-finite right-hand side"); continue; }
+    tol[k] = std::max(c->opt.gmres_rtol * bn[k], c->opt.gmres_atol);
+    out[k] = SolveOut{};
+    if (bn[k] == 0.0 || bn[k] <= tol[k]) continue;
+    beta[k] = bn[k];
+    go.push_back(k);
+  }
+  if (!Tm.shared) {
+    for (int k : go) TCHK(Tm, hipMemcpyAsync(Tm.m[k]->V, Tm.m[k]->r0, Tm.m[k]->N * sizeof(double), hipMemcpyDeviceToDevice, Tm.s));
+  } else if ((st = pw<PwCopy>(Tm, go, [&](int k) { return PwCopy{Tm.m[k]->N, Tm.m[k]->r0, Tm.m[k]->V}; }))) {
+    return st;
+  }
+  while (!go.empty()) {
+    std::vector<Cyc<double>> cy;
+    for (int k : go) {
+      dg_ctx* c = Tm.m[k];
+      cy.emplace_back(k, c->V, c->w, c->dinv, c->m, beta[k], tol[k], c->opt.gmres_maxit - out[k].its, c->delta, 1.0,
+                      dta[k], one_round_trip(c));
+    }
+    if ((st = gmres_team<double>(Tm, cy))) return st;
+    std::vector<int> rs;
+    for (auto& c : cy) {
+      const int k = c.k;
+      if (!Tm.alive(k)) continue;
+      out[k].its += c.cr.its;
+      out[k].relres = c.cr.res / bn[k];
+      if (c.cr.converged) continue;
+      if (out[k].its >= Tm.m[k]->opt.gmres_maxit) {
+        drop(Tm, k, DG_ENOCONV, "GMRES did not reach its tolerance within gmres_maxit iterations");
+        continue;
+      }
+      rs.push_back(k);
+    }
+    go.clear();
+    if (rs.empty()) break;
+    // restart from the true residual
+    std::vector<ApItem<double>> it;
+    for (int k : rs) it.push_back(ApItem<double>{k, dta[k], Tm.m[k]->delta, nullptr, 1.0, Tm.m[k]->w, nullptr});
+    if ((st = apply_A_team<double>(Tm, it))) return st;
+    if ((st = pw<PwSub>(Tm, rs, [&](int k) { dg_ctx* c = Tm.m[k]; return PwSub{c->N, c->r0, c->w, c->V}; }))) return st;
+    if ((st = dot_team<double>(Tm, rs, [&](int k) { return Tm.m[k]->V; }, [&](int k) { return Tm.m[k]->V; }, b2)))
+      return st;
+    for (int k : rs) {
+      beta[k] = std::sqrt(b2[k]);
+      out[k].relres = beta[k] / bn[k];
+      if (beta[k] > tol[k]) go.push_back(k);
+    }
+  }
   return DG_OK;
 }
 
-// Solve A delta = r0 (FP64), delta zeroed here.  Returns iterations and relative residual.
-dg_status solve64(dg_ctx* c, double dta, int& its, double& relres) {
-  const long N = c->N;
-  TIMED(4, hipLaunchKernelGGL(k_zero, pw_grid(N), dim3(256), 0, c->stream, c->delta, N));
-  double b2;
-  dg_status st = dot<double>(c, c->r0, c->r0, &b2);
-  if (st) return st;
-  const double bn = std::sqrt(b2);
-  if (!std::isfinite(bn)) return fail(c, DG_ENAN, "non-finite right-hand side");
-  const double tol = std::max(c->opt.gmres_rtol * bn, c->opt.gmres_atol);
-  its = 0;
-  relres = 0.0;
-  if (bn == 0.0 || bn <= tol) return DG_OK;
-  HIPCHK(hipMemcpyAsync(c->V, c->r0, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  double beta = bn;
-  while (true) {
-    CycleResult cr;
-    st = gmres_cycle<double>(c, dta, c->V, c->w, c->dinv, c->m, beta, tol, c->opt.gmres_maxit - its,
-                             c->delta, 1.0, cr);
-    if (st) return st;
-    its += cr.its;
-    relres = cr.res / bn;
-    if (cr.converged) return DG_OK;
-    if (its >= c->opt.gmres_maxit) break;
-    // restart from the true residual
-    if (apply_A<double>(c, dta, c->delta, nullptr, 1.0, c->w)) return fail(c, DG_EDEVICE, "operator launch failed");
-    TIMED(4, hipLaunchKernelGGL(k_sub, pw_grid(N), dim3(256), 0, c->stream, c->r0, c->w, N, c->V));
-    st = dot<double>(c, c->V, c->V, &b2);
-    if (st) return st;
-    beta = std::sqrt(b2);
-    relres = beta / bn;
-    if (beta <= tol) return DG_OK;
-  }
-  return fail(c, DG_ENOCONV, "GMRES did not reach its tolerance within gmres_maxit iterations");
-}
-
 // Mixed precision: FP64 defect correction around FP32 GMRES cycles.
-dg_status solve_mixed(dg_ctx* c, double dta, int& its, int& outer, double& relres) {
-  const long N = c->N;
-  TIMED(4, hipLaunchKernelGGL(k_zero, pw_grid(N), dim3(256), 0, c->stream, c->delta, N));
-  double b2;
-  dg_status st = dot<double>(c, c->r0, c->r0, &b2);
+dg_status solve_mixed_team(Team& Tm, const std::vector<int>& act, const std::vector<double>& dta,
+                           std::vector<SolveOut>& out) {
+  dg_status st = pw<PwZero>(Tm, act, [&](int k) { return PwZero{Tm.m[k]->N, Tm.m[k]->delta}; });
   if (st) return st;
-  const double bn = std::sqrt(b2);
-  if (!std::isfinite(bn)) return fail(c, DG_ENAN, "non-finite right-hand side");
-  const double tol = std::max(c->opt.gmres_rtol * bn, c->opt.gmres_atol);
-  its = 0;
-  outer = 0;
-  relres = 0.0;
-  if (bn == 0.0 || bn <= tol) return DG_OK;
-  HIPCHK(hipMemcpyAsync(c->rr, c->r0, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  double rn = bn;
-  const int max_outer = 100;
-  while (rn > tol) {
-    if (outer >= max_outer || its >= c->opt.gmres_maxit)
-      return fail(c, DG_ENOCONV, "mixed-precision defect correction did not converge");
-    TIMED(4, hipLaunchKernelGGL(k_scale_cast, pw_grid(N), dim3(256), 0, c->stream, c->rr, 1.0 / rn, N, c->V32));
-    double v2;
-    st = dot<float>(c, c->V32, c->V32, &v2);
-    if (st) return st;
-    const double vb = std::sqrt(v2);
-    CycleResult cr;
-    st = gmres_cycle<float>(c, dta, c->V32, c->w32, c->dinv32, c->m32, vb, c->opt.inner_rtol * vb,
-                            c->opt.inner_maxit, c->delta, rn, cr);
-    if (st) return st;
-    its += cr.its;
-    outer++;
-    // FP64 residual of the accumulated correction
-    if (apply_A<double>(c, dta, c->delta, nullptr, 1.0, c->w)) return fail(c, DG_EDEVICE, "operator launch failed");
-    TIMED(4, hipLaunchKernelGGL(k_sub, pw_grid(N), dim3(256), 0, c->stream, c->r0, c->w, N, c->rr));
-    st = dot<double>(c, c->rr, c->rr, &b2);
-    if (st) return st;
-    rn = std::sqrt(b2);
+  std::vector<double> b2;
+  st = dot_team<double>(Tm, act, [&](int k) { return Tm.m[k]->r0; }, [&](int k) { return Tm.m[k]->r0; }, b2);
+  if (st) return st;
+  std::vector<double> bn(Tm.n(), 0.0), tol(Tm.n(), 0.0), rn(Tm.n(), 0.0);
+  std::vector<int> go;
+  for (int k : act) {
+    dg_ctx* c = Tm.m[k];
+    bn[k] = std::sqrt(b2[k]);
+    if (!std::isfinite(bn[k])) { drop(Tm, k, DG_ENAN, "non-finite right-hand side"); continue; }
+    tol[k] = std::max(c->opt.gmres_rtol * bn[k], c->opt.gmres_atol);
+    out[k] = SolveOut{};
+    if (bn[k] == 0.0 || bn[k] <= tol[k]) continue;
+    rn[k] = bn[k];
+    go.push_back(k);
   }
-  relres = rn / bn;
+  if (!Tm.shared) {
+    for (int k : go) TCHK(Tm, hipMemcpyAsync(Tm.m[k]->rr, Tm.m[k]->r0, Tm.m[k]->N * sizeof(double), hipMemcpyDeviceToDevice, Tm.s));
+  } else if ((st = pw<PwCopy>(Tm, go, [&](int k) { return PwCopy{Tm.m[k]->N, Tm.m[k]->r0, Tm.m[k]->rr}; }))) {
+    return st;
+  }
+  const int max_outer = 100;
+  while (!go.empty()) {
+    std::vector<int> g2;
+    for (int k : go) {
+      if (out[k].outer >= max_outer || out[k].its >= Tm.m[k]->opt.gmres_maxit)
+        drop(Tm, k, DG_ENOCONV, "mixed-precision defect correction did not converge");
+      else g2.push_back(k);
+    }
+    go = g2;
+    if (go.empty()) break;
+    if ((st = pw<PwScaleCast>(Tm, go, [&](int k) { dg_ctx* c = Tm.m[k]; return PwScaleCast{c->N, c->rr, 1.0 / rn[k], c->V32}; })))
+      return st;
+    std::vector<double> v2;
+    if ((st = dot_team<float>(Tm, go, [&](int k) { return Tm.m[k]->V32; }, [&](int k) { return Tm.m[k]->V32; }, v2)))
+      return st;
+    std::vector<Cyc<float>> cy;
+    for (int k : go) {
+      dg_ctx* c = Tm.m[k];
+      const double vb = std::sqrt(v2[k]);
+      cy.emplace_back(k, c->V32, c->w32, c->dinv32, c->m32, vb, c->opt.inner_rtol * vb, c->opt.inner_maxit, c->delta,
+                      rn[k], dta[k], one_round_trip(c));
+    }
+    if ((st = gmres_team<float>(Tm, cy))) return st;
+    std::vector<int> al;
+    for (auto& c : cy) {
+      if (!Tm.alive(c.k)) continue;
+      out[c.k].its += c.cr.its;
+      out[c.k].outer++;
+      al.push_back(c.k);
+    }
+    // FP64 residual of the accumulated correction
+    std::vector<ApItem<double>> it;
+    for (int k : al) it.push_back(ApItem<double>{k, dta[k], Tm.m[k]->delta, nullptr, 1.0, Tm.m[k]->w, nullptr});
+    if ((st = apply_A_team<double>(Tm, it))) return st;
+    if ((st = pw<PwSub>(Tm, al, [&](int k) { dg_ctx* c = Tm.m[k]; return PwSub{c->N, c->r0, c->w, c->rr}; }))) return st;
+    if ((st = dot_team<double>(Tm, al, [&](int k) { return Tm.m[k]->rr; }, [&](int k) { return Tm.m[k]->rr; }, b2)))
+      return st;
+    go.clear();
+    for (int k : al) {
+      rn[k] = std::sqrt(b2[k]);
+      out[k].relres = rn[k] / bn[k];
+      if (rn[k] > tol[k]) go.push_back(k);
+    }
+  }
   return DG_OK;
 }
 
 // ----------------------------------------------------------------------------------- operators
-dg_status explicit_residual(dg_ctx* c, const double* U, double* R) {
-  int re;
-  if (c->md.nq > 0)
-    TIMEDB(0, 16.0 * c->F * c->N, re = launch_explicit_oi(c->md, c->degree, U, R, c->stream));
-  else
-    TIMEDB(0, 16.0 * c->F * c->N, re = launch_explicit(c->md, c->degree, U, R, c->stream));
-  LCHK(re);
-  if (c->tau) {
-    if (c->D == 2)
-      TIMED(4, hipLaunchKernelGGL((k_friction<2>), pw_grid(c->N), dim3(256), 0, c->stream, U, c->tau,
-                                  c->desc.sponge[4], c->N, c->ld, R));
-    else
-      TIMED(4, hipLaunchKernelGGL((k_friction<3>), pw_grid(c->N), dim3(256), 0, c->stream, U, c->tau,
-                                  c->desc.sponge[4], c->N, c->ld, R));
+dg_status explicit_team(Team& Tm, const std::vector<int>& act, const std::vector<const double*>& U,
+                        const std::vector<double*>& R) {
+  if (act.empty()) return DG_OK;
+  const hipStream_t s = Tm.s;
+  const int deg = Tm.m[act[0]]->degree;
+  dg_status st = op_launch<ExpArgs>(
+      Tm, act, 0, [&](int k) { return ExpArgs{U[k], R[k]}; },
+      [&](int k) { return 16.0 * Tm.m[k]->F * Tm.m[k]->N; },
+      [&](dg_ctx* c, const ExpArgs& a) {
+        return c->md.nq > 0 ? launch_explicit_oi(c->md, c->degree, a.U, a.R, s) : launch_explicit(c->md, c->degree, a.U, a.R, s);
+      },
+      [&](int n, const MeshDev* const* mh, const MeshDev* const* md, const ExpArgs* a) {
+        return launch_explicit_seg(n, mh, md, a, deg, s);
+      });
+  if (st) return st;
+  std::vector<int> sp;
+  for (int k : act)
+    if (Tm.m[k]->tau) sp.push_back(k);
+  if (sp.empty()) return DG_OK;
+  if (Tm.m[sp[0]]->D == 2)
+    return pw<PwFriction<2>>(Tm, sp, [&](int k) { dg_ctx* c = Tm.m[k]; return PwFriction<2>{c->N, c->ld, U[k], c->tau, c->desc.sponge[4], R[k]}; });
+  return pw<PwFriction<3>>(Tm, sp, [&](int k) { dg_ctx* c = Tm.m[k]; return PwFriction<3>{c->N, c->ld, U[k], c->tau, c->desc.sponge[4], R[k]}; });
+}
+
+// per-cell sound speed of every member from its h
+dg_status lam_team(Team& Tm, const std::vector<int>& act, bool f32) {
+  for (int k : act) {
+    dg_ctx* c = Tm.m[k];
+    Timed t_(Tm.tc, 4);
+    hipLaunchKernelGGL(k_lam, dim3((c->hm.ncell + 3) / 4), dim3(256), 0, Tm.s, c->h, c->NL, c->hm.ncell, c->lam,
+                       f32 ? c->lam32 : (float*)nullptr);
   }
+  TCHK(Tm, hipGetLastError());
   return DG_OK;
 }
 
 // F_I(U) into F; uses pp, h, lam, q as scratch
-dg_status implicit_term(dg_ctx* c, const double* U, double* F) {
-  const long N = c->N, ld = c->ld;
-  const int D = c->D;
-  if (D == 2)
-    TIMED(4, hipLaunchKernelGGL((k_pressure_h<2>), pw_grid(N), dim3(256), 0, c->stream, U, c->pbar, N, ld, c->pp, c->h));
-  else
-    TIMED(4, hipLaunchKernelGGL((k_pressure_h<3>), pw_grid(N), dim3(256), 0, c->stream, U, c->pbar, N, ld, c->pp, c->h));
-  TIMED(4, hipLaunchKernelGGL(k_lam, dim3((c->hm.ncell + 3) / 4), dim3(256), 0, c->stream, c->h, c->NL,
-                     c->hm.ncell, c->lam, (float*)nullptr));
-  TIMED(4, split_update(c));
-  GradArgs<double> g{c->pp, nullptr, 1.0, c->q, nullptr, nullptr};
-  int rg;
-  TIMED(7, rg = launch_grad64(c->md, c->degree, g, c->stream));
-  LCHK(rg);
-  if (D == 2)
-    TIMED(4, hipLaunchKernelGGL((k_fi_momentum<2>), pw_grid(N), dim3(256), 0, c->stream, c->q, U, c->rbar, N, ld, F));
-  else
-    TIMED(4, hipLaunchKernelGGL((k_fi_momentum<3>), pw_grid(N), dim3(256), 0, c->stream, c->q, U, c->rbar, N, ld, F));
-  const double beta = c->opt.penalty_beta;
-  DivArgs<double> a{U + ld, c->h, c->pp, nullptr, 1.0, c->lam, -1.0,
-                    -beta / (2.0 * (kGamma - 1.0)), 0.0, 0, F + (size_t)(1 + D) * ld};
-  int rd;
-  TIMED(7, rd = energy_div<double>(c, a));
-  LCHK(rd);
-  return DG_OK;
+template <int D>
+dg_status implicit_team(Team& Tm, const std::vector<int>& act, const std::vector<const double*>& U,
+                        const std::vector<double*>& F) {
+  dg_status st = pw<PwPressureH<D>>(Tm, act, [&](int k) {
+    dg_ctx* c = Tm.m[k];
+    return PwPressureH<D>{c->N, c->ld, U[k], c->pbar, c->pp, c->h};
+  });
+  if (st || (st = lam_team(Tm, act, false)) || (st = split_update_team(Tm, act))) return st;
+  st = grad_team<double>(
+      Tm, act, 7, [&](int k) { dg_ctx* c = Tm.m[k]; return GradArgs<double>{c->pp, nullptr, 1.0, c->q, nullptr, nullptr}; },
+      [&](int) { return 0.0; });
+  if (st) return st;
+  st = pw<PwFiMomentum<D>>(Tm, act, [&](int k) {
+    dg_ctx* c = Tm.m[k];
+    return PwFiMomentum<D>{c->N, c->ld, c->q, U[k], c->rbar, F[k]};
+  });
+  if (st) return st;
+  return energy_div_team<double>(
+      Tm, act, 7,
+      [&](int k) {
+        dg_ctx* c = Tm.m[k];
+        const double beta = c->opt.penalty_beta;
+        return DivArgs<double>{U[k] + c->ld, c->h, c->pp, nullptr, 1.0, c->lam, -1.0, -beta / (2.0 * (kGamma - 1.0)),
+                               0.0, 0, F[k] + (size_t)(1 + D) * c->ld, nullptr, nullptr, nullptr};
+      },
+      [&](int) { return 0.0; });
 }
 
+// mass sum(w J rho) and max |w| of each member's state into its slot ([3] and [kMaxAt])
+dg_status diagnostics_team(Team& Tm, const std::vector<int>& act, const std::vector<const double*>& U) {
+  std::vector<DotItem<double>> it;
+  for (int k : act) it.push_back(DotItem<double>{k, nullptr, Tm.m[k]->wJ, U[k]});
+  dg_status st = dots_team<double>(Tm, 0, it);
+  if (st) return st;
+  for (int k : act) {
+    dg_ctx* c = Tm.m[k];
+    const int G = red_grid(c->N);
+    hipLaunchKernelGGL(k_maxabs_ratio, dim3(G), dim3(kRedThreads), 0, Tm.s, U[k] + (size_t)c->D * c->ld, U[k],
+                       c->part + (size_t)3 * kMaxGrid, c->N);
+    hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(kRedThreads), 0, Tm.s, c->part + (size_t)3 * kMaxGrid, G,
+                       Tm.slot(k) + kMaxAt);
+  }
+  TCHK(Tm, hipGetLastError());
+  return fetch(Tm, act);
+}
+
+// One IMEX-RK2 step of every member (U[k], dt[k]); per-member status in Tm.st.
 template <int D>
-dg_status step_impl(dg_ctx* c, double* U, double dt, dg_step_stats* stats) {
-  const long N = c->N, ld = c->ld;
-  const dim3 pg = pw_grid(N), bs(256);
-  hipStream_t s = c->stream;
+dg_status step_team(Team& Tm, double* const* U, const double* dt, dg_step_stats* stats) {
+  const int n = Tm.n();
   const double g_ = 1.0 - 1.0 / std::sqrt(2.0), d_ = 1.0 / (2.0 * std::sqrt(2.0));
   const double al = (3.0 + 2.0 * std::sqrt(2.0)) / 6.0;
   const double A[3][3] = {{0, 0, 0}, {2 * g_, 0, 0}, {1 - al, al, 0}};
   const double At[3][3] = {{0, 0, 0}, {g_, g_, 0}, {d_, d_, g_}};
   const double bw[3] = {d_, d_, g_};
-  dg_step_stats st{};
-  dg_status rc;
-  c->ev_n = 0;
-  c->pev_n = 0;
-  for (double& b : c->kbytes) b = 0.0;
+  std::vector<dg_step_stats> S(n);
+  for (auto& x : S) x = dg_step_stats{};
+  if (Tm.tc) {
+    Tm.tc->ev_n = 0;
+    Tm.tc->pev_n = 0;
+    for (double& b : Tm.tc->kbytes) b = 0.0;
+  }
   const auto t0 = std::chrono::steady_clock::now();
-  const int G = red_grid(N);
-
+  std::vector<int> act;
+  for (int k = 0; k < n; ++k)
+    if (Tm.alive(k)) act.push_back(k);
+  std::vector<const double*> Uc(n), Usc(n);
+  std::vector<double*> R(n);
+  for (int k = 0; k < n; ++k) {
+    Uc[k] = U[k];
+    Usc[k] = Tm.m[k]->Us;
+  }
+  dg_status st = DG_OK;
+#define STEP_CHK(expr) \
+  do {                 \
+    if ((st = (expr))) return st; \
+    act = alive_of(Tm, act); \
+  } while (0)
+  auto FEof = [&](int j) { for (int k = 0; k < n; ++k) R[k] = Tm.m[k]->FE[j]; return R; };
+  auto FIof = [&](int j) { for (int k = 0; k < n; ++k) R[k] = Tm.m[k]->FI[j]; return R; };
   {
-    Phase ph(c, 0);
-    if ((rc = explicit_residual(c, U, c->FE[0]))) return rc;
+    Phase ph(Tm.tc, 0);
+    STEP_CHK(explicit_team(Tm, act, Uc, FEof(0)));
   }
   {
-    Phase ph(c, 1);
-    if ((rc = implicit_term(c, U, c->FI[0]))) return rc;
+    Phase ph(Tm.tc, 1);
+    STEP_CHK(implicit_team<D>(Tm, act, Uc, FIof(0)));
   }
-  // stage state starts from U^n: momentum, and p' (left in c->pp by implicit_term)
+  // stage state starts from U^n: momentum, and p' (left in pp by the implicit term)
   {
-    Phase ph(c, 2);
-    TIMED(4, hipLaunchKernelGGL((k_copy_m<D>), pg, bs, 0, s, U, ld, N, c->Us));
+    Phase ph(Tm.tc, 2);
+    STEP_CHK(pw<PwCopyM<D>>(Tm, act, [&](int k) { dg_ctx* c = Tm.m[k]; return PwCopyM<D>{c->N, c->ld, U[k], c->Us}; }));
   }
-  const double beta = c->opt.penalty_beta;
+  std::vector<double> dta(n, 0.0);
+  std::vector<SolveOut> so(n);
   for (int i = 1; i <= 2; ++i) {
-    const double aii = At[i][i], dta = dt * aii;
+    const double aii = At[i][i];
+    for (int k = 0; k < n; ++k) dta[k] = dt[k] * aii;
     // predictor; Us[0] <- rho_i, mt, et, mp
     {
-      Phase ph(c, 2);
-      TIMED(4, hipLaunchKernelGGL((k_predictor<D>), pg, bs, 0, s, U, c->FE[0], c->FE[1], c->FI[0], c->FI[1], i,
-                                  A[i][0], A[i][1], At[i][0], At[i][1], dt, dta, c->rbar, N, ld, c->Us, c->mt,
-                                  c->et, c->mp));
+      Phase ph(Tm.tc, 2);
+      STEP_CHK(pw<PwPredictor<D>>(Tm, act, [&](int k) {
+        dg_ctx* c = Tm.m[k];
+        return PwPredictor<D>{c->N, c->ld, U[k], c->FE[0], c->FE[1], c->FI[0], c->FI[1], i, A[i][0], A[i][1],
+                              At[i][0], At[i][1], dt[k], dta[k], c->rbar, c->Us, c->mt, c->et, c->mp};
+      }));
     }
-    for (int l = 0; l < c->opt.fp_iters; ++l) {
-      Phase ph3(c, 3);
-      TIMED(4, hipLaunchKernelGGL(k_coef, pg, bs, 0, s, c->Us, c->pbar, c->pp, c->wJ, c->d_cell, c->NL, D,
-                         c->hm.L[0], c->hm.L[1], c->hm.L[2], c->hm.nb[0], c->hm.nb[1], c->hm.nb[2],
-                         c->degree + 1, dta, N, c->h, c->dinv,
-                         c->opt.precision == DG_FP32_INNER ? c->h32 : (float*)nullptr,
-                         c->opt.precision == DG_FP32_INNER ? c->dinv32 : (float*)nullptr));
+    for (int l = 0; l < 8; ++l) {
+      std::vector<int> fa;
+      for (int k : act)
+        if (l < Tm.m[k]->opt.fp_iters) fa.push_back(k);
+      if (fa.empty()) break;
+      const bool mixed = Tm.m[fa[0]]->opt.precision == DG_FP32_INNER;
       {
-        const bool mixed = c->opt.precision == DG_FP32_INNER;
-        int rcc;
-        TIMED(4, rcc = launch_cellcoef(c->md, c->degree, c->h, c->wJ, dta, c->lam, mixed ? c->lam32 : nullptr,
-                                       c->coef, mixed ? c->coef32 : nullptr, s));
-        LCHK(rcc);
+        Phase ph3(Tm.tc, 3);
+        STEP_CHK(pw<PwCoef>(Tm, fa, [&](int k) {
+          dg_ctx* c = Tm.m[k];
+          return PwCoef{c->N, c->Us, c->pbar, c->pp, c->wJ, c->d_cell, c->NL, D, c->hm.L[0], c->hm.L[1], c->hm.L[2],
+                        c->hm.nb[0], c->hm.nb[1], c->hm.nb[2], c->degree + 1, dta[k], c->h, c->dinv,
+                        mixed ? c->h32 : (float*)nullptr, mixed ? c->dinv32 : (float*)nullptr};
+        }));
+        for (int k : fa) {
+          dg_ctx* c = Tm.m[k];
+          int rcc;
+          {
+            Timed t_(Tm.tc, 4);
+            rcc = launch_cellcoef(c->md, c->degree, c->h, c->wJ, dta[k], c->lam, mixed ? c->lam32 : nullptr, c->coef,
+                                  mixed ? c->coef32 : nullptr, Tm.s);
+          }
+          if (rcc) return team_fail(Tm, DG_EDEVICE, "launch failed: per-cell coefficients");
+        }
+        STEP_CHK(split_update_team(Tm, fa));
       }
-      TIMED(4, split_update(c));
-      ph3.end();
+      fa = alive_of(Tm, fa);
       {
-        Phase ph(c, 4);
+        Phase ph(Tm.tc, 4);
         // b = -dta C(h m') + M (e~ - rho k - pbar/(gamma-1))
-        DivArgs<double> a{c->mp, c->h, nullptr, nullptr, 1.0, c->lam, -dta, 0.0, 0.0, 1, c->b};
-        int rd;
-        TIMED(7, rd = energy_div<double>(c, a));
-        LCHK(rd);
-        TIMED(4, hipLaunchKernelGGL((k_rhs_add<D>), pg, bs, 0, s, c->b, c->wJ, c->et, c->Us, c->pbar, N, ld));
+        STEP_CHK(energy_div_team<double>(
+            Tm, fa, 7,
+            [&](int k) {
+              dg_ctx* c = Tm.m[k];
+              return DivArgs<double>{c->mp, c->h, nullptr, nullptr, 1.0, c->lam, -dta[k], 0.0, 0.0, 1, c->b,
+                                     nullptr, nullptr, nullptr};
+            },
+            [&](int) { return 0.0; }));
+        STEP_CHK(pw<PwRhsAdd<D>>(Tm, fa, [&](int k) {
+          dg_ctx* c = Tm.m[k];
+          return PwRhsAdd<D>{c->N, c->ld, c->b, c->wJ, c->et, c->Us, c->pbar};
+        }));
         // r0 = b - A p'
-        if (apply_A<double>(c, dta, c->pp, nullptr, 1.0, c->w)) return fail(c, DG_EDEVICE, "operator launch failed");
-        TIMED(4, hipLaunchKernelGGL(k_sub, pg, bs, 0, s, c->b, c->w, N, c->r0));
+        std::vector<ApItem<double>> it;
+        for (int k : fa) it.push_back(ApItem<double>{k, dta[k], Tm.m[k]->pp, nullptr, 1.0, Tm.m[k]->w, nullptr});
+        STEP_CHK(apply_A_team<double>(Tm, it));
+        STEP_CHK(pw<PwSub>(Tm, fa, [&](int k) { dg_ctx* c = Tm.m[k]; return PwSub{c->N, c->b, c->w, c->r0}; }));
       }
-      int its = 0, outer = 0;
-      double rel = 0.0;
+      fa = alive_of(Tm, fa);
       {
-        Phase ph(c, 5);
-        if (c->opt.precision == DG_FP32_INNER) rc = solve_mixed(c, dta, its, outer, rel);
-        else rc = solve64(c, dta, its, rel);
+        Phase ph(Tm.tc, 5);
+        st = mixed ? solve_mixed_team(Tm, fa, dta, so) : solve64_team(Tm, fa, dta, so);
+        if (st) return st;
       }
-      if (l < 8) {
-        st.gmres_iters[i - 1][l] = its;
-        st.outer_iters[i - 1][l] = outer;
-        st.gmres_relres[i - 1][l] = rel;
+      for (int k : fa) {
+        S[k].gmres_iters[i - 1][l] = so[k].its;
+        S[k].outer_iters[i - 1][l] = so[k].outer;
+        S[k].gmres_relres[i - 1][l] = so[k].relres;
       }
-      if (rc) {
-        if (stats) *stats = st;
-        return rc;
-      }
+      act = alive_of(Tm, act);
+      fa = alive_of(Tm, fa);
       {
-        Phase ph(c, 6);
-        TIMED(4, hipLaunchKernelGGL(k_add, pg, bs, 0, s, c->pp, c->delta, N));
-        GradArgs<double> gq{c->pp, nullptr, 1.0, c->q, nullptr, nullptr};
-        int rg;
-        TIMED(7, rg = launch_grad64(c->md, c->degree, gq, s));
-        LCHK(rg);
-        TIMED(4, hipLaunchKernelGGL((k_backsub<D>), pg, bs, 0, s, c->mp, c->q, dta, N, ld, c->Us));
+        Phase ph(Tm.tc, 6);
+        STEP_CHK(pw<PwAdd>(Tm, fa, [&](int k) { return PwAdd{Tm.m[k]->N, Tm.m[k]->pp, Tm.m[k]->delta}; }));
+        STEP_CHK(grad_team<double>(
+            Tm, fa, 7,
+            [&](int k) { dg_ctx* c = Tm.m[k]; return GradArgs<double>{c->pp, nullptr, 1.0, c->q, nullptr, nullptr}; },
+            [&](int) { return 0.0; }));
+        STEP_CHK(pw<PwBacksub<D>>(Tm, fa, [&](int k) {
+          dg_ctx* c = Tm.m[k];
+          return PwBacksub<D>{c->N, c->ld, c->mp, c->q, dta[k], c->Us};
+        }));
       }
-      if (stats && l < 8) {
+      if (stats) {
         // fixed-point increment |delta| / |p'| (one reduction pass: delta.delta, delta.p', p'.p')
-        double r3[3];
-        TIMEDB(3, 16.0 * N, launch_gs_dots<double>(0, G, s, (const double*)nullptr, ld, c->delta, c->pp, c->part, N));
-        if ((rc = reduce_to_host(c, 3, G, r3))) return rc;
-        st.fp_incr[i - 1][l] = r3[2] > 0.0 ? std::sqrt(r3[0] / r3[2]) : std::sqrt(r3[0]);
+        std::vector<DotItem<double>> it;
+        for (int k : fa) it.push_back(DotItem<double>{k, nullptr, Tm.m[k]->delta, Tm.m[k]->pp});
+        STEP_CHK(dots_team<double>(Tm, 0, it));
+        STEP_CHK(fetch(Tm, fa));
+        for (int k : fa) {
+          const double* r3 = Tm.hslot(k) + 2;
+          S[k].fp_incr[i - 1][l] = r3[2] > 0.0 ? std::sqrt(r3[0] / r3[2]) : std::sqrt(r3[0]);
+        }
       }
     }
     {
-      Phase ph(c, 2);
-      TIMED(4, hipLaunchKernelGGL((k_stage_finish<D>), pg, bs, 0, s, c->Us, c->pp, c->pbar, c->mt, c->et, dta,
-                                  N, ld, c->FI[i]));
+      Phase ph(Tm.tc, 2);
+      STEP_CHK(pw<PwStageFinish<D>>(Tm, act, [&](int k) {
+        dg_ctx* c = Tm.m[k];
+        return PwStageFinish<D>{c->N, c->ld, c->Us, c->pp, c->pbar, c->mt, c->et, dta[k], c->FI[i]};
+      }));
     }
     {
-      Phase ph(c, 0);
-      if ((rc = explicit_residual(c, c->Us, c->FE[i]))) return rc;
+      Phase ph(Tm.tc, 0);
+      STEP_CHK(explicit_team(Tm, act, Usc, FEof(i)));
     }
   }
-  (void)beta;
   {
-    Phase ph(c, 2);
-    TIMED(4, hipLaunchKernelGGL((k_final<D>), pg, bs, 0, s, U, c->FE[0], c->FE[1], c->FE[2], c->FI[0], c->FI[1],
-                                c->FI[2], bw[0], bw[1], bw[2], dt, N, ld, c->Un));
+    Phase ph(Tm.tc, 2);
+    STEP_CHK(pw<PwFinal<D>>(Tm, act, [&](int k) {
+      dg_ctx* c = Tm.m[k];
+      return PwFinal<D>{c->N, c->ld, U[k], c->FE[0], c->FE[1], c->FE[2], c->FI[0], c->FI[1], c->FI[2],
+                        bw[0], bw[1], bw[2], dt[k], c->Un};
+    }));
   }
-  Phase ph7(c, 7);
-  HIPCHK(hipMemsetAsync(c->flag, 0, sizeof(int), s));
-  for (int f = 0; f < c->F; ++f)
-    TIMED(4, hipLaunchKernelGGL(k_nonfinite, pw_grid(N), bs, 0, s, c->Un + (size_t)f * ld, N, c->flag));
-  int hflag = 0;
-  HIPCHK(hipMemcpyAsync(c->hred, c->flag, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  memcpy(&hflag, c->hred, sizeof(int));
-  if (hflag) {
-    if (stats) *stats = st;
-    return fail(c, DG_ENAN, "non-finite value in the new state");
+  Phase ph7(Tm.tc, 7);
+  STEP_CHK(pw<PwZero>(Tm, act, [&](int k) { return PwZero{1, Tm.slot(k) + kFlagAt}; }));
+  STEP_CHK(pw<PwNonfinite>(Tm, act, [&](int k) {
+    dg_ctx* c = Tm.m[k];
+    return PwNonfinite{(long)c->F * c->ld, c->Un, Tm.slot(k) + kFlagAt};
+  }));
+  STEP_CHK(fetch(Tm, act));
+  for (int k : act)
+    if (Tm.hslot(k)[kFlagAt] != 0.0) drop(Tm, k, DG_ENAN, "non-finite value in the new state");
+  act = alive_of(Tm, act);
+  if (!Tm.shared) {
+      for (int k : act)
+      TCHK(Tm, hipMemcpyAsync(U[k], Tm.m[k]->Un, (size_t)Tm.m[k]->F * Tm.m[k]->ld * sizeof(double),
+                          hipMemcpyDeviceToDevice, Tm.s));
+  } else {
+    STEP_CHK(pw<PwCopy>(Tm, act, [&](int k) {
+      dg_ctx* c = Tm.m[k];
+      return PwCopy{(long)c->F * c->ld, c->Un, U[k]};
+    }));
   }
-  HIPCHK(hipMemcpyAsync(U, c->Un, (size_t)c->F * ld * sizeof(double), hipMemcpyDeviceToDevice, s));
   if (stats) {
-    double mass, mw;
-    if ((rc = dg_diagnostics(c, U, &mass, &mw))) return rc;
-    st.mass = mass;
-    st.max_w = mw;
+    STEP_CHK(diagnostics_team(Tm, act, Uc));
+    for (int k : act) {
+      S[k].mass = Tm.hslot(k)[3];
+      S[k].max_w = Tm.hslot(k)[kMaxAt];
+    }
     ph7.end();
-    if (c->timing) {
-      HIPCHK(hipStreamSynchronize(s));
-      st.t_step_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (Tm.tc) {
+      dg_ctx* c = Tm.tc;
+      HIPCHK(hipStreamSynchronize(Tm.s));
+      S[0].t_step_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
       for (int e = 0; e < c->ev_n; ++e) {
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, c->ev[2 * e], c->ev[2 * e + 1]));
-        st.t_kernel_ms[c->ev_cls[e]] += ms;
-        st.n_kernel[c->ev_cls[e]] += 1;
+        S[0].t_kernel_ms[c->ev_cls[e]] += ms;
+        S[0].n_kernel[c->ev_cls[e]] += 1;
       }
-      for (int k = 0; k < 8; ++k) st.bytes_kernel[k] = c->kbytes[k];
+      for (int k = 0; k < 8; ++k) S[0].bytes_kernel[k] = c->kbytes[k];
       for (int e = 0; e < c->pev_n; ++e) {
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, c->pev[2 * e], c->pev[2 * e + 1]));
-        st.t_phase_ms[c->pev_cls[e]] += ms;
+        S[0].t_phase_ms[c->pev_cls[e]] += ms;
       }
     }
-    *stats = st;
   }
+#undef STEP_CHK
+  if (stats)
+    for (int k = 0; k < n; ++k) stats[k] = S[k];
   return DG_OK;
 }
 
@@ -1845,7 +2593,8 @@ dg_status dg_setup(const dg_case_desc* desc, int32_t degree, const dg_options* o
     *it.first = c->arena + off;
     off += (it.second + 255) & ~size_t(255);
   }
-  e = hipHostMalloc((void**)&c->hred, 4096, hipHostMallocDefault);
+  e = hipHostMalloc((void**)&c->hred, (size_t)kTeamMax * (kResStride + kCoefStride) * sizeof(double),
+                    hipHostMallocDefault);
   if (e != hipSuccess) { dg_destroy(c); return fail(nullptr, DG_ENOMEM, "pinned host allocation failed"); }
   // upload mesh and tables
   const HostMesh& M = c->hm;
@@ -1958,6 +2707,7 @@ dg_status dg_setup(const dg_case_desc* desc, int32_t degree, const dg_options* o
                          c->desc.atmosphere == DG_ATM_STRATIFIED ? 1 : 0, c->desc.atm[2], c->N, c->hb, c->dhb,
                          c->hb32, c->dhb32);
   }
+  SETUP_CHK(hipMemcpyAsync(c->d_md, &c->md, sizeof(MeshDev), hipMemcpyHostToDevice, s));
   SETUP_CHK(hipStreamSynchronize(s));
 #undef SETUP_CHK
   *out = c;
@@ -2051,36 +2801,36 @@ dg_status dg_init_state(dg_ctx* c, int32_t ic_kind, const double* ic_params, uin
 
 dg_status dg_explicit_residual(dg_ctx* c, const double* U, double* R) {
   if (!c || !U || !R) return fail(nullptr, DG_EINVAL, "null argument");
-  return explicit_residual(c, U, R);
+  Team T = solo(c);
+  const dg_status st = explicit_team(T, {0}, {U}, {R});
+  return st ? st : T.st[0];
 }
 
 dg_status dg_implicit_term(dg_ctx* c, const double* U, double* F) {
   if (!c || !U || !F) return fail(nullptr, DG_EINVAL, "null argument");
-  return implicit_term(c, U, F);
+  Team T = solo(c);
+  const dg_status st = c->D == 2 ? implicit_team<2>(T, {0}, {U}, {F}) : implicit_team<3>(T, {0}, {U}, {F});
+  return st ? st : T.st[0];
 }
 
 dg_status dg_apply_helmholtz(dg_ctx* c, double dta, const void* h, const void* p, void* Ap, int32_t prec) {
   if (!c || !h || !p || !Ap) return fail(nullptr, DG_EINVAL, "null argument");
   const long N = c->N;
+  Team T = solo(c);
+  dg_status st;
   if (prec == DG_FP64) {
     HIPCHK(hipMemcpyAsync(c->h, h, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    hipLaunchKernelGGL(k_lam, dim3((c->hm.ncell + 3) / 4), dim3(256), 0, c->stream, c->h, c->NL,
-                       c->hm.ncell, c->lam, (float*)nullptr);
-    split_update(c);
-    if (apply_A<double>(c, dta, (const double*)p, nullptr, 1.0, (double*)Ap)) return fail(c, DG_EDEVICE, "launch failed");
-    return DG_OK;
+    if ((st = lam_team(T, {0}, false)) || (st = split_update_team(T, {0}))) return st;
+    return apply_A_team<double>(T, {ApItem<double>{0, dta, (const double*)p, nullptr, 1.0, (double*)Ap, nullptr}});
   }
   if (prec == DG_FP32_INNER) {
     if (c->opt.precision != DG_FP32_INNER)
       return fail(c, DG_EINVAL, "context was set up without the FP32 workspace (precision option)");
     // h in FP32: copy, and widen to FP64 for the per-cell sound speed
     HIPCHK(hipMemcpyAsync(c->h32, h, N * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
-    hipLaunchKernelGGL(k_widen, pw_grid(N), dim3(256), 0, c->stream, (const float*)c->h32, N, c->h);
-    hipLaunchKernelGGL(k_lam, dim3((c->hm.ncell + 3) / 4), dim3(256), 0, c->stream, c->h, c->NL,
-                       c->hm.ncell, c->lam, c->lam32);
-    split_update(c);
-    if (apply_A<float>(c, dta, (const float*)p, nullptr, 1.0f, (float*)Ap)) return fail(c, DG_EDEVICE, "launch failed");
-    return DG_OK;
+    if ((st = pw<PwWiden>(T, {0}, [&](int) { return PwWiden{N, c->h32, c->h}; }))) return st;
+    if ((st = lam_team(T, {0}, true)) || (st = split_update_team(T, {0}))) return st;
+    return apply_A_team<float>(T, {ApItem<float>{0, dta, (const float*)p, nullptr, 1.0f, (float*)Ap, nullptr}});
   }
   return fail(c, DG_EINVAL, "bad precision");
 }
@@ -2097,10 +2847,10 @@ dg_status dg_apply_preconditioner(dg_ctx* c, double dta, const double* h, const 
     return fail(c, DG_EDEVICE, "launch failed");
   int rf;
   if (mixed) {
-    FdmArgs<float> f{(const float*)v, 1.0f, c->coef32, (float*)z};
+    FdmArgs<float> f{(const float*)v, 1.0f, c->coef32, (float*)z, nullptr};
     rf = launch_fdm32(c->md, c->degree, f, c->stream);
   } else {
-    FdmArgs<double> f{(const double*)v, 1.0, c->coef, (double*)z};
+    FdmArgs<double> f{(const double*)v, 1.0, c->coef, (double*)z, nullptr};
     rf = launch_fdm64(c->md, c->degree, f, c->stream);
   }
   if (rf) return fail(c, DG_EDEVICE, "launch failed");
@@ -2110,7 +2860,10 @@ dg_status dg_apply_preconditioner(dg_ctx* c, double dta, const double* h, const 
 dg_status imex_rk2_step(dg_ctx* c, double* U, double dt, dg_step_stats* stats) {
   if (!c || !U) return fail(nullptr, DG_EINVAL, "null argument");
   if (!(dt > 0.0)) return fail(c, DG_EINVAL, "dt must be positive");
-  return c->D == 2 ? step_impl<2>(c, U, dt, stats) : step_impl<3>(c, U, dt, stats);
+  Team T = solo(c);
+  double* Us[1] = {U};
+  const dg_status st = c->D == 2 ? step_team<2>(T, Us, &dt, stats) : step_team<3>(T, Us, &dt, stats);
+  return st ? st : T.st[0];
 }
 
 dg_status imex_rk2_step_batched(dg_ctx* const* ctxs, double* const* Us, const double* dts, int32_t n,
@@ -2118,18 +2871,79 @@ dg_status imex_rk2_step_batched(dg_ctx* const* ctxs, double* const* Us, const do
   if (n < 0 || (n > 0 && (!ctxs || !Us || !dts))) return fail(nullptr, DG_EINVAL, "bad batch");
   std::vector<dg_status> rc(n, DG_OK);
   std::vector<std::string> msg(n);
-  std::vector<std::thread> th;
-  th.reserve(n);
+  // members of one class share launches: same dimension, degree, precision, preconditioner and
+  // energy-flux form (the kernels and the control flow of the step); a class is cut into teams of
+  // at most kTeamMax, and the teams run on their own host threads and lead streams
+  std::vector<std::vector<int>> teams;
+  {
+    std::vector<int> cls(n, -1);
+    std::vector<int> rep;
+    for (int i = 0; i < n; ++i) {
+      dg_ctx* c = ctxs[i];
+      if (!c || !Us[i]) { rc[i] = DG_EINVAL; msg[i] = "null member"; continue; }
+      if (!(dts[i] > 0.0)) { rc[i] = DG_EINVAL; msg[i] = "dt must be positive"; continue; }
+      for (int r = 0; r < (int)rep.size() && cls[i] < 0; ++r) {
+        const dg_ctx* q = ctxs[rep[r]];
+        if (q->D == c->D && q->degree == c->degree && q->opt.precision == c->opt.precision &&
+            q->opt.preconditioner == c->opt.preconditioner && q->opt.enthalpy_split == c->opt.enthalpy_split)
+          cls[i] = r;
+      }
+      if (cls[i] < 0) {
+        cls[i] = (int)rep.size();
+        rep.push_back(i);
+      }
+    }
+    for (int r = 0; r < (int)rep.size(); ++r) {
+      std::vector<int> t;
+      for (int i = 0; i < n; ++i) {
+        if (cls[i] != r) continue;
+        t.push_back(i);
+        if ((int)t.size() == kTeamMax) {
+          teams.push_back(t);
+          t.clear();
+        }
+      }
+      if (!t.empty()) teams.push_back(t);
+    }
+  }
   const auto t0 = std::chrono::steady_clock::now();
-  for (int i = 0; i < n; ++i)
-    th.emplace_back([&, i]() {
-      rc[i] = imex_rk2_step(ctxs[i], Us[i], dts[i], stats ? &stats[i] : nullptr);
-      if (rc[i]) msg[i] = ctxs[i] ? ctxs[i]->err : g_last_error;
-      if (ctxs[i]) (void)hipStreamSynchronize(ctxs[i]->stream);
-      if (stats)
-        stats[i].t_step_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    });
-  for (auto& t : th) t.join();
+  auto run = [&](const std::vector<int>& mem) {
+    Team T;
+    T.lead = ctxs[mem[0]];
+    T.s = T.lead->stream;
+    T.shared = true;
+    std::vector<double*> U;
+    std::vector<double> dt;
+    for (int i : mem) {
+      T.m.push_back(ctxs[i]);
+      U.push_back(Us[i]);
+      dt.push_back(dts[i]);
+      // work queued on a member's own stream comes first
+      if (ctxs[i]->stream != T.s) (void)hipStreamSynchronize(ctxs[i]->stream);
+    }
+    T.st.assign(mem.size(), DG_OK);
+    std::vector<dg_step_stats> S(mem.size());
+    const dg_status st = T.m[0]->D == 2 ? step_team<2>(T, U.data(), dt.data(), stats ? S.data() : nullptr)
+                                        : step_team<3>(T, U.data(), dt.data(), stats ? S.data() : nullptr);
+    (void)hipStreamSynchronize(T.s);
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (size_t q = 0; q < mem.size(); ++q) {
+      const int i = mem[q];
+      rc[i] = st && T.st[q] == DG_OK ? st : T.st[q];
+      if (rc[i]) msg[i] = ctxs[i]->err;
+      if (stats) {
+        stats[i] = S[q];
+        stats[i].t_step_ms = ms;
+      }
+    }
+  };
+  if (teams.size() == 1) {
+    run(teams[0]);
+  } else {
+    std::vector<std::thread> th;
+    for (const auto& t : teams) th.emplace_back(run, std::cref(t));
+    for (auto& t : th) t.join();
+  }
   dg_status first = DG_OK;
   for (int i = 0; i < n; ++i) {
     if (status) status[i] = rc[i];
@@ -2143,21 +2957,11 @@ dg_status imex_rk2_step_batched(dg_ctx* const* ctxs, double* const* Us, const do
 
 dg_status dg_diagnostics(dg_ctx* c, const double* U, double* mass, double* max_w) {
   if (!c || !U) return fail(nullptr, DG_EINVAL, "null argument");
-  const long N = c->N;
-  if (mass) {
-    dg_status st = dot<double>(c, c->wJ, U, mass);
-    if (st) return st;
-  }
-  if (max_w) {
-    const int G = red_grid(N);
-    hipLaunchKernelGGL(k_maxabs_ratio, dim3(G), dim3(kRedThreads), 0, c->stream, U + (size_t)c->D * c->ld, U, c->part, N);
-    std::vector<double> parts(G);
-    HIPCHK(hipMemcpyAsync(parts.data(), c->part, G * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    double m = 0.0;
-    for (double v : parts) m = std::max(m, v);
-    *max_w = m;
-  }
+  Team T = solo(c);
+  const dg_status st = diagnostics_team(T, {0}, {U});
+  if (st) return st;
+  if (mass) *mass = T.hslot(0)[3];
+  if (max_w) *max_w = T.hslot(0)[kMaxAt];
   return DG_OK;
 }
 

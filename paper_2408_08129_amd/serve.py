@@ -3,9 +3,11 @@
 Requests (ensemble-forecast members over orography, of different mesh sizes and degrees) arrive
 over time.  The server admits a request as soon as it has arrived and its exact device footprint
 (``dg_footprint`` plus its state) fits in the HBM budget and an execution slot is free; admitted
-members keep their state resident and advance step by step, each on its own HIP stream driven by
-its own host thread, so the kernels of all in-flight members overlap on the device.  When a member
-finishes (or fails) its memory and slot are released and waiting requests are admitted.
+members keep their state resident and advance step by step.  Each round is one batched step:
+members of one class (dimension, degree, precision) share every kernel launch through segment
+tables and every host round trip of the Krylov iteration, and each class runs on its own stream
+from its own host thread.  When a member finishes (or fails) its memory and slot are released and
+waiting requests are admitted.
 
 Reported: throughput (DoF-updates/s over the run), per member-step latency p50/p99, request
 end-to-end latency (arrival -> last step done) and admission wait.
@@ -114,7 +116,8 @@ class _Member:
 
 class Server:
     """Iteration-level continuous batching: every round advances each admitted member by one step
-    in one batched call (members overlap on the device, each on its own stream); requests that
+    in one batched call, in which the members of one class (dimension, degree, precision) share
+    every launch of the step and every host round trip of the Krylov iteration; requests that
     have arrived are admitted at round boundaries while their footprint fits the budget."""
 
     def __init__(self, budget_bytes: int | None = None, max_active: int = 16, precision: int = 1,

@@ -1,0 +1,133 @@
+"""Shared launches of ensemble members (imex_rk2_step_batched): members of one class (dimension,
+degree, precision, preconditioner, energy-flux form) advance in lockstep through segment-table
+launches.  Each member's step must be the same bits alone (a batch of one) and in any mix, and
+agree with the single-context step; a member that fails leaves the others untouched."""
+import numpy as np
+import pytest
+
+from tests import _common as C
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def host(U):
+    return U.detach().cpu().numpy().copy()
+
+
+def make(ws, **opt):
+    import paper_2408_08129_amd as P
+    _torch()
+    out = []
+    for w in ws:
+        s = P.Solver(C.product_case(w), w["degree"], P.options(**opt) if opt else None)
+        out.append(s)
+    return out
+
+
+def batched(P, solvers, states, dts, steps):
+    status = None
+    for _ in range(steps):
+        _, status = P.imex_rk2_step_batched([s.ctx for s in solvers], states, dts, raise_on_error=False)
+    _torch().cuda.synchronize()
+    return status
+
+
+def check_alone_equals_mix(ws, dts, steps=2, **opt):
+    import paper_2408_08129_amd as P
+    print("[case] shared launches", [(w["dim"], w["degree"], w["nbase"]) for w in ws], opt, flush=True)
+    solvers = make(ws, **opt)
+    init = [s.init_state(10.0, noise_seed=7 + i, noise_sigma_K=0.05) for i, s in enumerate(solvers)]
+    alone = []
+    for s, U0, dt in zip(solvers, init, dts):
+        U = U0.clone()
+        st = batched(P, [s], [U], [dt], steps)
+        assert st == [0]
+        alone.append(host(U))
+    mix = [U0.clone() for U0 in init]
+    st = batched(P, solvers, mix, dts, steps)
+    assert st == [0] * len(ws)
+    for i, (U, a) in enumerate(zip(mix, alone)):
+        assert np.array_equal(host(U), a), i
+    # the single-context step (direct launches) computes the same arithmetic
+    for i, (s, U0, dt) in enumerate(zip(solvers, init, dts)):
+        U = U0.clone()
+        for _ in range(steps):
+            s.step(U, dt)
+        d = host(U)
+        err = max(C.rel_err(d[f], alone[i][f]) for f in range(d.shape[0]))
+        print("member %d: shared vs direct max rel diff %.3e" % (i, err), flush=True)
+        assert err <= 1e-13
+    return solvers
+
+
+@pytest.mark.gpu
+def test_shared_2d_members_of_different_sizes():
+    ws = [C.twolevel2d(3), C.tiny2d(3), C.walls2d(3), C.tiny2d(3, oro=1, h0=80.0)]
+    check_alone_equals_mix(ws, [0.5, 0.4, 0.5, 0.3])
+
+
+@pytest.mark.gpu
+def test_shared_3d_members_fp64_and_mixed_precision():
+    ws = [C.tiny3d(2), C.twolevel3d(2), C.tiny3d(2, oro=2, h0=90.0)]
+    check_alone_equals_mix(ws, [0.5, 0.5, 0.4])
+    check_alone_equals_mix(ws, [0.5, 0.5, 0.4], precision=1)
+
+
+@pytest.mark.gpu
+def test_shared_enthalpy_split_members():
+    ws = [C.tiny3d(3), C.twolevel3d(3)]
+    check_alone_equals_mix(ws, [0.5, 0.5], enthalpy_split=1, penalty_beta=0.0)
+
+
+@pytest.mark.gpu
+def test_shared_chunked_launches_and_failure_isolation():
+    """More members than one segment table holds (several launches per step), one of them failing."""
+    import paper_2408_08129_amd as P
+    torch = _torch()
+    ws = [C.tiny2d(2, h0=60.0 + 10.0 * i) for i in range(11)]
+    print("[case] shared launches, 11 members, member 4 poisoned", flush=True)
+    solvers = make(ws)
+    init = [s.init_state(10.0) for s in solvers]
+    alone = []
+    for s, U0 in zip(solvers, init):
+        U = U0.clone()
+        assert batched(P, [s], [U], [0.5], 2) == [0]
+        alone.append(host(U))
+    mix = [U0.clone() for U0 in init]
+    mix[4][0, 3] = float("nan")
+    before = host(mix[4])
+    _, st = P.imex_rk2_step_batched([s.ctx for s in solvers], mix, [0.5] * 11, raise_on_error=False)
+    torch.cuda.synchronize()
+    assert st[4] == P.DG_ENAN and all(v == 0 for i, v in enumerate(st) if i != 4)
+    after = host(mix[4])
+    assert np.array_equal(np.isnan(after), np.isnan(before))
+    assert np.array_equal(after[~np.isnan(after)], before[~np.isnan(before)])
+    # the survivors take a second step together and match their alone runs
+    rest = [i for i in range(11) if i != 4]
+    st = batched(P, [solvers[i] for i in rest], [mix[i] for i in rest], [0.5] * len(rest), 1)
+    assert st == [0] * len(rest)
+    for i in rest:
+        assert np.array_equal(host(mix[i]), alone[i]), i
+
+
+@pytest.mark.gpu
+def test_shared_members_of_several_classes():
+    """One call with three classes (2D r=3, 3D r=2, 2D r=2): each class shares its launches."""
+    import paper_2408_08129_amd as P
+    ws = [C.tiny2d(3), C.tiny3d(2), C.twolevel2d(3), C.tiny2d(2), C.twolevel3d(2), C.twolevel2d(2)]
+    print("[case] shared launches, three classes", flush=True)
+    solvers = make(ws)
+    init = [s.init_state(10.0) for s in solvers]
+    alone = []
+    for s, U0 in zip(solvers, init):
+        U = U0.clone()
+        assert batched(P, [s], [U], [0.5], 2) == [0]
+        alone.append(host(U))
+    mix = [U0.clone() for U0 in init]
+    assert batched(P, solvers, mix, [0.5] * len(ws), 2) == [0] * len(ws)
+    for i in range(len(ws)):
+        assert np.array_equal(host(mix[i]), alone[i]), i
