@@ -82,7 +82,7 @@ KERNELS = {
                        "(Helmholtz apply A(h) p: pass 1 h M^-1 B p, pass 2 divergence, penalty, mass)",
     "explicit_residual": "k_col_exp + 2:1-faces pass of k_cell<OpExplicit> (explicit residual)",
 }
-SOURCES = ("dg_ops.hip", "dg_helm.hip", "dg_internal.hpp", "dg_device.hpp")  # the operator kernels
+SOURCES = ("dg_ops.hip", "dg_helm.hip", "dg_internal.hpp", "dg_device.hpp", "dg_solver.hip")  # the operator kernels and their launch tables
 
 
 def source_sha256():

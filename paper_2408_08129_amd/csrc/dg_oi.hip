@@ -4,13 +4,17 @@
 // nodal (diagonal) one and the gravity work stays pointwise, as in the nodal kernels.
 //
 // One workgroup per cell.  Volume: the state is interpolated from the NP^d nodes to the NQ^d
-// points by three 1D passes (LDS), the contravariant fluxes are formed there with the analytic
-// metric, and the weak-form contraction back onto the nodes is three 1D passes per flux
-// component (derivative matrix along the component's axis, interpolation along the others).
-// Faces: traces on the NP^(d-1) face nodes (own from LDS; neighbours gathered along their normal
-// lines), interpolated to the NQ^(d-1) face points (on a 2:1 face: the fine sub-face's points, the
-// coarse polynomial evaluated there with the half-interval matrices), Rusanov / slip-wall flux
-// times the face weight, contracted back onto the face nodes and lifted along the normal lines.
+// points by three 1D passes (LDS); at each point the weighted conserved fluxes' common factors
+// (w rho, w m, w rho k) and the D contravariant velocities are stored, and for each direction k
+// the weak-form contraction back onto the nodes is three 1D passes (derivative matrix along k,
+// interpolation along the others) whose first pass forms the flux component on the fly.
+// Faces, one axis (two opposite faces) at a time: traces on the NP^(d-1) face nodes (own from
+// LDS; neighbours gathered along their normal lines), interpolated to the NQ^(d-1) face points
+// (on a 2:1 face: the fine sub-face's points, the coarse polynomial evaluated there with the
+// half-interval matrices), Rusanov / slip-wall flux times the face weight, contracted back onto
+// the face nodes and lifted along the normal lines into the accumulator.  Working on one flux
+// direction and one face axis at a time keeps the workgroup's LDS small enough for several
+// workgroups per compute unit.
 #include "dg_device.hpp"
 
 namespace dg {
@@ -32,35 +36,41 @@ struct Oi {
   // interpolation passes (per field): x pass NQ NP^(d-1), (3D) y pass NQ^2 NP, then NQ^d
   static constexpr int IA = NQ * ipow(NP, D - 1);
   static constexpr int IB = D == 3 ? NQ * NQ * NP : 0;
-  // contraction passes (per flux component and field): x pass NP NQ^(d-1), (3D) y pass NP^2 NQ
+  // contraction passes (per field, one flux direction): x pass NP NQ^(d-1), (3D) y pass NP^2 NQ
   static constexpr int CA = NP * ipow(NQ, D - 1);
   static constexpr int CB = D == 3 ? NP * NP * NQ : 0;
-  // face arrays: own node traces, neighbour node traces (per sub-face), point values, node sums
-  static constexpr int FO = NF * NV * NPF;
-  static constexpr int FN = NF * MS * NV * NPF;
-  static constexpr int FL = NF * MS * NV * NFQ;
-  static constexpr int FG = NF * NV * NPF;
-  static constexpr int SF = D * NV * NVQ;
-  // after the volume terms the face arrays reuse the flux and scratch buffers together
-  static constexpr int R1 = cmax(cmax(NV * (IA + IB + NVQ), D * NV * (CA + CB)), FO + FN + FL + FG - SF);
-  static constexpr int LDS = 8 * (2 * NV * NL + SF + R1 + OiLayout{NP, NQ}.size());
+  // face arrays of one axis (two faces): own node traces, neighbour node traces (per sub-face),
+  // point values, node sums
+  static constexpr int FO = 2 * NV * NPF;
+  static constexpr int FN = 2 * MS * NV * NPF;
+  static constexpr int FL = 2 * MS * NV * NFQ;
+  static constexpr int FG = 2 * NV * NPF;
+  // state at the points (NV NVQ) and contravariant velocities (D NVQ), then the pass scratch;
+  // the face arrays reuse all three
+  static constexpr int SQ = NV * NVQ + D * NVQ;
+  static constexpr int S1 = cmax(NV * (IA + IB), NV * (CA + CB));
+  static constexpr int S2 = cmax(0, FO + FN + FL + FG - SQ);
+  static constexpr int LDS = 8 * (2 * NV * NL + SQ + cmax(S1, S2) + OiLayout{NP, NQ}.size());
 };
 
 // y = M x along one axis of a tensor array: x has extent nin along the axis, y extent nout;
 // `lo` and `hi` are the extents of the axes before and after it.
+// With xs non-null the input is x times the field-independent factor xs (same layout as one
+// field of x).
 template <int NT>
 __device__ __forceinline__ void pass1d(const double* __restrict__ Mt, bool transpose, int nin, int nout,
                                        int lo, int hi, int nfield, const double* x, int xstride,
-                                       double* y, int ystride, bool accumulate) {
+                                       double* y, int ystride, bool accumulate, const double* xs = nullptr) {
   const int total = nfield * lo * nout * hi;
   for (int t = threadIdx.x; t < total; t += NT) {
     const int a = t % lo, o = (t / lo) % nout, b = (t / (lo * nout)) % hi, f = t / (lo * nout * hi);
     const double* xp = x + f * xstride + a + lo * nin * b;
+    const double* sp = xs ? xs + a + lo * nin * b : nullptr;
     double v = 0.0;
     for (int i = 0; i < nin; ++i) {
       // forward: M[o][i] stored as Mt[o * nin + i]; transposed: M[i][o] stored as Mt[i * nout + o]
       const double mm = transpose ? Mt[i * nout + o] : Mt[o * nin + i];
-      v += mm * xp[lo * i];
+      v += mm * (sp ? xp[lo * i] * sp[lo * i] : xp[lo * i]);
     }
     double* yp = y + f * ystride + a + lo * o + lo * nout * b;
     if (accumulate) *yp += v;
@@ -79,9 +89,10 @@ __global__ void __launch_bounds__(256) k_exp_oi(const double* __restrict__ U, do
   __shared__ double smem[C::LDS / 8];
   double* sU = smem;                 // [NV][NL] nodal state
   double* sW = sU + NV * NL;         // [NV][NL] weak-form accumulator
-  double* sF = sW + NV * NL;         // [D][NV][NVQ] weighted contravariant fluxes at the points
-  double* sR = sF + D * NV * NVQ;    // scratch (interpolation, contraction, faces)
-  double* sT = sR + C::R1;           // over-integration tables
+  double* sQ = sW + NV * NL;         // [NV][NVQ] state at the points, then w (rho, m, rho k)
+  double* sG = sQ + NV * NVQ;        // [D][NVQ] contravariant velocities at the points
+  double* sR = sG + D * NVQ;         // pass scratch
+  double* sT = sR + cmax(C::S1, C::S2);  // over-integration tables
   const double* xq = sT + OL.xq();
   const double* wq = sT + OL.wq();
   const double* Bq = sT + OL.bq();
@@ -105,23 +116,26 @@ __global__ void __launch_bounds__(256) k_exp_oi(const double* __restrict__ U, do
   __syncthreads();
 
   // ------------------------------------------------------------------ volume: nodes -> points
-  double* sA = sR;
-  double* sB = sA + NV * C::IA;
-  double* sQ = sB + NV * C::IB;
-  if constexpr (D == 3) {
-    pass1d<NT>(Bq, false, NP, NQ, 1, NP * NP, NV, sU, NL, sA, C::IA, false);
-    __syncthreads();
-    pass1d<NT>(Bq, false, NP, NQ, NQ, NP, NV, sA, C::IA, sB, C::IB, false);
-    __syncthreads();
-    pass1d<NT>(Bq, false, NP, NQ, NQ * NQ, 1, NV, sB, C::IB, sQ, NVQ, false);
-  } else {
-    pass1d<NT>(Bq, false, NP, NQ, 1, NP, NV, sU, NL, sA, C::IA, false);
-    __syncthreads();
-    pass1d<NT>(Bq, false, NP, NQ, NQ, 1, NV, sA, C::IA, sQ, NVQ, false);
+  {
+    double* sA = sR;
+    double* sB = sA + NV * C::IA;
+    if constexpr (D == 3) {
+      pass1d<NT>(Bq, false, NP, NQ, 1, NP * NP, NV, sU, NL, sA, C::IA, false);
+      __syncthreads();
+      pass1d<NT>(Bq, false, NP, NQ, NQ, NP, NV, sA, C::IA, sB, C::IB, false);
+      __syncthreads();
+      pass1d<NT>(Bq, false, NP, NQ, NQ * NQ, 1, NV, sB, C::IB, sQ, NVQ, false);
+    } else {
+      pass1d<NT>(Bq, false, NP, NQ, 1, NP, NV, sU, NL, sA, C::IA, false);
+      __syncthreads();
+      pass1d<NT>(Bq, false, NP, NQ, NQ, 1, NV, sA, C::IA, sQ, NVQ, false);
+    }
   }
   __syncthreads();
 
-  // ------------------------------------------------------------------ fluxes at the points
+  // ------------------------------------------------------------------ flux factors at the points
+  // the flux of direction k at point q is (w rho, w m, w rho k) times the contravariant velocity
+  // G_k . u, w the point's weight
   for (int q = tid; q < NVQ; q += NT) {
     double X[D], wgt = 1.0;
     int t = q;
@@ -147,185 +161,189 @@ __global__ void __launch_bounds__(256) k_exp_oi(const double* __restrict__ U, do
       double Gu = 0.0;
 #pragma unroll
       for (int a = 0; a < D; ++a) Gu += Gam[k][a] * u[a];
-      double* Fk = sF + k * NV * NVQ;
-      Fk[0 * NVQ + q] = wgt * rho * Gu;
-#pragma unroll
-      for (int a = 0; a < D; ++a) Fk[(1 + a) * NVQ + q] = wgt * Uq[1 + a] * Gu;
-      Fk[(1 + D) * NVQ + q] = wgt * rk * Gu;
+      sG[k * NVQ + q] = Gu;
     }
+    sQ[0 * NVQ + q] = wgt * rho;
+#pragma unroll
+    for (int a = 0; a < D; ++a) sQ[(1 + a) * NVQ + q] = wgt * Uq[1 + a];
+    sQ[(1 + D) * NVQ + q] = wgt * rk;
   }
   __syncthreads();
 
   // ------------------------------------------------------------------ volume: points -> nodes
   // W_i += sum_k sum_q d_k phi_i(x_q) F_k(x_q): along axis k the derivative matrix, else Bq
-  double* tA = sR;
-  double* tB = tA + D * NV * C::CA;
-  if constexpr (D == 3) {
-    for (int k = 0; k < D; ++k)
-      pass1d<NT>(k == 0 ? Dq : Bq, true, NQ, NP, 1, NQ * NQ, NV, sF + k * NV * NVQ, NVQ,
-                 tA + k * NV * C::CA, C::CA, false);
-    __syncthreads();
-    for (int k = 0; k < D; ++k)
-      pass1d<NT>(k == 1 ? Dq : Bq, true, NQ, NP, NP, NQ, NV, tA + k * NV * C::CA, C::CA,
-                 tB + k * NV * C::CB, C::CB, false);
-    __syncthreads();
+  {
+    double* tA = sR;
+    double* tB = tA + NV * C::CA;
     for (int k = 0; k < D; ++k) {
-      pass1d<NT>(k == 2 ? Dq : Bq, true, NQ, NP, NP * NP, 1, NV, tB + k * NV * C::CB, C::CB, sW, NL, true);
-      __syncthreads();
-    }
-  } else {
-    for (int k = 0; k < D; ++k)
-      pass1d<NT>(k == 0 ? Dq : Bq, true, NQ, NP, 1, NQ, NV, sF + k * NV * NVQ, NVQ,
-                 tA + k * NV * C::CA, C::CA, false);
-    __syncthreads();
-    for (int k = 0; k < D; ++k) {
-      pass1d<NT>(k == 1 ? Dq : Bq, true, NQ, NP, NP, 1, NV, tA + k * NV * C::CA, C::CA, sW, NL, true);
-      __syncthreads();
-    }
-  }
-
-  // ------------------------------------------------------------------ faces
-  double* sTO = sF;                  // [NF][NV][NPF]
-  double* sTN = sTO + C::FO;         // [NF][MS][NV][NPF]
-  double* sL = sTN + C::FN;          // [NF][MS][NV][NFQ]
-  double* sG = sL + C::FL;           // [NF][NV][NPF]
-  // node traces: own (LDS) and neighbours (HBM / L2, along their normal lines)
-  for (int t = tid; t < NF * NV * NPF; t += NT) {
-    const int f = t / (NV * NPF), v = (t / NPF) % NV, a = t % NPF;
-    const int k = f >> 1, s = f & 1;
-    double o = 0.0;
-    for (int n = 0; n < NP; ++n) o += tab[TL.lb() + s * NP + n] * sU[v * NL + compose<D, NP>(k, n, a)];
-    sTO[t] = o;
-  }
-  for (int t = tid; t < NF * MS * NV * NPF; t += NT) {
-    const int f = t / (MS * NV * NPF), sub = (t / (NV * NPF)) % MS, v = (t / NPF) % NV, a = t % NPF;
-    const int k = f >> 1, s = f & 1;
-    const int kd = m.fkind[cell * NF + f];
-    if (kd == kWall || (kd != kCoarse && sub > 0)) continue;
-    const int4 nb4 = m.fnbr[cell * NF + f];
-    const int nb = sub == 0 ? nb4.x : sub == 1 ? nb4.y : sub == 2 ? nb4.z : nb4.w;
-    double o = 0.0;
-    for (int n = 0; n < NP; ++n)
-      o += tab[TL.lb() + (1 - s) * NP + n] * U[(size_t)v * N + (size_t)nb * NL + compose<D, NP>(k, n, a)];
-    sTN[t] = o;
-  }
-  __syncthreads();
-
-  // flux at every point of every (sub-)face, times the face weight
-  for (int t = tid; t < NF * MS * NFQ; t += NT) {
-    const int f = t / (MS * NFQ), sub = (t / NFQ) % MS, j = t % NFQ;
-    const int k = f >> 1, s = f & 1;
-    const int kd = m.fkind[cell * NF + f];
-    if (kd != kCoarse && sub > 0) continue;
-    const int j0 = j % NQ, j1 = D == 3 ? j / NQ : 0;
-    // this cell's position on its coarse neighbour's face (fine side)
-    int cs[2] = {0, 0};
-    {
-      int tt = 0;
-#pragma unroll
-      for (int ax = 0; ax < D; ++ax)
-        if (ax != k) cs[tt++] = cid[ax] & 1;
-    }
-    // own-side and neighbour-side interpolation matrices per tangential direction
-    const int c0 = sub & 1, c1 = sub >> 1;
-    const double* Mo0 = kd == kCoarse ? Bs + c0 * NQ * NP : Bq;
-    const double* Mo1 = kd == kCoarse ? Bs + c1 * NQ * NP : Bq;
-    const double* Mn0 = kd == kFine ? Bs + cs[0] * NQ * NP : Bq;
-    const double* Mn1 = kd == kFine ? Bs + cs[1] * NQ * NP : Bq;
-    double tm[NV], tn[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const double* To = sTO + (f * NV + v) * NPF;
-      const double* Tn = sTN + ((f * MS + sub) * NV + v) * NPF;
-      double a = 0.0, b = 0.0;
+      const double* Gk = sG + k * NVQ;
       if constexpr (D == 3) {
-#pragma unroll 1
-        for (int a1 = 0; a1 < NP; ++a1) {
-          double ra = 0.0, rb = 0.0;
-#pragma unroll 1
-          for (int a0 = 0; a0 < NP; ++a0) {
-            ra += Mo0[j0 * NP + a0] * To[a0 + NP * a1];
-            rb += Mn0[j0 * NP + a0] * Tn[a0 + NP * a1];
-          }
-          a += Mo1[j1 * NP + a1] * ra;
-          b += Mn1[j1 * NP + a1] * rb;
-        }
+        pass1d<NT>(k == 0 ? Dq : Bq, true, NQ, NP, 1, NQ * NQ, NV, sQ, NVQ, tA, C::CA, false, Gk);
+        __syncthreads();
+        pass1d<NT>(k == 1 ? Dq : Bq, true, NQ, NP, NP, NQ, NV, tA, C::CA, tB, C::CB, false);
+        __syncthreads();
+        pass1d<NT>(k == 2 ? Dq : Bq, true, NQ, NP, NP * NP, 1, NV, tB, C::CB, sW, NL, true);
       } else {
-#pragma unroll 1
-        for (int a0 = 0; a0 < NP; ++a0) {
-          a += Mo0[j0 * NP + a0] * To[a0];
-          b += Mn0[j0 * NP + a0] * Tn[a0];
-        }
+        pass1d<NT>(k == 0 ? Dq : Bq, true, NQ, NP, 1, NQ, NV, sQ, NVQ, tA, C::CA, false, Gk);
+        __syncthreads();
+        pass1d<NT>(k == 1 ? Dq : Bq, true, NQ, NP, NP, 1, NV, tA, C::CA, sW, NL, true);
       }
-      tm[v] = a;
-      tn[v] = b;
+      __syncthreads();
     }
-    // area-weighted normal at the point, from the integer description of the (sub)face
-    const int lf = kd == kCoarse ? lev + 1 : lev;
-    int P = kd == kCoarse ? (s ? 2 * (cid[k] + 1) : 2 * cid[k]) : (s ? cid[k] + 1 : cid[k]);
-    if (m.per[k] && P >= m.nlev[lf][k]) P -= m.nlev[lf][k];
-    double X[D];
-    {
-      int tt = 0;
-#pragma unroll
-      for (int ax = 0; ax < D; ++ax) {
-        const double dx = m.dxl[lf][ax];
-        if (ax == k) {
-          X[ax] = dx * (double)P;
-        } else {
-          const int Tt = kd == kCoarse ? 2 * cid[ax] + ((sub >> tt) & 1) : cid[ax];
-          X[ax] = dx * ((double)Tt + 0.5 * (1.0 + xq[tt == 0 ? j0 : j1]));
-          ++tt;
-        }
-      }
-    }
-    double Gam[D][D], Jf, Nv[D];
-    metric<D, double>(m, lf, X, Gam, Jf);
-#pragma unroll
-    for (int a = 0; a < D; ++a) Nv[a] = Gam[k][a];
-    const double wj = D == 3 ? wq[j0] * wq[j1] : wq[j0];
-    double F[NV];
-    double sgn = s ? 1.0 : -1.0;
-    if (kd == kWall) {
-      double No[D];
-#pragma unroll
-      for (int a = 0; a < D; ++a) No[a] = sgn * Nv[a];
-      wall_flux<D>(tm, No, F);
-      sgn = 1.0;
-    } else if (s) {
-      rusanov<D>(tm, tn, Nv, F);
-    } else {
-      rusanov<D>(tn, tm, Nv, F);
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) sL[((f * MS + sub) * NV + v) * NFQ + j] = -sgn * wj * F[v];
   }
-  __syncthreads();
-  // back onto the face nodes (transposed own-side interpolation), every face at once
-  for (int t = tid; t < NF * NV * NPF; t += NT) {
-    const int f = t / (NV * NPF), v = (t / NPF) % NV, a = t % NPF;
-    const int kd = m.fkind[cell * NF + f];
-    const int nsub = kd == kCoarse ? MS : 1;
-    const int a0 = a % NP, a1 = D == 3 ? a / NP : 0;
-    double g = 0.0;
-#pragma unroll 1
-    for (int sub = 0; sub < nsub; ++sub) {
+
+  // ------------------------------------------------------------------ faces, one axis at a time
+  double* sTO = sQ;                  // [2][NV][NPF]
+  double* sTN = sTO + C::FO;         // [2][MS][NV][NPF]
+  double* sL = sTN + C::FN;          // [2][MS][NV][NFQ]
+  double* sGf = sL + C::FL;          // [2][NV][NPF]
+  for (int k = 0; k < D; ++k) {
+    // node traces: own (LDS) and neighbours (HBM / L2, along their normal lines)
+    for (int t = tid; t < 2 * NV * NPF; t += NT) {
+      const int s = t / (NV * NPF), v = (t / NPF) % NV, a = t % NPF;
+      double o = 0.0;
+      for (int n = 0; n < NP; ++n) o += tab[TL.lb() + s * NP + n] * sU[v * NL + compose<D, NP>(k, n, a)];
+      sTO[t] = o;
+    }
+    for (int t = tid; t < 2 * MS * NV * NPF; t += NT) {
+      const int s = t / (MS * NV * NPF), sub = (t / (NV * NPF)) % MS, v = (t / NPF) % NV, a = t % NPF;
+      const int f = 2 * k + s;
+      const int kd = m.fkind[cell * NF + f];
+      if (kd == kWall || (kd != kCoarse && sub > 0)) continue;
+      const int4 nb4 = m.fnbr[cell * NF + f];
+      const int nb = sub == 0 ? nb4.x : sub == 1 ? nb4.y : sub == 2 ? nb4.z : nb4.w;
+      double o = 0.0;
+      for (int n = 0; n < NP; ++n)
+        o += tab[TL.lb() + (1 - s) * NP + n] * U[(size_t)v * N + (size_t)nb * NL + compose<D, NP>(k, n, a)];
+      sTN[t] = o;
+    }
+    __syncthreads();
+
+    // flux at every point of both (sub-)faces, times the face weight
+    for (int t = tid; t < 2 * MS * NFQ; t += NT) {
+      const int s = t / (MS * NFQ), sub = (t / NFQ) % MS, j = t % NFQ;
+      const int f = 2 * k + s;
+      const int kd = m.fkind[cell * NF + f];
+      if (kd != kCoarse && sub > 0) continue;
+      const int j0 = j % NQ, j1 = D == 3 ? j / NQ : 0;
+      // this cell's position on its coarse neighbour's face (fine side)
+      int cs[2] = {0, 0};
+      {
+        int tt = 0;
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax)
+          if (ax != k) cs[tt++] = cid[ax] & 1;
+      }
+      // own-side and neighbour-side interpolation matrices per tangential direction
       const int c0 = sub & 1, c1 = sub >> 1;
       const double* Mo0 = kd == kCoarse ? Bs + c0 * NQ * NP : Bq;
       const double* Mo1 = kd == kCoarse ? Bs + c1 * NQ * NP : Bq;
-      const double* Lp = sL + ((f * MS + sub) * NV + v) * NFQ;
+      const double* Mn0 = kd == kFine ? Bs + cs[0] * NQ * NP : Bq;
+      const double* Mn1 = kd == kFine ? Bs + cs[1] * NQ * NP : Bq;
+      double tm[NV], tn[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double* To = sTO + (s * NV + v) * NPF;
+        const double* Tn = sTN + ((s * MS + sub) * NV + v) * NPF;
+        double a = 0.0, b = 0.0;
+        if constexpr (D == 3) {
 #pragma unroll 1
-      for (int j = 0; j < NFQ; ++j) {
-        const int j0 = j % NQ, j1 = D == 3 ? j / NQ : 0;
-        const double b = D == 3 ? Mo0[j0 * NP + a0] * Mo1[j1 * NP + a1] : Mo0[j0 * NP + a0];
-        g += b * Lp[j];
+          for (int a1 = 0; a1 < NP; ++a1) {
+            double ra = 0.0, rb = 0.0;
+#pragma unroll 1
+            for (int a0 = 0; a0 < NP; ++a0) {
+              ra += Mo0[j0 * NP + a0] * To[a0 + NP * a1];
+              rb += Mn0[j0 * NP + a0] * Tn[a0 + NP * a1];
+            }
+            a += Mo1[j1 * NP + a1] * ra;
+            b += Mn1[j1 * NP + a1] * rb;
+          }
+        } else {
+#pragma unroll 1
+          for (int a0 = 0; a0 < NP; ++a0) {
+            a += Mo0[j0 * NP + a0] * To[a0];
+            b += Mn0[j0 * NP + a0] * Tn[a0];
+          }
+        }
+        tm[v] = a;
+        tn[v] = b;
       }
+      // area-weighted normal at the point, from the integer description of the (sub)face
+      const int lf = kd == kCoarse ? lev + 1 : lev;
+      int P = kd == kCoarse ? (s ? 2 * (cid[k] + 1) : 2 * cid[k]) : (s ? cid[k] + 1 : cid[k]);
+      if (m.per[k] && P >= m.nlev[lf][k]) P -= m.nlev[lf][k];
+      double X[D];
+      {
+        int tt = 0;
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+          const double dx = m.dxl[lf][ax];
+          if (ax == k) {
+            X[ax] = dx * (double)P;
+          } else {
+            const int Tt = kd == kCoarse ? 2 * cid[ax] + ((sub >> tt) & 1) : cid[ax];
+            X[ax] = dx * ((double)Tt + 0.5 * (1.0 + xq[tt == 0 ? j0 : j1]));
+            ++tt;
+          }
+        }
+      }
+      double Gam[D][D], Jf, Nv[D];
+      metric<D, double>(m, lf, X, Gam, Jf);
+#pragma unroll
+      for (int a = 0; a < D; ++a) Nv[a] = Gam[k][a];
+      const double wj = D == 3 ? wq[j0] * wq[j1] : wq[j0];
+      double F[NV];
+      double sgn = s ? 1.0 : -1.0;
+      if (kd == kWall) {
+        double No[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) No[a] = sgn * Nv[a];
+        wall_flux<D>(tm, No, F);
+        sgn = 1.0;
+      } else if (s) {
+        rusanov<D>(tm, tn, Nv, F);
+      } else {
+        rusanov<D>(tn, tm, Nv, F);
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sL[((s * MS + sub) * NV + v) * NFQ + j] = -sgn * wj * F[v];
     }
-    sG[t] = g;
+    __syncthreads();
+    // back onto the face nodes (transposed own-side interpolation)
+    for (int t = tid; t < 2 * NV * NPF; t += NT) {
+      const int s = t / (NV * NPF), v = (t / NPF) % NV, a = t % NPF;
+      const int kd = m.fkind[cell * NF + 2 * k + s];
+      const int nsub = kd == kCoarse ? MS : 1;
+      const int a0 = a % NP, a1 = D == 3 ? a / NP : 0;
+      double g = 0.0;
+#pragma unroll 1
+      for (int sub = 0; sub < nsub; ++sub) {
+        const int c0 = sub & 1, c1 = sub >> 1;
+        const double* Mo0 = kd == kCoarse ? Bs + c0 * NQ * NP : Bq;
+        const double* Mo1 = kd == kCoarse ? Bs + c1 * NQ * NP : Bq;
+        const double* Lp = sL + ((s * MS + sub) * NV + v) * NFQ;
+#pragma unroll 1
+        for (int j = 0; j < NFQ; ++j) {
+          const int j0 = j % NQ, j1 = D == 3 ? j / NQ : 0;
+          const double b = D == 3 ? Mo0[j0 * NP + a0] * Mo1[j1 * NP + a1] : Mo0[j0 * NP + a0];
+          g += b * Lp[j];
+        }
+      }
+      sGf[t] = g;
+    }
+    __syncthreads();
+    // lift both faces along the normal lines into the accumulator (face 2k, then 2k + 1)
+    for (int t = tid; t < NV * NL; t += NT) {
+      const int v = t / NL, i = t % NL;
+      double acc = sW[t];
+      acc += tab[TL.lb() + along<D, NP>(i, k)] * sGf[(0 * NV + v) * NPF + tang<D, NP>(i, k)];
+      acc += tab[TL.lb() + NP + along<D, NP>(i, k)] * sGf[(1 * NV + v) * NPF + tang<D, NP>(i, k)];
+      sW[t] = acc;
+    }
+    __syncthreads();
   }
-  __syncthreads();
 
-  // ------------------------------------------------------------------ lift and finalize
+  // ------------------------------------------------------------------ finalize
   for (int t = tid; t < NL; t += NT) {
     const int i = t;
     double X[D];
@@ -340,13 +358,7 @@ __global__ void __launch_bounds__(256) k_exp_oi(const double* __restrict__ U, do
     const double imass = 1.0 / (wi * J);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      double acc = sW[v * NL + i];
-#pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        const int k = f >> 1, s = f & 1;
-        acc += tab[TL.lb() + s * NP + along<D, NP>(i, k)] * sG[(f * NV + v) * NPF + tang<D, NP>(i, k)];
-      }
-      double r = acc * imass;
+      double r = sW[v * NL + i] * imass;
       if (v == NV - 1) r -= kG * sU[D * NL + i];
       R[(size_t)v * N + (size_t)cell * NL + i] = r;
     }
