@@ -49,6 +49,8 @@ def run_gpu(w, precision, steps, warmup, timing=True):
     extra = {}
     if w.get("enthalpy_split"):
         extra = dict(enthalpy_split=1, penalty_beta=float(w.get("penalty_beta", 0.0)))
+    if w.get("gmres_restart"):
+        extra["gmres_restart"] = int(w["gmres_restart"])
     opt = P.options(precision=precision, gmres_rtol=w.get("rtol", 1e-8), quad_extra=w.get("quad_extra", 0), **extra)
     t0 = time.perf_counter()
     s = P.Solver(cases.product_case(w), w["degree"], opt)
@@ -268,6 +270,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-split", action="store_true",
                     help="skip the leg with the enthalpy-split energy flux (the stable long-run form)")
+    ap.add_argument("--gmres-restart", type=int, default=0,
+                    help="GMRES restart length of the FP64 solve (0: the library default)")
     ap.add_argument("--quad-extra", type=int, default=0,
                     help="over-integrate the explicit flux with degree + 1 + Q points per direction")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -301,6 +305,8 @@ def main():
     w = dict(cases.WORKLOADS[args.workload])
     w["rtol"] = 1e-8
     w["quad_extra"] = args.quad_extra
+    if args.gmres_restart:
+        w["gmres_restart"] = args.gmres_restart
 
     r64 = run_gpu(w, P.DG_FP64, args.steps, args.warmup)
     value = r64["dofs"] * args.steps / r64["total"]
@@ -312,7 +318,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "cells": r64["ncell"], "dofs": r64["dofs"],
                    "degree": w["degree"], "dim": w["dim"], "dt": w["dt"], "gmres_rtol": w["rtol"],
-                   "precision": "fp64", "quad_extra": args.quad_extra},
+                   "precision": "fp64", "quad_extra": args.quad_extra, "gmres_restart": args.gmres_restart or 15},
         "p50_step_ms": round(percentile(r64["lat"], 50), 3),
         "p99_step_ms": round(percentile(r64["lat"], 99), 3),
         "gmres_iters": [s["gmres_iters"] for s in r64["stats"]],
