@@ -51,6 +51,8 @@ def run_gpu(w, precision, steps, warmup, timing=True):
         extra = dict(enthalpy_split=1, penalty_beta=float(w.get("penalty_beta", 0.0)))
     if w.get("gmres_restart"):
         extra["gmres_restart"] = int(w["gmres_restart"])
+    if w.get("inner_restart"):
+        extra["inner_restart"] = int(w["inner_restart"])
     opt = P.options(precision=precision, gmres_rtol=w.get("rtol", 1e-8), quad_extra=w.get("quad_extra", 0), **extra)
     t0 = time.perf_counter()
     s = P.Solver(cases.product_case(w), w["degree"], opt)
@@ -272,6 +274,8 @@ def main():
                     help="skip the leg with the enthalpy-split energy flux (the stable long-run form)")
     ap.add_argument("--gmres-restart", type=int, default=0,
                     help="GMRES restart length of the FP64 solve (0: the library default)")
+    ap.add_argument("--inner-restart", type=int, default=0,
+                    help="restart length of the FP32 inner GMRES of the mixed form (0: the library default)")
     ap.add_argument("--quad-extra", type=int, default=0,
                     help="over-integrate the explicit flux with degree + 1 + Q points per direction")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -307,6 +311,8 @@ def main():
     w["quad_extra"] = args.quad_extra
     if args.gmres_restart:
         w["gmres_restart"] = args.gmres_restart
+    if args.inner_restart:
+        w["inner_restart"] = args.inner_restart
 
     r64 = run_gpu(w, P.DG_FP64, args.steps, args.warmup)
     value = r64["dofs"] * args.steps / r64["total"]
@@ -351,6 +357,7 @@ def main():
             "gain_vs_fp64": round(v32 / value, 3),
             "max_rel_diff_vs_fp64_per_field": diff,
             "max_abs_diff_vs_fp64_per_field": adiff,
+            "inner_restart": args.inner_restart or 30,
             "inner_iters": [s["gmres_iters"] for s in r32["stats"]],
             "outer_iters": [s["outer_iters"] for s in r32["stats"]],
         }

@@ -131,3 +131,11 @@ def test_shared_members_of_several_classes():
     assert batched(P, solvers, mix, [0.5] * len(ws), 2) == [0] * len(ws)
     for i in range(len(ws)):
         assert np.array_equal(host(mix[i]), alone[i]), i
+
+
+@pytest.mark.gpu
+def test_shared_fallback_paths():
+    """Members whose launches the team makes one per member: the Jacobi-preconditioned operator
+    (general cell kernel) and the over-integrated explicit residual."""
+    check_alone_equals_mix([C.tiny2d(3), C.twolevel2d(3)], [0.5, 0.5], preconditioner=0)
+    check_alone_equals_mix([C.tiny3d(2), C.twolevel3d(2)], [0.5, 0.5], quad_extra=1)
