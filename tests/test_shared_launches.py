@@ -139,3 +139,13 @@ def test_shared_fallback_paths():
     (general cell kernel) and the over-integrated explicit residual."""
     check_alone_equals_mix([C.tiny2d(3), C.twolevel2d(3)], [0.5, 0.5], preconditioner=0)
     check_alone_equals_mix([C.tiny3d(2), C.twolevel3d(2)], [0.5, 0.5], quad_extra=1)
+
+
+@pytest.mark.gpu
+def test_shared_team_with_a_two_round_trip_member():
+    """A member above 2^23 nodes per field keeps two host round trips per Krylov iteration; in a
+    team with a small member (one round trip) both keep their own arithmetic."""
+    from paper_2408_08129_amd import cases
+    big = dict(cases.WORKLOADS["box3d_r4_hill"])
+    small = C.tiny3d(4)
+    check_alone_equals_mix([big, small], [big["dt"], 0.5], steps=1)
