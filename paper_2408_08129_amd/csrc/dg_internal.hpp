@@ -259,9 +259,21 @@ int launch_grad_hang_seg32(int n, const MeshDev* const* mh, const MeshDev* const
 int launch_div_hang_seg64(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<double>* a, int degree, hipStream_t s);
 int launch_div_hang_seg32(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<float>* a, int degree, hipStream_t s);
 int launch_explicit_hang_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const ExpArgs* a, int degree, hipStream_t s);
-// per-cell sound speed (lam) and preconditioner coefficients from h and w J
+// per-cell sound speed (lam) and preconditioner coefficients from h and w J (coef may be null:
+// lam only)
 int launch_cellcoef(const MeshDev& m, int degree, const double* h, const double* wJ, double dta,
                     double* lam, float* lam32, double* coef, float* coef32, hipStream_t s);
+struct CoefArgs {
+  const double* h;
+  const double* wJ;
+  double dta;
+  double* lam;
+  float* lam32;
+  double* coef;
+  float* coef32;
+};
+int launch_cellcoef_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const CoefArgs* a, int degree,
+                        hipStream_t s);
 
 // node geometry: physical coordinates, w J, background p and rho, absorbing-layer rate per node
 // (each output optional)

@@ -846,12 +846,21 @@ namespace {
 // One wavefront per cell: lam = sqrt((gamma-1) max h); hbar, Jbar (J = wJ / w); coefficients of
 // the fast-diagonalisation preconditioner alpha_k = (dt a)^2 hbar (2 / D_k)^2 with the vertical
 // size scaled by the cell's mean terrain stretching.
-template <int D, int NP>
-__global__ void k_cellcoef(const MeshDev m, const double* __restrict__ h, const double* __restrict__ wJ,
-                           double dta, double* lam, float* lam32, double* coef, float* coef32) {
+template <int D, int NP, class S = Direct<CoefArgs>>
+__global__ void k_cellcoef(const S src) {
+  const int sg = src.seg();
+  const MeshDev& m = src.mesh(sg);
+  const CoefArgs& ca = src.args(sg);
+  const double* __restrict__ h = ca.h;
+  const double* __restrict__ wJ = ca.wJ;
+  const double dta = ca.dta;
+  double* lam = ca.lam;
+  float* lam32 = ca.lam32;
+  double* coef = ca.coef;
+  float* coef32 = ca.coef32;
   constexpr int NL = ipow(NP, D);
   constexpr TabLayout TL{NP};
-  const int c = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int c = src.blk(sg) * (blockDim.x / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (c >= m.ncell) return;
   const double* w1 = m.tab + TL.w();
@@ -896,11 +905,32 @@ namespace {
 template <int D, int NP>
 int run_cellcoef(const MeshDev& m, const double* h, const double* wJ, double dta, double* lam,
                  float* lam32, double* coef, float* coef32, hipStream_t s) {
-  hipLaunchKernelGGL((k_cellcoef<D, NP>), dim3((m.ncell + 3) / 4), dim3(256), 0, s, m, h, wJ, dta, lam,
-                     lam32, coef, coef32);
+  hipLaunchKernelGGL((k_cellcoef<D, NP>), dim3((m.ncell + 3) / 4), dim3(256), 0, s,
+                     Direct<CoefArgs>{CoefArgs{h, wJ, dta, lam, lam32, coef, coef32}, m});
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
+template <int D, int NP>
+int run_cellcoef_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const CoefArgs* a, hipStream_t s) {
+  return seg_launch<CoefArgs>(
+      n, md, [&](int k) { return (mh[k]->ncell + 3) / 4; }, [&](int k) { return a[k]; },
+      [&](const SegTab<CoefArgs>& t, int g) {
+        hipLaunchKernelGGL((k_cellcoef<D, NP, Shared<CoefArgs>>), dim3(g), dim3(256), 0, s, Shared<CoefArgs>{t});
+        return hipGetLastError() == hipSuccess ? 0 : -3;
+      });
+}
 }  // namespace
+
+int launch_cellcoef_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const CoefArgs* a, int degree,
+                        hipStream_t s) {
+  if (n <= 0) return 0;
+  for (int k = 0; k < n; ++k)
+    if (mh[k]->dim != mh[0]->dim) return -6;
+  if (mh[0]->dim == 2) {
+    DG_DISPATCH(2, degree, return (run_cellcoef_seg<2, NP>(n, mh, md, a, s)));
+  } else {
+    DG_DISPATCH(3, degree, return (run_cellcoef_seg<3, NP>(n, mh, md, a, s)));
+  }
+}
 
 int launch_cellcoef(const MeshDev& m, int degree, const double* h, const double* wJ, double dta,
                     double* lam, float* lam32, double* coef, float* coef32, hipStream_t s) {

@@ -665,22 +665,6 @@ struct PwNonfinite {
   }
 };
 
-// per-cell maximum of c = sqrt((gamma - 1) h): one wavefront per cell
-__global__ void k_lam(const double* __restrict__ h, int nloc, int ncell, double* lam, float* lam32) {
-  const int c = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (c >= ncell) return;
-  double m = 0.0;
-  for (int i = lane; i < nloc; i += 64) m = fmax(m, h[(long)c * nloc + i]);
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-  if (lane == 0) {
-    const double v = sqrt((kGamma - 1.0) * m);
-    lam[c] = v;
-    if (lam32) lam32[c] = (float)v;
-  }
-}
-
 // Background enthalpy hbar = gamma pbar / ((gamma - 1) rhobar) and its height derivative from the
 // closed form of the hydrostatic background: -g + c_p T N^2 / g (stratified), 0 (isothermal).
 __global__ void k_hbar(const double* __restrict__ pbar, const double* __restrict__ rbar, int strat, double Nbv,
@@ -2232,16 +2216,28 @@ dg_status explicit_team(Team& Tm, const std::vector<int>& act, const std::vector
   return pw<PwFriction<3>>(Tm, sp, [&](int k) { dg_ctx* c = Tm.m[k]; return PwFriction<3>{c->N, c->ld, U[k], c->tau, c->desc.sponge[4], R[k]}; });
 }
 
-// per-cell sound speed of every member from its h
+// Per-cell sound speed and (with coef) preconditioner coefficients of every member from its h.
+dg_status cellcoef_team(Team& Tm, const std::vector<int>& act, const std::vector<double>& dta, bool f32, bool coef) {
+  if (act.empty()) return DG_OK;
+  const hipStream_t s = Tm.s;
+  const int deg = Tm.m[act[0]]->degree;
+  return op_launch<CoefArgs>(
+      Tm, act, 4,
+      [&](int k) {
+        dg_ctx* c = Tm.m[k];
+        return CoefArgs{c->h, c->wJ, dta[k], c->lam, f32 ? c->lam32 : nullptr, coef ? c->coef : nullptr,
+                        (coef && f32) ? c->coef32 : nullptr};
+      },
+      [&](int) { return 0.0; },
+      [&](dg_ctx* c, const CoefArgs& a) {
+        return launch_cellcoef(c->md, c->degree, a.h, a.wJ, a.dta, a.lam, a.lam32, a.coef, a.coef32, s);
+      },
+      [&](int n, const MeshDev* const* mh, const MeshDev* const* md, const CoefArgs* a) {
+        return launch_cellcoef_seg(n, mh, md, a, deg, s);
+      });
+}
 dg_status lam_team(Team& Tm, const std::vector<int>& act, bool f32) {
-  for (int k : act) {
-    dg_ctx* c = Tm.m[k];
-    Timed t_(Tm.tc, 4);
-    hipLaunchKernelGGL(k_lam, dim3((c->hm.ncell + 3) / 4), dim3(256), 0, Tm.s, c->h, c->NL, c->hm.ncell, c->lam,
-                       f32 ? c->lam32 : (float*)nullptr);
-  }
-  TCHK(Tm, hipGetLastError());
-  return DG_OK;
+  return cellcoef_team(Tm, act, std::vector<double>(Tm.n(), 0.0), f32, false);
 }
 
 // F_I(U) into F; uses pp, h, lam, q as scratch
@@ -2366,16 +2362,7 @@ dg_status step_team(Team& Tm, double* const* U, const double* dt, dg_step_stats*
                         c->hm.nb[0], c->hm.nb[1], c->hm.nb[2], c->degree + 1, dta[k], c->h, c->dinv,
                         mixed ? c->h32 : (float*)nullptr, mixed ? c->dinv32 : (float*)nullptr};
         }));
-        for (int k : fa) {
-          dg_ctx* c = Tm.m[k];
-          int rcc;
-          {
-            Timed t_(Tm.tc, 4);
-            rcc = launch_cellcoef(c->md, c->degree, c->h, c->wJ, dta[k], c->lam, mixed ? c->lam32 : nullptr, c->coef,
-                                  mixed ? c->coef32 : nullptr, Tm.s);
-          }
-          if (rcc) return team_fail(Tm, DG_EDEVICE, "launch failed: per-cell coefficients");
-        }
+        STEP_CHK(cellcoef_team(Tm, fa, dta, mixed, true));
         STEP_CHK(split_update_team(Tm, fa));
       }
       fa = alive_of(Tm, fa);
