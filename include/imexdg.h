@@ -305,7 +305,8 @@ dg_status imex_rk2_step(dg_ctx* ctx, double* U_dev, double dt, dg_step_stats* st
  * for first, and the call returns when every team is done.  stats: array of n or NULL
  * (t_step_ms = time from the call to the member's team completion); status: array of n or NULL
  * (per-member result).  Returns DG_OK or the first member error; a member that fails keeps its
- * state, the others advance. */
+ * state, the others advance.  A context may appear once per call: a repeat gets DG_EINVAL and is
+ * not stepped. */
 dg_status imex_rk2_step_batched(dg_ctx* const* ctxs, double* const* U_devs, const double* dts,
                                 int32_t n, dg_step_stats* stats, int32_t* status);
 

@@ -2869,6 +2869,9 @@ dg_status imex_rk2_step_batched(dg_ctx* const* ctxs, double* const* Us, const do
       dg_ctx* c = ctxs[i];
       if (!c || !Us[i]) { rc[i] = DG_EINVAL; msg[i] = "null member"; continue; }
       if (!(dts[i] > 0.0)) { rc[i] = DG_EINVAL; msg[i] = "dt must be positive"; continue; }
+      bool dup = false;
+      for (int q = 0; q < i && !dup; ++q) dup = ctxs[q] == c && cls[q] >= 0;
+      if (dup) { rc[i] = DG_EINVAL; msg[i] = "context appears twice in the batch"; continue; }
       for (int r = 0; r < (int)rep.size() && cls[i] < 0; ++r) {
         const dg_ctx* q = ctxs[rep[r]];
         if (q->D == c->D && q->degree == c->degree && q->opt.precision == c->opt.precision &&

@@ -149,3 +149,19 @@ def test_shared_team_with_a_two_round_trip_member():
     big = dict(cases.WORKLOADS["box3d_r4_hill"])
     small = C.tiny3d(4)
     check_alone_equals_mix([big, small], [big["dt"], 0.5], steps=1)
+
+
+@pytest.mark.gpu
+def test_shared_rejects_a_repeated_member():
+    import paper_2408_08129_amd as P
+    print("[case] shared launches, one context twice", flush=True)
+    s, = make([C.tiny2d(2)])
+    U = s.init_state(10.0)
+    Ua = U.clone()
+    assert batched(P, [s], [Ua], [0.5], 1) == [0]
+    V = U.clone()
+    _, st = P.imex_rk2_step_batched([s.ctx, s.ctx], [U, V], [0.5, 0.5], raise_on_error=False)
+    _torch().cuda.synchronize()
+    assert st == [0, P.DG_EINVAL]
+    assert np.array_equal(host(U), host(Ua))
+    assert np.array_equal(host(V), host(s.init_state(10.0)))
