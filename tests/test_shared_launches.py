@@ -165,3 +165,32 @@ def test_shared_rejects_a_repeated_member():
     assert st == [0, P.DG_EINVAL]
     assert np.array_equal(host(U), host(Ua))
     assert np.array_equal(host(V), host(s.init_state(10.0)))
+
+
+@pytest.mark.gpu
+def test_shared_team_members_match_the_oracle():
+    """Members stepped together in shared launches end where the FP64 oracle ends."""
+    import math
+    import paper_2408_08129_amd as P
+    from oracle import oracle as O
+    from tests.test_gpu_parity import TOL_STEP
+    ws = [C.twolevel2d(3), C.tiny2d(3), C.walls2d(3)]
+    print("[case] shared team vs oracle", [(w["dim"], w["degree"], w["nbase"]) for w in ws], flush=True)
+    solvers = make(ws)
+    oracles = [O.Oracle(C.oracle_case(w)) for w in ws]
+    perms = [C.cell_perm(s.cell_table(), o.cells) for s, o in zip(solvers, oracles)]
+    Uo = [o.initial_state(10.0) for o in oracles]
+    torch = _torch()
+    U = [torch.from_numpy(C.to_product_order(u, p, o.nloc)).cuda() for u, p, o in zip(Uo, perms, oracles)]
+    dts = [0.5, 0.4, 0.5]
+    assert batched(P, solvers, U, dts, 2) == [0, 0, 0]
+    for i, (o, p) in enumerate(zip(oracles, perms)):
+        ref = Uo[i]
+        for _ in range(2):
+            ref = o.step(ref, dts[i])
+        Ug = C.to_oracle_order(host(U[i]), p, o.nloc)
+        for f in range(o.nf):
+            err = C.rel_err(Ug[f], ref[f])
+            l2 = math.sqrt(np.sum(o.wJ * (Ug[f] - ref[f]) ** 2) / max(np.sum(o.wJ * ref[f] ** 2), 1e-300))
+            print("member %d field %d max rel %.2e L2 rel %.2e" % (i, f, err, l2), flush=True)
+            assert err < TOL_STEP, (i, f, err)
