@@ -111,3 +111,17 @@ def test_single_hip_runtime_after_loading():
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_batched_step_argument_checks():
+    """The batched step validates its members on the host: an empty batch is a no-op, and a null
+    context or a non-positive time step fails only that member (no device work is issued)."""
+    import torch
+    assert P.imex_rk2_step_batched([], [], []) == ([], [])
+    U = torch.zeros(4, 8, dtype=torch.float64)
+    stats, status = P.imex_rk2_step_batched([0], [U], [0.5], raise_on_error=False)
+    assert status == [P.DG_EINVAL]
+    with pytest.raises(P.DGError) as e:
+        P.imex_rk2_step_batched([0, 0], [U, U], [0.5, -1.0])
+    assert e.value.status == P.DG_EINVAL
+    assert "member 0" in str(e.value)
