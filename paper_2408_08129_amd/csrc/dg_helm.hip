@@ -1182,30 +1182,21 @@ int launch_div64(const MeshDev& m, int degree, const DivArgs<double>& a, hipStre
   return r;
 }
 // The enthalpy-split energy flux in one column pass (a.h = h - hbar, a.hb, a.dhb set), then the
-// 2:1 face terms of C((h - hbar) qv) with the penalty, and of C(qv) multiplied by hbar at the node.
+// 2:1 face terms of C((h - hbar) qv) with the penalty and of C(qv) multiplied by hbar at the
+// node, both in one faces-only pass.
 template <class T>
 int div_split(const MeshDev& m, int degree, const DivArgs<T>& a, hipStream_t s,
               int (*hang)(const MeshDev&, int, const DivArgs<T>&, hipStream_t)) {
   if (a.dinv || !a.h || !a.hb || !a.dhb) return -3;
   int r = div_col<T, true, true>(m, degree, a, s);
   if (r) return r;
-  r = hang(m, degree, a, s);
-  if (r) return r;
-  DivArgs<T> a2 = a;
-  a2.h = nullptr;
-  a2.p = nullptr;
-  a2.apen = T(0);
-  a2.amass = T(0);
-  a2.hb = nullptr;
-  a2.dhb = nullptr;
-  a2.omul = a.hb;
-  return hang(m, degree, a2, s);
+  return hang(m, degree, a, s);
 }
 int launch_div_split64(const MeshDev& m, int degree, const DivArgs<double>& a, hipStream_t s) {
-  return div_split<double>(m, degree, a, s, launch_div_hang64);
+  return div_split<double>(m, degree, a, s, launch_div_split_hang64);
 }
 int launch_div_split32(const MeshDev& m, int degree, const DivArgs<float>& a, hipStream_t s) {
-  return div_split<float>(m, degree, a, s, launch_div_hang32);
+  return div_split<float>(m, degree, a, s, launch_div_split_hang32);
 }
 
 // ---------------------------------------------------------------- shared launches
@@ -1291,25 +1282,10 @@ template <class T>
 int div_split_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<T>* a, int degree,
                   hipStream_t s, int (*hang)(int, const MeshDev* const*, const MeshDev* const*, const DivArgs<T>*, int, hipStream_t)) {
   if (n <= 0) return 0;
-  if (n > 64) return -6;
   for (int k = 0; k < n; ++k)
     if (a[k].dinv || !a[k].h || !a[k].hb || !a[k].dhb || mh[k]->dim != mh[0]->dim) return -6;
-  int r = div_col_seg<T, true, true>(n, mh, md, a, degree, s);
-  if (r) return r;
-  r = hang(n, mh, md, a, degree, s);
-  if (r) return r;
-  DivArgs<T> a2[64];
-  for (int k = 0; k < n; ++k) {
-    a2[k] = a[k];
-    a2[k].h = nullptr;
-    a2[k].p = nullptr;
-    a2[k].apen = T(0);
-    a2[k].amass = T(0);
-    a2[k].hb = nullptr;
-    a2[k].dhb = nullptr;
-    a2[k].omul = a[k].hb;
-  }
-  return hang(n, mh, md, a2, degree, s);
+  const int r = div_col_seg<T, true, true>(n, mh, md, a, degree, s);
+  return r ? r : hang(n, mh, md, a, degree, s);
 }
 
 template <class T>
@@ -1339,10 +1315,10 @@ int launch_div_seg32(int n, const MeshDev* const* mh, const MeshDev* const* md, 
   return div_seg<float>(n, mh, md, a, degree, s, launch_div_hang_seg32);
 }
 int launch_div_split_seg64(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<double>* a, int degree, hipStream_t s) {
-  return div_split_seg<double>(n, mh, md, a, degree, s, launch_div_hang_seg64);
+  return div_split_seg<double>(n, mh, md, a, degree, s, launch_div_split_hang_seg64);
 }
 int launch_div_split_seg32(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<float>* a, int degree, hipStream_t s) {
-  return div_split_seg<float>(n, mh, md, a, degree, s, launch_div_hang_seg32);
+  return div_split_seg<float>(n, mh, md, a, degree, s, launch_div_split_hang_seg32);
 }
 int launch_fdm_seg64(int n, const MeshDev* const* mh, const MeshDev* const* md, const FdmArgs<double>* a, int degree, hipStream_t s) {
   return fdm_seg<double>(n, mh, md, a, degree, s);

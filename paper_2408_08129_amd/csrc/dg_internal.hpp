@@ -190,8 +190,6 @@ struct DivArgs {
   // hbar C(qv) + adiv M (d hbar/dz) qv_z, with hbar and its height derivative at the nodes
   const T* hb;
   const T* dhb;
-  // faces-only 2:1 pass: multiplier of the added face terms per node (may be null: 1)
-  const T* omul;
 };
 
 // Explicit residual R = F_E(U) ([F][N] each).
@@ -259,6 +257,11 @@ int launch_grad_hang_seg32(int n, const MeshDev* const* mh, const MeshDev* const
 int launch_div_hang_seg64(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<double>* a, int degree, hipStream_t s);
 int launch_div_hang_seg32(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<float>* a, int degree, hipStream_t s);
 int launch_explicit_hang_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const ExpArgs* a, int degree, hipStream_t s);
+// both 2:1-face terms of the enthalpy-split divergence in one pass (a.h = h - hbar, a.hb = hbar)
+int launch_div_split_hang64(const MeshDev& m, int degree, const DivArgs<double>& a, hipStream_t s);
+int launch_div_split_hang32(const MeshDev& m, int degree, const DivArgs<float>& a, hipStream_t s);
+int launch_div_split_hang_seg64(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<double>* a, int degree, hipStream_t s);
+int launch_div_split_hang_seg32(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<float>* a, int degree, hipStream_t s);
 // per-cell sound speed (lam) and preconditioner coefficients from h and w J (coef may be null:
 // lam only)
 int launch_cellcoef(const MeshDev& m, int degree, const double* h, const double* wJ, double dta,

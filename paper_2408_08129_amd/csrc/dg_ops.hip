@@ -202,7 +202,97 @@ struct OpDiv {
   }
   __device__ __forceinline__ void finalize_add(unsigned idx, const T* acc, T w, T J) const {
     const T v = a.weak ? w * acc[0] : acc[0] / J;
-    a.out[idx] += a.omul ? a.omul[idx] * v : v;
+    a.out[idx] += v;
+  }
+  __device__ __forceinline__ T lam(int cell) const { return a.lam ? a.lam[cell] : T(0); }
+};
+
+// The enthalpy-split divergence's two 2:1-face terms in one pass (a.h = h - hbar, a.hb = hbar):
+// C((h - hbar) qv) with the penalty and mass terms of a (output 0), and C(qv) (output 1), whose
+// lifted value the node multiplies by hbar.  Each output is the one of the corresponding OpDiv
+// pass (the second with h = 1, no p, no penalty), and they are added to out in that order.
+template <int D, class TT>
+struct OpDivSplit {
+  using T = TT;
+  static constexpr int NIN = D + 2, NTR = 2 * D + 1, NOUT = 2;
+  static constexpr int NVOL = 2 * D;
+  static constexpr int vidx(int o, int k) { return o * D + k; }
+  DivArgs<T> a;
+  unsigned N;
+  __device__ __forceinline__ void load(unsigned idx, T* in) const {
+#pragma unroll
+    for (int l = 0; l < D; ++l) in[l] = a.qv[l * N + idx];
+    in[D] = a.h[idx];
+    in[D + 1] = a.p ? a.p[idx] : T(0);
+  }
+  // as OpDiv, for both vector traces (h - hbar) qv (0..d-1) and qv (d+1..2d); p is trace d
+  static constexpr bool need(int k, int g) {
+    return g == D || k == D - 1 || (g < D ? g == k : g - D - 1 == k);
+  }
+  __device__ __forceinline__ void load_face(unsigned idx, int k, T* in) const {
+#pragma unroll
+    for (int l = 0; l < D; ++l) in[l] = (k == D - 1 || l == k) ? a.qv[l * N + idx] : T(0);
+    in[D] = a.h[idx];
+    in[D + 1] = a.p ? a.p[idx] : T(0);
+  }
+  __device__ __forceinline__ void transform(const T* in, T* tr) const {
+#pragma unroll
+    for (int l = 0; l < D; ++l) {
+      tr[l] = in[D] * in[l];
+      tr[D + 1 + l] = in[l];
+    }
+    tr[D] = in[D + 1];
+  }
+  __device__ __forceinline__ void vol(const T* tr, const T (&Gam)[D][D], T (&G)[NOUT][D]) const {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      T G0 = 0, G1 = 0;
+#pragma unroll
+      for (int l = 0; l < D; ++l) {
+        G0 += Gam[k][l] * tr[l];
+        G1 += Gam[k][l] * tr[D + 1 + l];
+      }
+      G[0][k] = -a.adiv * G0;
+      G[1][k] = -a.adiv * G1;
+    }
+  }
+  __device__ __forceinline__ void face(int kind, int left, const T* tm, const T* tn, const T* Nv,
+                                       T lm, T ln, T* phi) const {
+    if (kind == kWall) {
+      phi[0] = 0;
+      phi[1] = 0;
+      return;
+    }
+    const T sign = left ? T(1) : T(-1);
+    T wm = 0, wn = 0, nn = 0, um = 0, un = 0;
+#pragma unroll
+    for (int l = 0; l < D; ++l) {
+      wm += Nv[l] * tm[l];
+      wn += Nv[l] * tn[l];
+      nn += Nv[l] * Nv[l];
+      um += Nv[l] * tm[D + 1 + l];
+      un += Nv[l] * tn[D + 1 + l];
+    }
+    const T wh = left ? T(0.5) * (wm + wn) : T(0.5) * (wn + wm);
+    T v = a.adiv * sign * wh;
+    if (a.apen != T(0)) {
+      const T lf = lm > ln ? lm : ln;
+      v += a.apen * (lf * sqrt(nn) * (tm[D] - tn[D]));
+    }
+    phi[0] = v;
+    const T uh = left ? T(0.5) * (um + un) : T(0.5) * (un + um);
+    phi[1] = a.adiv * sign * uh;
+  }
+  __device__ __forceinline__ void finalize(unsigned idx, const T* acc, T w, T J, const T* tr) const {
+    T o = a.weak ? w * (acc[0] + a.amass * J * tr[D]) : acc[0] / J;
+    o += a.hb[idx] * (a.weak ? w * acc[1] : acc[1] / J);
+    a.out[idx] = o;
+  }
+  __device__ __forceinline__ void finalize_add(unsigned idx, const T* acc, T w, T J) const {
+    T o = a.out[idx];
+    o += a.weak ? w * acc[0] : acc[0] / J;
+    o += a.hb[idx] * (a.weak ? w * acc[1] : acc[1] / J);
+    a.out[idx] = o;
   }
   __device__ __forceinline__ T lam(int cell) const { return a.lam ? a.lam[cell] : T(0); }
 };
@@ -218,6 +308,7 @@ struct CellArgs {
 
 template <class Op> struct HasLam { static constexpr bool value = false; };
 template <int D, class T> struct HasLam<OpDiv<D, T>> { static constexpr bool value = true; };
+template <int D, class T> struct HasLam<OpDivSplit<D, T>> { static constexpr bool value = true; };
 
 // --------------------------------------------------------------------------------- the kernel
 // Coarse-face values at a fine sub-face point (tensor interpolation along the tangential axes).
@@ -781,6 +872,24 @@ int launch_grad_cells32(const MeshDev& m, int degree, const GradArgs<float>& a, 
 int launch_div_cells32(const MeshDev& m, int degree, const DivArgs<float>& a, const int* list, int n, hipStream_t s) {
   return div_impl<float>(m, degree, a, list, n, s);
 }
+template <class T>
+static int div_split_hang_impl(const MeshDev& m, int degree, const DivArgs<T>& a, hipStream_t s) {
+  if (!a.h || !a.hb) return -3;
+  if (m.dim == 2) {
+    OpDivSplit<2, T> op{a, (unsigned)m.N};
+    DG_DISPATCH(2, degree, return (run<2, NP, OpDivSplit<2, T>, true>(op, m, m.irr, m.nirr, s)));
+  } else {
+    OpDivSplit<3, T> op{a, (unsigned)m.N};
+    DG_DISPATCH(3, degree, return (run<3, NP, OpDivSplit<3, T>, true>(op, m, m.irr, m.nirr, s)));
+  }
+}
+int launch_div_split_hang64(const MeshDev& m, int degree, const DivArgs<double>& a, hipStream_t s) {
+  return div_split_hang_impl<double>(m, degree, a, s);
+}
+int launch_div_split_hang32(const MeshDev& m, int degree, const DivArgs<float>& a, hipStream_t s) {
+  return div_split_hang_impl<float>(m, degree, a, s);
+}
+
 int launch_grad_hang64(const MeshDev& m, int degree, const GradArgs<double>& a, hipStream_t s) {
   return grad_impl<double, true>(m, degree, a, m.irr, m.nirr, s);
 }
@@ -829,6 +938,26 @@ int launch_div_hang_seg64(int n, const MeshDev* const* mh, const MeshDev* const*
 }
 int launch_div_hang_seg32(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<float>* a, int degree, hipStream_t s) {
   return div_hang_seg<float>(n, mh, md, a, degree, s);
+}
+template <class T>
+static int div_split_hang_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<T>* a,
+                              int degree, hipStream_t s) {
+  if (n <= 0) return 0;
+  for (int k = 0; k < n; ++k)
+    if (!a[k].h || !a[k].hb) return -3;
+  if (mh[0]->dim == 2) {
+    auto mk = [&](int k) { return OpDivSplit<2, T>{a[k], (unsigned)mh[k]->N}; };
+    DG_DISPATCH(2, degree, return (run_hang_seg<2, NP, OpDivSplit<2, T>>(n, mh, md, mk, s)));
+  } else {
+    auto mk = [&](int k) { return OpDivSplit<3, T>{a[k], (unsigned)mh[k]->N}; };
+    DG_DISPATCH(3, degree, return (run_hang_seg<3, NP, OpDivSplit<3, T>>(n, mh, md, mk, s)));
+  }
+}
+int launch_div_split_hang_seg64(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<double>* a, int degree, hipStream_t s) {
+  return div_split_hang_seg<double>(n, mh, md, a, degree, s);
+}
+int launch_div_split_hang_seg32(int n, const MeshDev* const* mh, const MeshDev* const* md, const DivArgs<float>* a, int degree, hipStream_t s) {
+  return div_split_hang_seg<float>(n, mh, md, a, degree, s);
 }
 int launch_explicit_hang_seg(int n, const MeshDev* const* mh, const MeshDev* const* md, const ExpArgs* a, int degree, hipStream_t s) {
   if (n <= 0) return 0;

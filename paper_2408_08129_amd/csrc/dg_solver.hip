@@ -1563,7 +1563,7 @@ dg_status apply_A_team(Team& Tm, const std::vector<ApItem<T>>& it) {
         const double beta = c->opt.penalty_beta;
         return DivArgs<T>{PB::q(c), split ? PB::h(c) : nullptr, given(e) ? e.v : PB::z(c), nullptr, T(1), PB::lam(c),
                           (T)(-e.dta * e.dta), (T)(e.dta * beta / (2.0 * (kGamma - 1.0))), (T)(1.0 / (kGamma - 1.0)),
-                          1, e.w, nullptr, nullptr, nullptr};
+                          1, e.w, nullptr, nullptr};
       },
       [&](int k) { dg_ctx* c = Tm.m[k]; return (double)sizeof(T) * c->N * (c->D + 2); });
 }
@@ -2264,7 +2264,7 @@ dg_status implicit_team(Team& Tm, const std::vector<int>& act, const std::vector
         dg_ctx* c = Tm.m[k];
         const double beta = c->opt.penalty_beta;
         return DivArgs<double>{U[k] + c->ld, c->h, c->pp, nullptr, 1.0, c->lam, -1.0, -beta / (2.0 * (kGamma - 1.0)),
-                               0.0, 0, F[k] + (size_t)(1 + D) * c->ld, nullptr, nullptr, nullptr};
+                               0.0, 0, F[k] + (size_t)(1 + D) * c->ld, nullptr, nullptr};
       },
       [&](int) { return 0.0; });
 }
@@ -2374,7 +2374,7 @@ dg_status step_team(Team& Tm, double* const* U, const double* dt, dg_step_stats*
             [&](int k) {
               dg_ctx* c = Tm.m[k];
               return DivArgs<double>{c->mp, c->h, nullptr, nullptr, 1.0, c->lam, -dta[k], 0.0, 0.0, 1, c->b,
-                                     nullptr, nullptr, nullptr};
+                                     nullptr, nullptr};
             },
             [&](int) { return 0.0; }));
         STEP_CHK(pw<PwRhsAdd<D>>(Tm, fa, [&](int k) {
