@@ -64,3 +64,46 @@ def test_full_size_box3d_hill_operators():
     print("[full] Helmholtz FP32 rel err %.2e" % e, flush=True)
     assert e < 2e-5
     s32.close()
+
+
+@pytest.mark.gpu
+def test_full_size_ridge_large_step_properties():
+    """The headline workload at full size (2,183,168 cells, degree 4, 272.9 M nodes per field,
+    1.36e9 DoFs) in the configuration the benchmark times (FP64, GMRES rtol 1e-8), through
+    properties that hold at any size: the hydrostatic rest state over the ridge stays at rest (the
+    scheme in perturbation form is well balanced), a step with the wind and seeded temperature
+    noise conserves mass to rounding (the continuity equation is explicit and in flux form), and
+    the step is deterministic (the same bits twice).  The oracle covers this workload through its
+    one-column sample (test_gpu_oracle_configs)."""
+    import math
+
+    import torch
+
+    import paper_2408_08129_amd as P
+    w = dict(cases.WORKLOADS["box3d_r4_ridge_large"])
+    t0 = time.time()
+    s = P.Solver(cases.product_case(w), w["degree"], P.options(gmres_rtol=1e-8))
+    assert s.ncell == 2183168 and s.N == 272896000
+    print("[full C5] setup %.1f s" % (time.time() - t0), flush=True)
+
+    U = s.init_state(0.0)
+    st = s.step(U, w["dt"])
+    _, max_w = s.diagnostics(U)
+    print("[full C5] rest: max |w| after one step %.3e m/s, GMRES its %s" % (max_w, st.as_dict(2)["gmres_iters"]),
+          flush=True)
+    assert max_w < 1e-10
+    del U
+    torch.cuda.empty_cache()
+
+    U1 = s.init_state(w["ubar"], noise_seed=11, noise_sigma_K=0.05)
+    U2 = U1.clone()
+    m0, _ = s.diagnostics(U1)
+    st = s.step(U1, w["dt"])
+    s.step(U2, w["dt"])
+    m1, w1 = s.diagnostics(U1)
+    print("[full C5] wind + noise: mass drift %.3e, max |w| %.3f m/s, GMRES its %s" %
+          ((m1 - m0) / m0, w1, st.as_dict(2)["gmres_iters"]), flush=True)
+    assert abs(m1 - m0) < 1e-13 * m0
+    assert math.isfinite(w1) and w1 < 50.0
+    assert torch.equal(U1, U2)
+    s.close()
