@@ -150,6 +150,20 @@ def test_step_slice2d_r4_twolevel_2_steps():
     _run_pair(w, 2, w["ubar"], w["dt"])
 
 
+@pytest.mark.parametrize("mk,r,steps,dt", [(C.twolevel2d, 1, 3, 0.5), (C.twolevel2d, 5, 2, 0.3),
+                                            (C.twolevel3d, 1, 2, 1.0), (C.twolevel3d, 3, 2, 0.5),
+                                            (C.tiny3d, 5, 2, 0.5)])
+def test_step_every_degree_with_2to1_faces(mk, r, steps, dt):
+    """Whole steps at the degrees the other step tests leave out (1, 3 and the largest, 5), on
+    meshes with 2:1 faces, FP64."""
+    _run_pair(mk(r), steps, 10.0, dt)
+
+
+def test_step_mixed_precision_degree3():
+    import paper_2408_08129_amd as P
+    _run_pair(C.twolevel3d(3), 2, 10.0, 0.5, precision=P.DG_FP32_INNER, tol=TOL_MIXED)
+
+
 def test_step_mixed_precision():
     import paper_2408_08129_amd as P
     _run_pair(C.twolevel3d(2), 3, 10.0, 1.0, precision=P.DG_FP32_INNER, tol=TOL_MIXED)
