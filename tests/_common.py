@@ -73,3 +73,10 @@ def walls2d(r):
     w = twolevel2d(r)
     w["periodic"] = (0, 0)
     return w
+
+
+def walls3d(r):
+    """Lateral walls on all four sides (not periodic), two levels over the bell."""
+    w = twolevel3d(r)
+    w["periodic"] = (0, 0)
+    return w

@@ -152,10 +152,11 @@ def test_step_slice2d_r4_twolevel_2_steps():
 
 @pytest.mark.parametrize("mk,r,steps,dt", [(C.twolevel2d, 1, 3, 0.5), (C.twolevel2d, 5, 2, 0.3),
                                             (C.twolevel3d, 1, 2, 1.0), (C.twolevel3d, 3, 2, 0.5),
-                                            (C.tiny3d, 5, 2, 0.5)])
+                                            (C.tiny3d, 5, 2, 0.5), (C.walls2d, 3, 3, 0.5),
+                                            (C.walls3d, 2, 2, 0.5)])
 def test_step_every_degree_with_2to1_faces(mk, r, steps, dt):
-    """Whole steps at the degrees the other step tests leave out (1, 3 and the largest, 5), on
-    meshes with 2:1 faces, FP64."""
+    """Whole steps at the degrees the other step tests leave out (1, 3 and the largest, 5), and
+    with lateral walls in 2D and 3D, on meshes with 2:1 faces, FP64."""
     _run_pair(mk(r), steps, 10.0, dt)
 
 
