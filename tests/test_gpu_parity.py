@@ -23,8 +23,8 @@ def _torch():
 
 def pair(w, **opt):
     import paper_2408_08129_amd as P
-    print("[case] %s" % ({k: w[k] for k in ("dim", "degree", "nbase")},), flush=True)
-    o = O.Oracle(C.oracle_case(w))
+    print("[case] %s %s" % ({k: w[k] for k in ("dim", "degree", "nbase")}, opt), flush=True)
+    o = O.Oracle(C.oracle_case(w), beta=opt.get("penalty_beta", 1.0))
     s = P.Solver(C.product_case(w), w["degree"], P.options(**opt) if opt else None)
     perm = C.cell_perm(s.cell_table(), o.cells)
     return o, s, perm
@@ -109,9 +109,9 @@ def test_helmholtz_fp32(mk, r):
     assert C.rel_err(Ap, ref) < 2e-5
 
 
-def _run_pair(w, steps, ubar, dt, precision=0, tol=TOL_STEP):
+def _run_pair(w, steps, ubar, dt, precision=0, tol=TOL_STEP, **opt):
     import paper_2408_08129_amd as P
-    o, s, perm = pair(w, precision=precision)
+    o, s, perm = pair(w, precision=precision, **opt)
     Uo = o.initial_state(ubar)
     U = dev(C.to_product_order(Uo, perm, o.nloc))
     for n in range(steps):
@@ -158,6 +158,22 @@ def test_step_every_degree_with_2to1_faces(mk, r, steps, dt):
     """Whole steps at the degrees the other step tests leave out (1, 3 and the largest, 5), and
     with lateral walls in 2D and 3D, on meshes with 2:1 faces, FP64."""
     _run_pair(mk(r), steps, 10.0, dt)
+
+
+def test_step_diagonal_preconditioner():
+    """The GPU's Jacobi-preconditioned Krylov path (general cell kernels) against the oracle."""
+    _run_pair(C.twolevel3d(2), 2, 10.0, 1.0, preconditioner=0)
+
+
+def test_step_plain_flux_without_penalty():
+    """The plain implicit energy flux with penalty_beta = 0 on both sides."""
+    _run_pair(C.twolevel2d(3), 3, 10.0, 0.5, penalty_beta=0.0)
+
+
+@pytest.mark.parametrize("mk,r,dt", [(C.twolevel2d, 1, 0.5), (C.tiny3d, 5, 0.5)])
+def test_step_mixed_precision_lowest_and_highest_degree(mk, r, dt):
+    import paper_2408_08129_amd as P
+    _run_pair(mk(r), 2, 10.0, dt, precision=P.DG_FP32_INNER, tol=TOL_MIXED)
 
 
 def test_step_mixed_precision_degree3():
