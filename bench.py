@@ -109,7 +109,7 @@ def measured_traffic(kernel, workload):
 
 
 def roofline(res, workload):
-    """The Helmholtz apply over the timed region: SURVEY-style algorithmic bytes (3 words per node:
+    """The Helmholtz apply over the timed region: its algorithmic minimum bytes (3 words per node:
     p and h in, A p out) per apply over its HIP-event-measured device time (both passes)."""
     st = res["stats"]
     tk = {k: sum(s["t_kernel_ms"][k] for s in st) for k in st[0]["t_kernel_ms"]}
@@ -287,7 +287,7 @@ def main():
         print(json.dumps(cpu_leg(args.workload, args.cpu_leg)), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

@@ -84,12 +84,12 @@ def test_full_size_ridge_large_step_properties():
     t0 = time.time()
     s = P.Solver(cases.product_case(w), w["degree"], P.options(gmres_rtol=1e-8))
     assert s.ncell == 2183168 and s.N == 272896000
-    print("[full C5] setup %.1f s" % (time.time() - t0), flush=True)
+    print("[full ridge] setup %.1f s" % (time.time() - t0), flush=True)
 
     U = s.init_state(0.0)
     st = s.step(U, w["dt"])
     _, max_w = s.diagnostics(U)
-    print("[full C5] rest: max |w| after one step %.3e m/s, GMRES its %s" % (max_w, st.as_dict(2)["gmres_iters"]),
+    print("[full ridge] rest: max |w| after one step %.3e m/s, GMRES its %s" % (max_w, st.as_dict(2)["gmres_iters"]),
           flush=True)
     assert max_w < 1e-10
     del U
@@ -101,7 +101,7 @@ def test_full_size_ridge_large_step_properties():
     st = s.step(U1, w["dt"])
     s.step(U2, w["dt"])
     m1, w1 = s.diagnostics(U1)
-    print("[full C5] wind + noise: mass drift %.3e, max |w| %.3f m/s, GMRES its %s" %
+    print("[full ridge] wind + noise: mass drift %.3e, max |w| %.3f m/s, GMRES its %s" %
           ((m1 - m0) / m0, w1, st.as_dict(2)["gmres_iters"]), flush=True)
     assert abs(m1 - m0) < 1e-13 * m0
     assert math.isfinite(w1) and w1 < 50.0
