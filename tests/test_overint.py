@@ -249,11 +249,16 @@ def test_gpu_overintegrated_residual(mk, r, e):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("mk,r,e,steps,dt", [(C.twolevel3d, 2, 1, 3, 1.0), (C.twolevel2d, 4, 2, 4, 0.5)])
-def test_gpu_overintegrated_steps(mk, r, e, steps, dt):
+@pytest.mark.parametrize("mk,r,e,steps,dt,prec", [(C.twolevel3d, 2, 1, 3, 1.0, 0), (C.twolevel2d, 4, 2, 4, 0.5, 0),
+                                                 (C.twolevel2d, 3, 1, 2, 0.5, 1)])
+def test_gpu_overintegrated_steps(mk, r, e, steps, dt, prec):
+    """Steps with the over-integrated explicit flux against the oracle; the last case with the
+    FP32-inner / FP64-outer solve (tolerance of the mixed form)."""
     import math
-    from tests.test_gpu_parity import TOL_STEP, dev, host
-    o, s, perm = _gpu_pair(mk(r), e)
+    from tests.test_gpu_parity import TOL_MIXED, TOL_STEP, dev, host
+    if prec:
+        TOL_STEP = TOL_MIXED
+    o, s, perm = _gpu_pair(mk(r), e, precision=prec)
     Uo = o.initial_state(10.0)
     U = dev(C.to_product_order(Uo, perm, o.nloc))
     for n in range(steps):

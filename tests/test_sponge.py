@@ -133,6 +133,13 @@ def test_gpu_steps_with_layers(i):
     _run_pair(_layer_cases()[i], 3, 6.0, 0.5)
 
 
+@pytest.mark.gpu
+def test_gpu_steps_with_layers_fp32_inner():
+    import paper_2408_08129_amd as P
+    from tests.test_gpu_parity import TOL_MIXED, _run_pair
+    _run_pair(_layer_cases()[0], 3, 6.0, 0.5, precision=P.DG_FP32_INNER, tol=TOL_MIXED)
+
+
 def test_invalid_layer_parameters_rejected():
     import paper_2408_08129_amd as P
     from tests import _common as C
