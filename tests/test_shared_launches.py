@@ -81,6 +81,7 @@ def test_shared_3d_members_fp64_and_mixed_precision():
 def test_shared_enthalpy_split_members():
     ws = [C.tiny3d(3), C.twolevel3d(3)]
     check_alone_equals_mix(ws, [0.5, 0.5], enthalpy_split=1, penalty_beta=0.0)
+    check_alone_equals_mix(ws, [0.5, 0.5], enthalpy_split=1, penalty_beta=0.0, precision=1)
 
 
 @pytest.mark.gpu
